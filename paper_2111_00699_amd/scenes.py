@@ -1,0 +1,190 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module only creates inputs (positions, initial velocities and material
+states, material constants and run settings); it contains none of the
+simulation method's arithmetic, so both the HIP path and the FP64 oracle can be
+fed from it.  Random numbers come from a counter-based splitmix64 stream
+(Steele, Lea and Flood 2014) so the arrays do not depend on numpy's generator
+versions.
+
+Workloads (Results section of the paper; sizes as printed there where given):
+  * jelly cube  -- 64^3 grid, a 0.25^3 cube of fixed-corotated jelly, 8 ppc;
+  * snow        -- 12 seeded spheres, about 1.33M particles (the size of the
+                   paper's "Crawling in Snow" scene), 256^3 grid;
+  * fountain    -- water emitted from a 0.05-radius inlet at 3 m/s, growing
+                   to about 143.5K particles (the paper's fountain size);
+  * sand blocks -- 4 or 16 boxes of l^3 cells at 8 ppc (l = 12, 23, 46).
+Particle samples are stratified: one uniform sample in each of the 2x2x2
+half-cell sub-cubes of every covered cell (the paper seeds its blocks "in a
+stratified random way" at 8 particles per cell).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+
+
+def splitmix64(seed: int, count: int, stream: int = 0) -> np.ndarray:
+    """`count` consecutive splitmix64 outputs for (seed, stream) as uint64."""
+    with np.errstate(over="ignore"):
+        base = np.uint64((int(seed) * 0x100000001B3 + int(stream) * 0xD1B54A32D192ED03) & (2**64 - 1))
+        z = base + (np.arange(1, count + 1, dtype=np.uint64) * GOLDEN)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform(seed: int, count: int, stream: int = 0, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:
+    """Uniform float64 in [lo, hi) from the top 53 bits of splitmix64."""
+    u = (splitmix64(seed, count, stream) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+    return lo + (hi - lo) * u
+
+
+# ------------------------------------------------------------------ materials
+JELLY = dict(kind="jelly", E=1e4, nu=0.2, rho=1.0, ppc=8.0)
+SNOW = dict(kind="snow", E=1.4e5, nu=0.2, rho=400.0, ppc=8.0, theta_c=2.5e-2, theta_s=7.5e-3, xi=10.0)
+WATER = dict(kind="water", rho=1000.0, ppc=8.0, bulk=1e4)
+
+FRAME = 1.0 / 60.0
+
+
+def frame_substeps(dt_nominal: float, frame: float = FRAME) -> tuple[int, float]:
+    """Substeps per frame and the effective dt: ceil(frame/dt) steps of frame/steps."""
+    ns = int(math.ceil(frame / dt_nominal - 1e-9))
+    return ns, frame / ns
+
+
+# ---------------------------------------------------------------- samplers
+def stratified_cells(cells: np.ndarray, n: int, seed: int, stream: int = 0) -> np.ndarray:
+    """One uniform sample per half-cell sub-cube of each cell in `cells` (K,3 ints).
+    Returns FP32 positions (3, 8K), cell-major in the order given."""
+    K = cells.shape[0]
+    dx = 1.0 / n
+    sub = np.array([[i, j, k] for i in range(2) for j in range(2) for k in range(2)], dtype=np.float64)
+    u = uniform(seed, 3 * 8 * K, stream).reshape(K, 8, 3)
+    pos = (cells[:, None, :].astype(np.float64) + 0.5 * (sub[None, :, :] + u)) * dx
+    return np.ascontiguousarray(pos.reshape(-1, 3).T.astype(np.float32))
+
+
+def box_cells(lo_cell, hi_cell) -> np.ndarray:
+    """All integer cells in [lo, hi) per axis, as (K,3), x fastest."""
+    rng = [np.arange(lo_cell[a], hi_cell[a]) for a in range(3)]
+    gz, gy, gx = np.meshgrid(rng[2], rng[1], rng[0], indexing="ij")
+    return np.stack([gx.ravel(), gy.ravel(), gz.ravel()], axis=1)
+
+
+def jelly_cube(seed: int = 0, n: int = 64, lo: float = 0.375, hi: float = 0.625) -> dict:
+    """The 64^3 jelly parity scene: cube [lo,hi]^3 at 8 ppc, at rest."""
+    lc = int(round(lo * n))
+    hc = int(round(hi * n))
+    x = stratified_cells(box_cells((lc,) * 3, (hc,) * 3), n, seed)
+    return {"x": x}
+
+
+def nontrivial_state(x: np.ndarray, seed: int = 5, kind: str = "jelly") -> dict:
+    """A random, non-trivial particle state around positions x (3,N):
+    v ~ U(-0.5,0.5) m/s, C ~ U(-5,5) 1/s, F = I + U(-0.05,0.05) per entry
+    (det F > 0.8 for such perturbations), and J_P ~ U(0.9,1.05) (snow) or
+    J ~ U(0.95,1.05) (water)."""
+    N = x.shape[1]
+    v = uniform(seed, 3 * N, 1, -0.5, 0.5).reshape(3, N)
+    C = uniform(seed, 9 * N, 2, -5.0, 5.0).reshape(9, N)
+    F = uniform(seed, 9 * N, 3, -0.05, 0.05).reshape(9, N)
+    F[[0, 4, 8]] += 1.0
+    assert np.all(np.linalg.det(F.T.reshape(N, 3, 3)) > 0.5)
+    st = {"x": x, "v": v.astype(np.float32), "C": C.astype(np.float32), "F": F.astype(np.float32)}
+    if kind == "snow":
+        st["s"] = uniform(seed, N, 4, 0.9, 1.05).astype(np.float32)
+    elif kind == "water":
+        st["s"] = uniform(seed, N, 4, 0.95, 1.05).astype(np.float32)
+    return st
+
+
+def snow_spheres(seed: int = 1, n: int = 256, target: float = 1.33e6, count: int = 12,
+                 rmin: float = 0.04, rmax: float = 0.1) -> dict:
+    """12 non-overlapping spheres; the radius vector is redrawn until the
+    volume estimate 8 * sum(4/3 pi r^3) / dx^3 is within 5% of `target`."""
+    dx = 1.0 / n
+    trial = 0
+    while True:
+        r = uniform(seed, count, 100 + trial, rmin, rmax)
+        est = 8.0 * np.sum(4.0 / 3.0 * np.pi * r ** 3) / dx ** 3
+        trial += 1
+        if abs(est - target) <= 0.05 * target:
+            break
+    r = np.sort(r)[::-1]
+    lo = np.array([0.15, 0.30, 0.15])
+    hi = np.array([0.85, 0.85, 0.85])
+    centers = []
+    draw = 0
+    for i in range(count):
+        while True:
+            c = lo + (hi - lo) * uniform(seed, 3, 10000 + draw)
+            draw += 1
+            ok = all(np.linalg.norm(c - cj) >= r[i] + rj + 2 * dx for cj, rj in zip(centers, r[:i]))
+            if ok:
+                break
+        centers.append(c)
+    centers = np.array(centers)
+    pieces = []
+    for i in range(count):
+        lc = np.floor((centers[i] - r[i]) / dx).astype(int)
+        hc = np.ceil((centers[i] + r[i]) / dx).astype(int)
+        x = stratified_cells(box_cells(lc, hc), n, seed, stream=200 + i)
+        d = x.astype(np.float64) - centers[i][:, None]
+        keep = np.sum(d * d, axis=0) <= r[i] ** 2
+        pieces.append(x[:, keep])
+    x = np.ascontiguousarray(np.concatenate(pieces, axis=1))
+    return {"x": x, "centers": centers, "radii": r}
+
+
+def fountain_emission(frame: int, seed: int = 2, n: int = 128, radius: float = 0.05,
+                      center=(0.5, 0.1, 0.5), height: float = 0.05, speed: float = 3.0) -> dict:
+    """One frame's emission: stratified 8-ppc samples in the inlet cylinder
+    (axis +y, radius 0.05, y in [0.1, 0.15]) moving up at 3 m/s."""
+    dx = 1.0 / n
+    cx, cy, cz = center
+    lc = np.floor(np.array([cx - radius, cy, cz - radius]) / dx).astype(int)
+    hc = np.ceil(np.array([cx + radius, cy + height, cz + radius]) / dx).astype(int)
+    x = stratified_cells(box_cells(lc, hc), n, seed, stream=1000 + frame)
+    xd = x.astype(np.float64)
+    keep = ((xd[0] - cx) ** 2 + (xd[2] - cz) ** 2 <= radius ** 2) & (xd[1] >= cy) & (xd[1] < cy + height)
+    x = np.ascontiguousarray(x[:, keep])
+    v = np.zeros_like(x)
+    v[1] = speed
+    return {"x": x, "v": v}
+
+
+def sand_blocks(l: int = 12, boxes: int = 4, n: int = 128, seed: int = 6) -> dict:
+    """The paper's Sand Blocks layout: `boxes` cubes of l^3 cells at 8 ppc
+    (4 x 12^3 x 8 = 55,296 particles), side by side with a two-cell gap."""
+    side = int(round(boxes ** (1 / 2)))
+    gap = 2
+    total = side * l + (side - 1) * gap
+    start = (n - total) // 2
+    cells = []
+    for bz in range(side):
+        for bx in range(side):
+            lo = (start + bx * (l + gap), n // 8, start + bz * (l + gap))
+            cells.append(box_cells(lo, (lo[0] + l, lo[1] + l, lo[2] + l)))
+    x = stratified_cells(np.concatenate(cells), n, seed)
+    return {"x": x}
+
+
+# ------------------------------------------------------------- run settings
+def snow_config(n: int = 256) -> dict:
+    ns, dt = frame_substeps(5e-5)
+    return dict(n=n, bc="separate", bc_cells=3, gravity=(0.0, -9.8, 0.0), dt=dt, substeps_per_frame=ns)
+
+
+def jelly_config(n: int = 64) -> dict:
+    return dict(n=n, bc="sticky", bc_cells=3, gravity=(0.0, -9.8, 0.0), dt=1e-4, substeps_per_frame=167)
+
+
+def fountain_config(n: int = 128) -> dict:
+    ns, dt = frame_substeps(1e-4)
+    return dict(n=n, bc="separate", bc_cells=3, gravity=(0.0, -9.8, 0.0), dt=dt, substeps_per_frame=ns)

@@ -1,0 +1,479 @@
+"""Pins of the FP64 oracle against what the mathematics and the paper fix.
+
+None of these re-types the oracle's own formulas: each checks a property that
+a dropped term, a wrong sign, a wrong index or a transposed operand would
+break (moments of the B-spline, brute force over all nodes, conservation,
+affine reproduction, the symplectic-Euler free-fall closed form, LAPACK's SVD,
+closed forms of the constitutive laws, Python's stable sort, set algebra for
+the blocks, and the free-zone sizes printed in the paper).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2111_00699_amd import scenes
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def rot(seed):
+    q = scenes.uniform(seed, 4, 7, -1, 1)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+                     [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+                     [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+
+
+def bspline(u):
+    """Textbook quadratic B-spline N(u) (compact support [-3/2, 3/2])."""
+    a = np.abs(u)
+    return np.where(a < 0.5, 0.75 - a * a, np.where(a < 1.5, 0.5 * (1.5 - a) ** 2, 0.0))
+
+
+# ------------------------------------------------------------------ weights
+def test_weight_moments(oracle):
+    ts = scenes.uniform(11, 2000, 0, 3.0, 60.0)
+    for t in ts:
+        base, w = oracle.weights(t)
+        nodes = base + np.arange(3)
+        assert np.all(w >= 0)
+        assert abs(w.sum() - 1.0) < 1e-14                       # partition of unity
+        assert abs(np.dot(w, nodes - t)) < 1e-12                  # linear reproduction
+        assert abs(np.dot(w, (nodes - t) ** 2) - 0.25) < 1e-12   # D_p = dx^2/4
+        assert np.allclose(w, bspline(t - nodes), atol=1e-15)     # the B-spline itself
+        # every node outside the stencil has zero weight
+        others = np.concatenate([np.arange(base - 3, base), np.arange(base + 3, base + 6)])
+        assert np.all(bspline(t - others) == 0)
+
+
+def test_p2g_mass_brute_force_all_nodes(oracle):
+    """Tiny grid: evaluate N(x/dx - i) for ALL nodes and particles."""
+    n = 16
+    x = scenes.uniform(3, 3 * 8, 0, 0.2, 0.8).reshape(3, 8)
+    st = {"x": x}
+    mat = dict(scenes.JELLY)
+    cfg = dict(n=n, bc="sticky", dt=1e-4)
+    _, gm, _, bad = oracle.p2g(cfg, mat, st)
+    assert bad == 0
+    mp = mat["rho"] / n ** 3 / mat["ppc"]
+    i = np.arange(n + 1)
+    wx = bspline(x[0][:, None] * n - i[None, :])
+    wy = bspline(x[1][:, None] * n - i[None, :])
+    wz = bspline(x[2][:, None] * n - i[None, :])
+    brute = mp * np.einsum("pi,pj,pk->ijk", wx, wy, wz).ravel()
+    assert np.allclose(gm, brute, rtol=0, atol=1e-16 * mp + 1e-13 * brute.max())
+
+
+# ------------------------------------------------------------ conservation
+def _state(seed, n=32, N=500, kind="jelly"):
+    x = scenes.uniform(seed, 3 * N, 0, 0.3, 0.7).reshape(3, N).astype(np.float32)
+    return scenes.nontrivial_state(x, seed=seed, kind=kind)
+
+
+@pytest.mark.parametrize("kind,mat", [("jelly", scenes.JELLY), ("snow", scenes.SNOW), ("water", scenes.WATER)])
+def test_p2g_conserves_mass_and_momentum(oracle, kind, mat):
+    st = _state(21, kind=kind)
+    n = 32
+    cfg = dict(n=n, bc="sticky", dt=1e-4)
+    _, gm, gp, bad = oracle.p2g(cfg, mat, st)
+    assert bad == 0
+    mp = mat["rho"] / n ** 3 / mat["ppc"]
+    N = st["x"].shape[1]
+    assert abs(gm.sum() - N * mp) <= 1e-13 * N * mp
+    mom = mp * st["v"].astype(np.float64).sum(axis=1)
+    # the affine and stress terms vanish since sum_i w_ip (x_i - x_p) = 0
+    assert np.allclose(gp.sum(axis=1), mom, rtol=0, atol=1e-12 * N * mp)
+    # the stress term is not zero per node (guards against dropping it)
+    _, _, gp0, _ = oracle.p2g(cfg, dict(mat, E=0.0, bulk=0.0), st)
+    assert np.abs(gp - gp0).max() > 1e-6 * np.abs(gp).max()
+
+
+def test_g2p_conserves_momentum(oracle):
+    st = _state(22)
+    n = 32
+    cfg = dict(n=n, bc="sticky", dt=1e-4, gravity=(0, 0, 0))
+    _, gm, _, _ = oracle.p2g(cfg, scenes.JELLY, st)
+    gv = scenes.uniform(4, 3 * (n + 1) ** 3, 0, -1, 1).reshape(3, -1)
+    s2, bad = oracle.g2p(cfg, scenes.JELLY, st, gv)
+    assert bad == 0
+    mp = scenes.JELLY["rho"] / n ** 3 / 8
+    lhs = mp * s2["v"].sum(axis=1)
+    rhs = (gm[None, :] * gv).sum(axis=1)
+    assert np.allclose(lhs, rhs, rtol=1e-12, atol=1e-15)
+
+
+def test_affine_field_reproduced(oracle):
+    n = 32
+    N = 400
+    x = scenes.uniform(8, 3 * N, 0, 0.3, 0.7).reshape(3, N).astype(np.float32)
+    a = np.array([0.3, -0.2, 0.1])
+    B = scenes.uniform(8, 9, 1, -2, 2).reshape(3, 3)
+    v = a[:, None] + B @ x.astype(np.float64)
+    C = np.repeat(B.reshape(9, 1), N, axis=1)
+    st = {"x": x, "v": v, "C": C}
+    cfg = dict(n=n, bc="sticky", dt=1e-4, gravity=(0, 0, 0))
+    mat = dict(scenes.JELLY, E=0.0)  # tau = 0
+    s2, _, _, bad = oracle.substep(cfg, mat, st)
+    assert bad == 0
+    assert np.allclose(s2["v"], v, rtol=0, atol=1e-12)
+    assert np.allclose(s2["C"], C, rtol=0, atol=1e-10)
+    assert np.allclose(s2["x"], x.astype(np.float64) + 1e-4 * v, rtol=0, atol=1e-14)
+
+
+def _psi(mat, F, s):
+    """Elastic energy density whose Kirchhoff stress the P2G force must be."""
+    if mat["kind"] == "water":
+        return 0.5 * mat["bulk"] * (s - 1) ** 2
+    sig = np.linalg.svd(F, compute_uv=False)
+    J = np.linalg.det(F)
+    if J < 0:
+        sig[-1] = -sig[-1]
+    mu, la = lame(mat["E"], mat["nu"])
+    if mat["kind"] == "snow":
+        h = np.exp(mat["xi"] * (1 - s))
+        mu, la = mu * h, la * h
+    return mu * np.sum((sig - 1) ** 2) + 0.5 * la * (J - 1) ** 2
+
+
+@pytest.mark.parametrize("mat", [scenes.JELLY, scenes.SNOW, scenes.WATER])
+def test_p2g_force_is_energy_gradient(oracle, mat):
+    """MLS-MPM: the stress part of the nodal momentum is dt * f_i with
+    f_i = -dE/dx_i, E = sum_p V0 psi(F_p(x)), where moving node i by delta
+    deforms particle p by (I + 4/dx^2 w_ip delta (x_i - x_p)^T)."""
+    n = 16
+    N = 12
+    x = scenes.uniform(90, 3 * N, 0, 0.45, 0.55).reshape(3, N).astype(np.float32)
+    st = scenes.nontrivial_state(x, seed=91, kind=mat["kind"])
+    st["F"] = (np.eye(3).reshape(9, 1) + 1.5 * (st["F"].astype(np.float64) - np.eye(3).reshape(9, 1)))
+    dt = 1e-3
+    cfg = dict(n=n, bc="sticky", dt=dt)
+    _, gm, gp, _ = oracle.p2g(cfg, mat, st)
+    _, _, gp0, _ = oracle.p2g(cfg, dict(mat, E=0.0, bulk=0.0), st)
+    force = (gp - gp0) / dt
+    dx = 1.0 / n
+    V0 = dx ** 3 / mat["ppc"]
+    xp = st["x"].astype(np.float64)
+    Fp = st["F"].astype(np.float64).T.reshape(N, 3, 3)
+    sp = st["s"].astype(np.float64) if "s" in st else np.ones(N)
+    i = np.arange(n + 1)
+    W = [bspline(xp[a][:, None] * n - i[None, :]) for a in range(3)]
+
+    def energy(node, delta):
+        e = 0.0
+        xi = np.array(node) * dx
+        for p in range(N):
+            w = W[0][p, node[0]] * W[1][p, node[1]] * W[2][p, node[2]]
+            G = np.eye(3) + 4.0 / dx ** 2 * w * np.outer(delta, xi - xp[:, p])
+            if mat["kind"] == "water":
+                e += V0 * _psi(mat, None, sp[p] * np.linalg.det(G))
+            else:
+                e += V0 * _psi(mat, G @ Fp[p], sp[p])
+        return e
+
+    nodes = np.argsort(gm)[::-1][:6]
+    checked = 0
+    for nid in nodes:
+        node = np.unravel_index(nid, (n + 1,) * 3)
+        for a in range(3):
+            h = 1e-6 * dx
+            d = np.zeros(3); d[a] = h
+            fd = -(energy(node, d) - energy(node, -d)) / (2 * h)
+            assert abs(force[a, nid] - fd) <= 1e-5 * np.abs(force).max() + 1e-12, (node, a, force[a, nid], fd)
+            checked += abs(fd) > 1e-3 * np.abs(force).max()
+    assert checked > 6
+
+
+def test_deformation_gradient_follows_the_flow(oracle):
+    """In an affine flow v = a + B x every particle separation is mapped by
+    the same matrix M = (I + dt B); the updated gradient must satisfy
+    F'_p F_p^{-1} = M, with M read off the advected particle positions."""
+    n = 32
+    N = 300
+    x = scenes.uniform(92, 3 * N, 0, 0.35, 0.65).reshape(3, N).astype(np.float32)
+    a = np.array([0.1, 0.2, -0.1])
+    B = scenes.uniform(92, 9, 1, -3, 3).reshape(3, 3)
+    v = a[:, None] + B @ x.astype(np.float64)
+    C = np.repeat(B.reshape(9, 1), N, axis=1)
+    F0 = np.eye(3) + scenes.uniform(92, 9, 2, -0.3, 0.3).reshape(3, 3)
+    F = np.repeat(F0.reshape(9, 1), N, axis=1)
+    dt = 1e-3
+    cfg = dict(n=n, bc="sticky", dt=dt, gravity=(0, 0, 0))
+    s2, _, _, bad = oracle.substep(cfg, dict(scenes.JELLY, E=0.0), {"x": x, "v": v, "C": C, "F": F})
+    assert bad == 0
+    X0 = x.astype(np.float64)
+    dX = X0[:, 1:] - X0[:, :1]
+    dY = s2["x"][:, 1:] - s2["x"][:, :1]
+    M = dY @ np.linalg.pinv(dX)
+    for p in range(0, N, 37):
+        Fn = s2["F"][:, p].reshape(3, 3)
+        assert np.allclose(Fn @ np.linalg.inv(F0), M, atol=1e-9)
+
+
+def test_free_fall_closed_form(oracle):
+    """Jelly cube at rest away from the walls: symplectic Euler free fall."""
+    sc = scenes.jelly_cube(0)
+    cfg = scenes.jelly_config()
+    x0 = sc["x"].astype(np.float64)
+    N = x0.shape[1]
+    assert N == 32768
+    steps = 20
+    st, _, _, bad = oracle.substep(cfg, scenes.JELLY, sc, steps=steps)
+    assert bad == 0
+    dt, g = cfg["dt"], -9.8
+    assert np.allclose(st["v"][1], steps * dt * g, rtol=1e-11, atol=0)
+    assert np.abs(st["v"][[0, 2]]).max() < 1e-12
+    assert np.allclose(st["x"][1], x0[1] + dt * dt * g * steps * (steps + 1) / 2, rtol=0, atol=1e-14)
+    assert np.abs(st["C"]).max() < 1e-8
+    eye = np.zeros((9, 1)); eye[[0, 4, 8]] = 1
+    assert np.abs(st["F"] - eye).max() < 1e-12
+
+
+# ---------------------------------------------------------------------- SVD
+def _svd_cases():
+    mats = [scenes.uniform(30, 9, i, -1, 1).reshape(3, 3) for i in range(3000)]
+    for i in range(300):  # near-degenerate / repeated singular values
+        R1, R2 = rot(100 + i), rot(400 + i)
+        s = np.array([1.0, 1.0 + 1e-9 * (i % 7), 1.0 - 1e-12 * (i % 3)]) * (0.5 + i / 300)
+        mats.append(R1 @ np.diag(s) @ R2.T)
+    for i in range(300):  # inverted
+        M = np.eye(3) + scenes.uniform(31, 9, i, -0.3, 0.3).reshape(3, 3)
+        M[:, 0] *= -1
+        mats.append(M)
+    mats.append(np.zeros((3, 3)))
+    mats.append(np.diag([2.0, 0.0, 0.0]))
+    mats.append(np.eye(3))
+    return mats
+
+
+def test_svd_matches_lapack(oracle):
+    for F in _svd_cases():
+        U, S, V = oracle.svd3(F)
+        ref = np.linalg.svd(F, compute_uv=False)
+        assert np.allclose(np.abs(S), ref, rtol=0, atol=1e-12 * max(1.0, ref[0]))
+        assert np.all(np.diff(np.abs(S)) <= 1e-12)
+        assert np.allclose(U @ np.diag(S) @ V.T, F, atol=1e-12 * max(1.0, ref[0]))
+        assert np.allclose(U.T @ U, np.eye(3), atol=1e-12)
+        assert np.allclose(V.T @ V, np.eye(3), atol=1e-12)
+        assert np.linalg.det(U) > 0 and np.linalg.det(V) > 0
+        assert np.sign(np.prod(S)) == np.sign(np.linalg.det(F)) or abs(np.linalg.det(F)) < 1e-12
+
+
+# -------------------------------------------------------- constitutive laws
+def lame(E, nu):
+    return E / (2 * (1 + nu)), E * nu / ((1 + nu) * (1 - 2 * nu))
+
+
+def test_fixed_corotated_closed_forms(oracle):
+    mu, la = lame(1e4, 0.2)
+    assert np.abs(oracle.fixed_corotated(np.eye(3), mu, la)).max() < 1e-10
+    for s in (0.7, 0.95, 1.0, 1.1, 1.6):
+        tau = oracle.fixed_corotated(s * np.eye(3), mu, la)
+        want = (2 * mu * (s - 1) * s + la * (s ** 3 - 1) * s ** 3) * np.eye(3)
+        assert np.allclose(tau, want, rtol=1e-12, atol=1e-9)
+    for i in range(200):
+        F = np.eye(3) + scenes.uniform(40, 9, i, -0.3, 0.3).reshape(3, 3)
+        Q = rot(700 + i)
+        tau = oracle.fixed_corotated(F, mu, la)
+        assert np.allclose(tau, tau.T, atol=1e-9 * np.abs(tau).max())
+        assert np.allclose(oracle.fixed_corotated(Q @ F, mu, la), Q @ tau @ Q.T, atol=1e-9 * np.abs(tau).max())
+        # independent route: left stretch from LAPACK's eigendecomposition of b = F F^T
+        lam, W = np.linalg.eigh(F @ F.T)
+        Vs = W @ np.diag(np.sqrt(lam)) @ W.T
+        J = np.linalg.det(F)
+        ref = 2 * mu * (F @ F.T - Vs) + la * (J - 1) * J * np.eye(3)
+        assert np.allclose(tau, ref, atol=1e-9 * np.abs(ref).max())
+
+
+def test_snow_return_map(oracle):
+    m = scenes.SNOW
+    lo, hi = 1 - m["theta_c"], 1 + m["theta_s"]
+    # inside the yield bounds: identity
+    for i in range(50):
+        s = scenes.uniform(50, 3, i, lo + 1e-4, hi - 1e-4)
+        F = rot(800 + i) @ np.diag(s) @ rot(900 + i).T
+        Fe, Jp = oracle.snow_project(m, F, 0.97)
+        assert np.allclose(Fe, F, atol=1e-13) and abs(Jp - 0.97) < 1e-13
+    # diagonal case with both bounds active
+    Fe, Jp = oracle.snow_project(m, np.diag([1.02, 1.0, 0.96]), 1.0)
+    assert np.allclose(Fe, np.diag([hi, 1.0, lo]), atol=1e-14)
+    assert abs(Jp - (1.02 * 0.96) / (hi * lo)) < 1e-14
+    # rotated: the clamp acts on the singular values only; total volume is kept
+    for i in range(100):
+        s = scenes.uniform(51, 3, i, 0.9, 1.1)
+        P, Q = rot(1000 + i), rot(1100 + i)
+        F = P @ np.diag(s) @ Q.T
+        Fe, Jp = oracle.snow_project(m, F, 1.03)
+        assert np.allclose(Fe, P @ np.diag(np.clip(s, lo, hi)) @ Q.T, atol=1e-12)
+        assert abs(np.linalg.det(Fe) * Jp - np.linalg.det(F) * 1.03) < 1e-12
+    # hardening: h(J_P = 1) = 1, and it scales both Lame parameters
+    F = np.eye(3) + scenes.uniform(52, 9, 0, -0.02, 0.02).reshape(3, 3)
+    mu, la = lame(m["E"], m["nu"])
+    assert np.allclose(oracle.stress(m, F, 1.0), oracle.fixed_corotated(F, mu, la), atol=1e-9)
+    h = np.exp(m["xi"] * (1 - 0.95))
+    assert np.allclose(oracle.stress(m, F, 0.95), oracle.fixed_corotated(F, mu * h, la * h), rtol=1e-12, atol=1e-7)
+
+
+def test_water_eos_and_volume_update(oracle):
+    m = scenes.WATER
+    for J in (0.9, 1.0, 1.05):
+        assert np.allclose(oracle.stress(m, np.eye(3), J), m["bulk"] * (J - 1) * J * np.eye(3), atol=1e-9)
+    # J' = J det(I + dt C') must equal det F' of the jelly update started at F = J^(1/3) I
+    n = 32
+    st = _state(23, kind="water")
+    cfg = dict(n=n, bc="sticky", dt=1e-4, gravity=(0, 0, 0))
+    gv = scenes.uniform(5, 3 * (n + 1) ** 3, 0, -1, 1).reshape(3, -1)
+    sw, _ = oracle.g2p(cfg, m, st, gv)
+    J = st["s"].astype(np.float64)
+    F = np.zeros((9, J.size)); F[[0, 4, 8]] = np.cbrt(J)
+    sj, _ = oracle.g2p(cfg, scenes.JELLY, dict(st, F=F), gv)
+    detF = np.linalg.det(sj["F"].T.reshape(-1, 3, 3))
+    assert np.allclose(sw["s"], detF, rtol=1e-12)
+
+
+# --------------------------------------------------------------------- grid
+@pytest.mark.parametrize("bc", ["sticky", "slip", "separate"])
+def test_grid_boundary_conditions(oracle, bc):
+    n = 16
+    NN = (n + 1) ** 3
+    cfg = dict(n=n, bc=bc, bc_cells=3, dt=0.0, gravity=(0, 0, 0))
+    gm = np.zeros(NN)
+    gp = np.zeros((3, NN))
+
+    def nid(i, j, k):
+        return (i * (n + 1) + j) * (n + 1) + k
+
+    cases = {  # node, velocity
+        "low_x_in": ((1, 8, 8), (-1.0, 0.5, 0.25)),
+        "low_x_out": ((2, 8, 8), (1.0, 0.5, 0.25)),
+        "high_y_in": ((8, 15, 8), (0.5, 2.0, -0.25)),
+        "high_y_out": ((8, 14, 8), (0.5, -2.0, -0.25)),
+        "corner": ((0, 16, 8), (-1.0, 1.0, 0.5)),
+        "inside": ((8, 8, 8), (1.0, 1.0, 1.0)),
+        "edge_inside": ((3, 13, 8), (-1.0, 1.0, 1.0)),  # i=3 and j=13=n-3: not in the wall band
+    }
+    for (node, vel) in cases.values():
+        gm[nid(*node)] = 2.0
+        gp[:, nid(*node)] = 2.0 * np.array(vel)
+    gv = oracle.grid_update(cfg, gm, gp)
+    got = {k: gv[:, nid(*node)] for k, (node, _) in cases.items()}
+    np.testing.assert_allclose(got["inside"], [1, 1, 1])
+    np.testing.assert_allclose(got["edge_inside"], [-1, 1, 1])
+    if bc == "sticky":
+        for k in ("low_x_in", "low_x_out", "high_y_in", "high_y_out", "corner"):
+            np.testing.assert_allclose(got[k], 0)
+    elif bc == "slip":
+        np.testing.assert_allclose(got["low_x_in"], [0, 0.5, 0.25])
+        np.testing.assert_allclose(got["low_x_out"], [0, 0.5, 0.25])
+        np.testing.assert_allclose(got["high_y_in"], [0.5, 0, -0.25])
+        np.testing.assert_allclose(got["high_y_out"], [0.5, 0, -0.25])
+        np.testing.assert_allclose(got["corner"], [0, 0, 0.5])
+    else:
+        np.testing.assert_allclose(got["low_x_in"], [0, 0.5, 0.25])
+        np.testing.assert_allclose(got["low_x_out"], [1, 0.5, 0.25])
+        np.testing.assert_allclose(got["high_y_in"], [0.5, 0, -0.25])
+        np.testing.assert_allclose(got["high_y_out"], [0.5, -2, -0.25])
+        np.testing.assert_allclose(got["corner"], [0, 0, 0.5])
+    # empty nodes get zero velocity even under gravity
+    gv2 = oracle.grid_update(dict(cfg, dt=1e-3, gravity=(0, -9.8, 0)), np.zeros(NN), np.zeros((3, NN)))
+    assert np.all(gv2 == 0)
+
+
+# ------------------------------------------------------------------ binning
+def _pos_for_cells(cells, n):
+    return ((np.asarray(cells, dtype=np.float64).T + 0.25) / n).astype(np.float32)
+
+
+def test_particle_code_bits(oracle):
+    n = 64
+    cells = [(1, 0, 0), (0, 1, 0), (0, 0, 1), (2, 0, 0), (3, 3, 3), (4, 0, 0), (0, 4, 0), (5, 6, 7), (63, 63, 63)]
+    k, cell, bad = oracle.keys(_pos_for_cells(cells, n), n)
+    assert cell.T.tolist() == [list(c) for c in cells]
+    assert k.tolist()[:7] == [1, 2, 4, 8, 63, 64, 128]
+    # x=5=101b, y=6=110b, z=7=111b; bit k of (x,y,z) lands at 3k, 3k+1, 3k+2
+    assert k[7] == int("111" "110" "101", 2)
+    assert k[8] == (1 << 18) - 1
+    assert bad == 6  # every cell with a zero coordinate is outside [1, n-1]
+
+
+def test_block_code_in_high_bits(oracle):
+    n = 128
+    N = 5000
+    x = scenes.uniform(60, 3 * N, 0, 0.05, 0.95).reshape(3, N).astype(np.float32)
+    k, cell, bad = oracle.keys(x, n)
+    assert bad == 0
+    kb, _, _ = oracle.keys(_pos_for_cells((cell >> 2).T, n), n)
+    kc, _, _ = oracle.keys(_pos_for_cells((cell & 3).T, n), n)
+    assert np.array_equal(k >> 6, kb)
+    assert np.array_equal(k & 63, kc)
+    # the code orders by cell: equal codes iff equal cells
+    assert len(np.unique(k)) == len(np.unique(cell.T, axis=0))
+
+
+def test_stable_sort_matches_python(oracle):
+    k = (scenes.splitmix64(70, 20000) % np.uint64(97)).astype(np.uint32)
+    perm, srt = oracle.stable_sort(k)
+    ref = sorted(range(k.size), key=lambda i: int(k[i]))
+    assert perm.tolist() == ref
+    assert np.array_equal(srt, k[perm])
+
+
+def test_blocks_match_set_algebra(oracle):
+    n = 64
+    N = 3000
+    lo = np.array([0.2, 0.3, 0.1])[:, None]
+    hi = np.array([0.6, 0.5, 0.3])[:, None]
+    x = (lo + (hi - lo) * scenes.uniform(61, 3 * N, 0).reshape(3, N)).astype(np.float32)
+    b = oracle.bin_particles(x, n)
+    cells = b["cell"].T[b["perm"]]
+    gset = sorted({tuple(int(ci) >> 2 for ci in c) for c in cells.tolist()},
+                  key=lambda B: oracle.keys(_pos_for_cells([B], n), n)[0][0])
+    assert len(gset) == len(b["gblock"])
+    assert int(b["gcount"].sum()) == N
+    for (B, start, cnt) in zip(gset, b["gstart"], b["gcount"]):
+        blk = cells[start:start + cnt] >> 2
+        assert np.all(blk == np.array(B))
+    NB = n // 4 + 2
+    pset = set()
+    for B in gset:
+        for d in np.ndindex(3, 3, 3):
+            bx, by, bz = (B[i] + d[i] for i in range(3))
+            pset.add((bz * NB + by) * NB + bx)
+    assert b["pblock"].tolist() == sorted(pset)
+
+
+def _golden(name):
+    vals = {}
+    with open(os.path.join(HERE, "golden", name)) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if line:
+                k, v = line.split("=")
+                vals[k.strip()] = float(v)
+    return vals
+
+
+def test_free_zone_sizes_from_paper(oracle):
+    """The free zone spans 10 cells per axis, and a particle inside it only
+    reaches the 12 nodes of 3 consecutive blocks (Rebuild-Mapping subsection;
+    the 10 bits of the in-warp sort in the Particle Sorting subsection)."""
+    g = _golden("free_zone.txt")
+    n = 64
+    B = 5
+    cs = np.arange(4 * B - 8, 4 * B + 12)
+    x = _pos_for_cells([(c, 4 * B + 1, 4 * B + 1) for c in cs], n)
+    Bs = np.full((3, cs.size), B, dtype=np.int32)
+    out = oracle.free_zone_exit(x, n, Bs)
+    inside = cs[~out]
+    assert inside.size == g["free_zone_cells_per_axis"]
+    assert inside.size ** 3 <= 2 ** g["in_warp_sort_bits"]  # (10 dx)^3 cells fit a 10-bit local code
+    assert inside.min() == 4 * B - 3 and inside.max() == 4 * B + 6
+    nodes = set()
+    for c in inside:
+        base, _ = oracle.weights(float(c))  # cell c's stencil: nodes c-1 .. c+1
+        nodes.update(range(base, base + 3))
+    assert len(nodes) == g["reachable_nodes_per_axis"]
+    blocks = {(i >> 2) for i in nodes}
+    assert len(blocks) == g["physical_blocks_per_axis"]
+    assert min(nodes) == 4 * (B - 1) and max(nodes) == 4 * (B + 1) + 3
