@@ -1,0 +1,147 @@
+"""Benchmark: the snow scene (12 seeded spheres, ~1.28M particles, 256^3 grid).
+
+One benchmark step is one 1/60 s frame: 334 substeps of 4.99e-5 s, each a
+full pass of the hot path (rebuild-mapping + radix sort when a particle left
+its free zone, P2G with the fused snow return map and stress, grid update
+with boundary conditions, G2P with the free-zone test).  Prints ONE JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+`value` is particle-substeps per second over the K timed frames (inputs
+resident in HBM before timing starts).  `roofline` covers the P2G kernel,
+timed with HIP events on the library's stream during the timed frames;
+`cpu_baseline` times the FP64 oracle on the host on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per particle and launch (FP32 state, deferred deformation
+# update): P2G reads x, v, C, F_E, J_P (100 B) and writes F_E, J_P (40 B);
+# G2P reads x (12 B) and writes x, v, C (60 B).
+P2G_BYTES = {"jelly": 132, "snow": 140, "water": 68}
+G2P_BYTES = 72
+
+# HBM bytes per P2G launch measured with rocprofv3 counters (FETCH_SIZE +
+# WRITE_SIZE, KiB per dispatch, scaled by a plain copy kernel's reading); see
+# profiles/.  None until taken for the current kernel.
+P2G_TRAFFIC_BYTES = None
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(sc, cfg, steps=4):
+    import oracle
+    from paper_2111_00699_amd import scenes
+
+    oracle.build()
+    N = sc["x"].shape[1]
+    t0 = time.perf_counter()
+    _, _, _, bad = oracle.substep(cfg, scenes.SNOW, sc, steps=steps)
+    dt = time.perf_counter() - t0
+    return {"value": N * steps / dt, "unit": "particle-substeps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} substeps of the full snow scene ({N} particles) from its initial state, "
+                      f"FP64 dense-grid oracle, single thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30, help="timed frames")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed frames")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--flags", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2111_00699_amd import mpm, scenes
+
+    torch.cuda.set_device(0)
+    sc = scenes.snow_spheres(1)
+    cfg = scenes.snow_config()
+    N = sc["x"].shape[1]
+    nsub = cfg["substeps_per_frame"]
+    log(f"[bench] snow scene N={N} n={cfg['n']} substeps/frame={nsub} dt={cfg['dt']:.4e}")
+    sim = mpm.Sim(cfg["n"], cfg["dt"], bc=cfg["bc"], bc_cells=cfg["bc_cells"], gravity=cfg["gravity"],
+                  capacity=2 * N + 256, chunk=args.chunk, flags=args.flags)
+    sim.add_particles(scenes.SNOW, sc["x"])
+    torch.cuda.synchronize()
+    for f in range(args.warmup):
+        sim.substep(nsub)
+        log(f"[bench] warmup frame {f + 1}/{args.warmup} enqueued")
+    sim.synchronize()
+    st0 = sim.stats()
+    sim.profile(mpm.PHASE_P2G)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    for f in range(args.steps):
+        sim.substep(nsub)
+        if (f + 1) % 10 == 0:
+            log(f"[bench] timed frame {f + 1}/{args.steps} enqueued")
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    gpu_ms = e0.elapsed_time(e1)
+    prof = sim.profile_read()
+    st1 = sim.stats()
+    ms = max(gpu_ms, wall * 1e3)
+    substeps = args.steps * nsub
+    value = N * substeps / (ms * 1e-3)
+    p2g = prof["p2g"]
+    p2g_avg_ms = p2g["ms"] / max(p2g["launches"], 1)
+    achieved = P2G_BYTES["snow"] * N / (p2g_avg_ms * 1e-3) / 1e9
+    rebuilds = st1["rebuilds"] - st0["rebuilds"]
+    out = {
+        "metric": "particle-substeps/s",
+        "value": value,
+        "unit": "particle-substeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "ms_per_frame": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "snow: 12 seeded spheres dropped in a 256^3 grid, snow plasticity with "
+                               "hardening, 334 substeps of 4.99e-5 s per 1/60 s frame",
+                   "particles": N, "grid": cfg["n"], "substeps_per_frame": nsub, "frames_timed": args.steps,
+                   "rebuilds_in_timed_frames": rebuilds,
+                   "substeps_per_rebuild": substeps / max(rebuilds, 1), "chunk": args.chunk or 512},
+        "roofline": {"kernel": "p2g", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None if P2G_TRAFFIC_BYTES is None else P2G_TRAFFIC_BYTES,
+                     "avg_launch_us": p2g_avg_ms * 1e3, "launches": p2g["launches"],
+                     "bytes_per_particle": P2G_BYTES["snow"]},
+        "wall_ms": wall * 1e3,
+        "gpu_event_ms": gpu_ms,
+    }
+    sim.close()
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 oracle on the host")
+        out["cpu_baseline"] = cpu_baseline(sc, cfg)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

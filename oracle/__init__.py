@@ -92,7 +92,8 @@ def _mat(m: dict) -> _Mat:
 
 
 def _cfg(c: dict) -> _Cfg:
-    bc = c["bc"] if isinstance(c["bc"], int) else BC[c["bc"]]
+    bc = c.get("bc", "sticky")
+    bc = bc if isinstance(bc, int) else BC[bc]
     g = c.get("gravity", (0.0, -9.8, 0.0))
     return _Cfg(int(c["n"]), bc, int(c.get("bc_cells", 3)), (ct.c_double * 3)(*map(float, g)), float(c["dt"]))
 

@@ -1,0 +1,331 @@
+// Rebuild-mapping and particle sorting on gfx950.
+//
+// Paper, "Material Point Method on a Single GPU": particle codes interleave
+// the 3-D cell index with the block code in the high bits and the cell code
+// in the low bits; the blocks holding particles (gblocks) and their 3x3x3
+// neighbours (pblocks) are recorded; particles are sorted to cell
+// granularity.  "Rebuild-Mapping": particle blocks are shifted by -dx/2 so a
+// particle block with its 3x3x3 neighbours covers a (10 dx)^3 free zone.
+//
+// MI355X design: the block table is a dense array over the padded domain
+// (288 GB of HBM make a dense (n/4+2)^3 table trivial), so no hash is needed
+// and block activation is a mark + compaction, deterministic and in block
+// order.  Sorting is a stable LSD radix sort with 8-bit digits, ranks taken
+// inside each wave64 from eight ballots (no atomics), so the permutation is
+// exactly a stable sort by particle code.
+#include "mpm_internal.h"
+
+namespace mpm {
+
+namespace {
+
+constexpr int RS_ITEMS = 16;
+constexpr int RS_TILE = WG * RS_ITEMS;  // 4096 keys per radix tile
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = WG * SCAN_ITEMS;  // 2048 entries per scan tile
+
+inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ int wave_incl_scan(int v) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(v, d, 64);
+        if (lane_id() >= d) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan over the 256 threads of a workgroup; *total gets the sum.
+__device__ __forceinline__ int block_excl_scan(int v, int* total) {
+    __shared__ int wsum[WG / 64];
+    const int w = threadIdx.x >> 6;
+    const int inc = wave_incl_scan(v);
+    if (lane_id() == 63) wsum[w] = inc;
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < WG / 64; ++i) {
+        off += (i < w) ? wsum[i] : 0;
+        tot += wsum[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+// ------------------------------------------------------------ particle code
+// c = floor(x/dx + 1/2) = floor(x n - 1/2) + 1 per axis.  For power-of-two
+// n, x*n is exact in FP32 and x*n - 1/2 is exact wherever it matters, so the
+// code is bit-identical to one computed in FP64 from the same FP32 x.
+__global__ __launch_bounds__(WG) void k_keys(const float* __restrict__ S, int64_t cap, int N, float fn, int n,
+                                             uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                             int* __restrict__ ctl) {
+    const int j = blockIdx.x * WG + threadIdx.x;
+    if (j >= N) return;
+    uint32_t code = 0;
+    unsigned err = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float x = S[(FX + a) * cap + j];
+        const float b = floorf(x * fn - 0.5f);
+        int c;
+        if (!(b == b)) {
+            err |= MPM_ERR_NONFINITE;
+            c = 0;
+        } else {
+            if (!(b >= 0.0f && b <= (float)(n - 2))) err |= MPM_ERR_DOMAIN;
+            c = (int)fminf(fmaxf(b + 1.0f, 0.0f), (float)(n - 1));
+        }
+        code |= spread3((uint32_t)c) << a;
+    }
+    keys[j] = code;
+    vals[j] = (uint32_t)j;
+    if (err) atomicOr(&ctl[CTL_ERROR], (int)err);
+}
+
+// --------------------------------------------------------------- radix sort
+__global__ __launch_bounds__(WG) void k_rs_hist(const uint32_t* __restrict__ keys, int N, int shift, int tiles,
+                                                int* __restrict__ hist) {
+    __shared__ int h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int base = blockIdx.x * RS_TILE;
+#pragma unroll
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        const int i = base + r * WG + threadIdx.x;
+        if (i < N) atomicAdd(&h[(keys[i] >> shift) & 255u], 1);
+    }
+    __syncthreads();
+    hist[threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter: keys of the tile are taken in order, 256 at a time; inside
+// a wave the rank among lanes with the same digit comes from eight ballots,
+// across the four waves from per-wave digit counts in LDS.
+__global__ __launch_bounds__(WG) void k_rs_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                   uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, int N,
+                                                   int shift, int tiles, const int* __restrict__ offs) {
+    __shared__ int base[256];
+    __shared__ int wcnt[WG / 64][256];
+    const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
+    base[tid] = offs[tid * tiles + blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < WG / 64; ++i) wcnt[i][tid] = 0;
+    __syncthreads();
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        const int i = blockIdx.x * RS_TILE + r * WG + tid;
+        const bool valid = i < N;
+        const uint32_t key = valid ? kin[i] : 0u;
+        const uint32_t val = valid ? vin[i] : 0u;
+        const uint32_t d = (key >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const int rank = __popcll(peers & below);
+        if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            int off = base[d] + rank;
+#pragma unroll
+            for (int k = 0; k < WG / 64; ++k) off += (k < w) ? wcnt[k][d] : 0;
+            kout[off] = key;
+            vout[off] = val;
+        }
+        __syncthreads();
+        int add = 0;
+#pragma unroll
+        for (int k = 0; k < WG / 64; ++k) {
+            add += wcnt[k][tid];
+            wcnt[k][tid] = 0;
+        }
+        base[tid] += add;
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------- generic scan
+// Three launches: per-tile totals, a one-workgroup scan of the totals, and a
+// per-tile exclusive scan that hands each element its output offset.
+template <class Op>
+__global__ __launch_bounds__(WG) void k_scan_count(Op op, int n, int* __restrict__ tile_sums) {
+    const int first = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i)
+        if (first + i < n) s += op.count(first + i);
+    int tot;
+    block_excl_scan(s, &tot);
+    if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(WG) void k_scan_top(int* __restrict__ a, int n, int* __restrict__ total) {
+    int carry = 0;
+    for (int base = 0; base < n; base += WG) {
+        const int i = base + threadIdx.x;
+        const int v = i < n ? a[i] : 0;
+        int tot;
+        const int ex = block_excl_scan(v, &tot);
+        if (i < n) a[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+template <class Op>
+__global__ __launch_bounds__(WG) void k_scan_emit(Op op, int n, const int* __restrict__ tile_offs) {
+    const int first = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    int c[SCAN_ITEMS];
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        c[i] = (first + i < n) ? op.count(first + i) : 0;
+        s += c[i];
+    }
+    int tot;
+    int off = tile_offs[blockIdx.x] + block_excl_scan(s, &tot);
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        if (c[i] > 0) op.emit(first + i, off, c[i]);
+        off += c[i];
+    }
+}
+
+template <class Op>
+void device_scan(hipStream_t st, const Op& op, int n, int* tile_sums, int* total) {
+    const int tiles = cdiv(n > 0 ? n : 1, SCAN_TILE);
+    hipLaunchKernelGGL(k_scan_count<Op>, dim3(tiles), dim3(WG), 0, st, op, n, tile_sums);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(WG), 0, st, tile_sums, tiles, total);
+    hipLaunchKernelGGL(k_scan_emit<Op>, dim3(tiles), dim3(WG), 0, st, op, n, tile_sums);
+}
+
+struct OpHistScan {  // exclusive scan of the radix histogram in place
+    int* h;
+    __device__ int count(int i) const { return h[i]; }
+    __device__ void emit(int i, int off, int) const { h[i] = off; }
+};
+
+// Geometric blocks: positions where the block code (code >> 6) changes.
+struct OpGBlocks {
+    const uint32_t* keys;
+    int N;
+    int* gstart;
+    uint32_t* gcode;
+    __device__ int count(int j) const { return (j == 0 || (keys[j] >> 6) != (keys[j - 1] >> 6)) ? 1 : 0; }
+    __device__ void emit(int j, int off, int) const {
+        gstart[off] = j;
+        gcode[off] = keys[j] >> 6;
+    }
+};
+
+// Work chunks: each geometric block split into runs of at most `chunk`.
+struct OpChunks {
+    const int* gstart;
+    const uint32_t* gcode;
+    const int* ctl;
+    int N, chunk;
+    Chunk* out;
+    __device__ int len(int g) const {
+        const int ng = ctl[CTL_NGB];
+        const int end = (g + 1 < ng) ? gstart[g + 1] : N;
+        return end - gstart[g];
+    }
+    __device__ int count(int g) const {
+        if (g >= ctl[CTL_NGB]) return 0;
+        return (len(g) + chunk - 1) / chunk;
+    }
+    __device__ void emit(int g, int off, int k) const {
+        const uint32_t code = gcode[g];
+        const int packed = (int)(compact3(code) | (compact3(code >> 1) << 10) | (compact3(code >> 2) << 20));
+        const int s0 = gstart[g], l = len(g);
+        for (int i = 0; i < k; ++i) {
+            Chunk c;
+            c.start = s0 + i * chunk;
+            c.count = min(chunk, l - i * chunk);
+            c.block = packed;
+            c.pad = g;
+            out[off + i] = c;
+        }
+    }
+};
+
+struct OpActive {
+    const int* state;
+    int* active;
+    __device__ int count(int b) const { return state[b] != 0 ? 1 : 0; }
+    __device__ void emit(int b, int off, int) const { active[off] = b; }
+};
+
+// ------------------------------------------------------------ data movement
+__global__ __launch_bounds__(WG) void k_permute(const float* __restrict__ Sin, float* __restrict__ Sout,
+                                                const int* __restrict__ idin, int* __restrict__ idout,
+                                                const uint32_t* __restrict__ src, int64_t cap, int N) {
+    const int j = blockIdx.x * WG + threadIdx.x;
+    if (j >= N) return;
+    const int k = (int)src[j];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) Sout[f * cap + j] = Sin[f * cap + k];
+    idout[j] = idin[k];
+}
+
+__global__ __launch_bounds__(WG) void k_fill(int* __restrict__ p, int v, int n) {
+    const int i = blockIdx.x * WG + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Mark the 3x3x3 neighbourhood of every geometric block as physical.
+__global__ __launch_bounds__(WG) void k_dilate(const uint32_t* __restrict__ gcode, const int* __restrict__ ctl,
+                                               int NB, int* __restrict__ state) {
+    const int total = ctl[CTL_NGB] * 27;
+    for (int t = blockIdx.x * WG + threadIdx.x; t < total; t += gridDim.x * WG) {
+        const int g = t / 27, o = t % 27;
+        const uint32_t code = gcode[g];
+        const int bx = (int)compact3(code) + (o % 3);  // (B - 1) + o + 1 in padded coordinates
+        const int by = (int)compact3(code >> 1) + (o / 3) % 3;
+        const int bz = (int)compact3(code >> 2) + o / 9;
+        state[(bz * NB + by) * NB + bx] = 1;
+    }
+}
+
+__global__ void k_clear_rebuild(int* ctl) { ctl[CTL_REBUILD] = 0; }
+
+}  // namespace
+
+void enqueue_rebuild(hipStream_t st, const Step& P, float* S_cur, float* S_alt, int* id_cur, int* id_alt, int64_t cap,
+                     int N, int chunk, BinBuffers& B, int* ctl, int nbricks) {
+    const int nb = cdiv(N > 0 ? N : 1, WG);
+    // 1. particle codes
+    hipLaunchKernelGGL(k_keys, dim3(nb), dim3(WG), 0, st, S_cur, cap, N, P.fn, P.n, B.keys[0], B.vals[0], ctl);
+    // 2. stable radix sort of (code, position)
+    int bits = 0;
+    while ((1 << bits) < P.n) ++bits;
+    const int passes = (3 * bits + 7) / 8;
+    const int tiles = cdiv(N > 0 ? N : 1, RS_TILE);
+    int cur = 0;
+    for (int p = 0; p < passes; ++p) {
+        hipLaunchKernelGGL(k_rs_hist, dim3(tiles), dim3(WG), 0, st, B.keys[cur], N, 8 * p, tiles, B.hist);
+        device_scan(st, OpHistScan{B.hist}, 256 * tiles, B.scan_tiles, ctl + CTL_SCAN);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(tiles), dim3(WG), 0, st, B.keys[cur], B.vals[cur], B.keys[cur ^ 1],
+                           B.vals[cur ^ 1], N, 8 * p, tiles, B.hist);
+        cur ^= 1;
+    }
+    B.sorted = cur;  // slot holding the sorted codes and their source positions
+    // 3. gather the whole particle state into sorted order
+    hipLaunchKernelGGL(k_permute, dim3(nb), dim3(WG), 0, st, S_cur, S_alt, id_cur, id_alt, B.vals[cur], cap, N);
+    // 4. geometric blocks and work chunks
+    device_scan(st, OpGBlocks{B.keys[cur], N, B.gstart, B.gcode}, N, B.scan_tiles, ctl + CTL_NGB);
+    device_scan(st, OpChunks{B.gstart, B.gcode, ctl, N, chunk, B.chunks}, N, B.scan_tiles, ctl + CTL_NCHUNK);
+    // 5. physical blocks: 3x3x3 dilation, compacted in padded linear order
+    hipLaunchKernelGGL(k_fill, dim3(cdiv(nbricks, WG)), dim3(WG), 0, st, B.brick_state, 0, nbricks);
+    hipLaunchKernelGGL(k_dilate, dim3(512), dim3(WG), 0, st, B.gcode, ctl, P.NB, B.brick_state);
+    device_scan(st, OpActive{B.brick_state, B.active}, nbricks, B.scan_tiles, ctl + CTL_NACTIVE);
+    hipLaunchKernelGGL(k_clear_rebuild, dim3(1), dim3(1), 0, st, ctl);
+}
+
+}  // namespace mpm

@@ -1,0 +1,269 @@
+// Internal declarations of the gfx950 MLS-MPM library: buffer layout,
+// per-substep constants, launchers and the per-particle device math.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mpm.h"
+
+namespace mpm {
+
+// ----------------------------------------------------------------- layout
+// Particle state: one FP32 array per scalar field, field f at S + f * cap.
+enum Field : int { FX = 0, FV = 3, FC = 6, FF = 15, FS = 24, NF = 25 };
+
+constexpr int WG = 256;       // threads per workgroup (four wave64s)
+constexpr int TILE = 12;      // nodes per axis reachable from one particle block (3 blocks)
+constexpr int TILE3 = TILE * TILE * TILE;
+constexpr int BLOCK_NODES = 64;  // 4^3 nodes per grid block
+
+// Small device-side control words.
+enum Ctl : int {
+    CTL_NGB = 0,       // geometric (particle) blocks of the last rebuild
+    CTL_NCHUNK = 1,    // work chunks of the last rebuild
+    CTL_NACTIVE = 2,   // physical blocks of the last rebuild
+    CTL_REBUILD = 3,   // a particle left its free zone since the last rebuild
+    CTL_ERROR = 4,     // sticky MPM_ERR_* bits
+    CTL_OVF = 5,       // overflow-block counts, two slots by substep parity
+    CTL_SCAN = 8,      // scratch total of a device scan
+    CTL_WORDS = 16
+};
+
+// Derived material constants.
+struct Mat {
+    int kind;
+    float mu, la;      // Lame parameters
+    float mp;          // particle mass rho * V0
+    float scale;       // 4 dt V0 / dx^2 (stress term of the APIC affine matrix)
+    float lo, hi;      // snow singular-value bounds 1 - theta_c, 1 + theta_s
+    float xi, bulk;
+};
+
+// Per-substep constants.
+struct Step {
+    int n;          // cells per axis
+    int NB;         // padded blocks per axis, n/4 + 2
+    float fn;       // float(n) = 1/dx
+    float dx, dt;
+    float g0, g1, g2;
+    int bc, bc_cells;
+};
+
+// A run of at most `chunk` sorted particles that share one particle block.
+struct Chunk {
+    int start, count;
+    int block;  // packed block coordinates Bx | By << 10 | Bz << 20
+    int pad;
+};
+
+// ------------------------------------------------------------ launchers
+// Binning and sorting (mpm_bin.hip).
+struct BinBuffers {
+    uint32_t *keys[2], *vals[2];
+    int* hist;         // radix digit histograms [256][tiles]
+    int* scan_tiles;   // per-tile sums of the generic scan
+    int* gstart;       // [cap + 1]
+    uint32_t* gcode;   // [cap]
+    Chunk* chunks;     // [cap]
+    int* brick_state;  // [NB^3] 0 idle, 1 physical block of the rebuild, 2 overflow this substep
+    int* active;       // [NB^3]
+    int sorted;        // which keys/vals slot holds the last sorted codes (host side)
+};
+
+void enqueue_rebuild(hipStream_t st, const Step& P, float* S_cur, float* S_alt, int* id_cur, int* id_alt,
+                     int64_t cap, int N, int chunk, BinBuffers& B, int* ctl, int nbricks);
+
+// Substep kernels (mpm_step.hip).
+struct GridBuffers {
+    float* acc;     // [NB^3 * 64 * 4] (m, px, py, pz) accumulators, zero between substeps
+    float4* vel;    // [NB^3 * 64] (vx, vy, vz, m) after the grid update
+    int* stamp;     // [NB^3] substep index of the last update of each block
+    int* ovf[2];    // overflow block lists, by substep parity
+};
+
+struct Launch {
+    int p2g_grid, g2p_grid, grid_grid, cus;
+};
+
+void enqueue_p2g(hipStream_t st, const Launch& L, const Step& P, const Mat& M, float* S, int64_t cap,
+                 const Chunk* chunks, int* ctl, GridBuffers& G, int* brick_state, int pending, int parity,
+                 int global_atomics, int transpose_lanes, int nbricks);
+int p2g_grid_size(int cus);
+void enqueue_grid(hipStream_t st, const Launch& L, const Step& P, const int* active, int* ctl, GridBuffers& G,
+                  int* brick_state, int parity, int step);
+void enqueue_g2p(hipStream_t st, const Launch& L, const Step& P, float* S, int64_t cap, const Chunk* chunks,
+                 int* ctl, const GridBuffers& G, int* host_flag);
+void enqueue_materialize(hipStream_t st, const Step& P, const Mat& M, float* S, int64_t cap, int N);
+void enqueue_insert(hipStream_t st, float* S, int* ids, int64_t cap, int N0, int count, const float* x,
+                    const float* v, const float* C, const float* F, const float* s, int* ctl);
+void enqueue_read(hipStream_t st, const Step& P, const Mat& M, const float* S, const int* ids, int64_t cap, int N,
+                  int pending, float* x, float* v, float* C, float* F, float* s);
+void enqueue_read_grid(hipStream_t st, const Step& P, const GridBuffers& G, int step, float* m, float* v);
+void query_launch(Launch& L);
+
+// ----------------------------------------------------------- device math
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {  // 10 low bits -> every third bit
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__device__ __forceinline__ uint32_t compact3(uint32_t v) {  // inverse of spread3
+    v &= 0x09249249u;
+    v = (v ^ (v >> 2)) & 0x030C30C3u;
+    v = (v ^ (v >> 4)) & 0x0300F00Fu;
+    v = (v ^ (v >> 8)) & 0x030000FFu;
+    v = (v ^ (v >> 16)) & 0x000003FFu;
+    return v;
+}
+
+// One Jacobi rotation of a symmetric 3x3 in the (p,q) plane that zeroes a_pq;
+// r is the remaining index.  The rotation is accumulated into columns p, q of U.
+__device__ __forceinline__ void jacobi_rotate(float& app, float& aqq, float& apq, float& arp, float& arq, float& u0p,
+                                              float& u0q, float& u1p, float& u1q, float& u2p, float& u2q) {
+    const float d = aqq - app;
+    const float den = fabsf(d) + sqrtf(d * d + 4.0f * apq * apq);
+    const float t = den > 0.0f ? (d >= 0.0f ? 2.0f * apq : -2.0f * apq) / den : 0.0f;
+    const float c = rsqrtf(1.0f + t * t);
+    const float s = t * c;
+    app -= t * apq;
+    aqq += t * apq;
+    apq = 0.0f;
+    const float rp = arp, rq = arq;
+    arp = c * rp - s * rq;
+    arq = s * rp + c * rq;
+    float a, b;
+    a = u0p; b = u0q; u0p = c * a - s * b; u0q = s * a + c * b;
+    a = u1p; b = u1q; u1p = c * a - s * b; u1q = s * a + c * b;
+    a = u2p; b = u2q; u2p = c * a - s * b; u2q = s * a + c * b;
+}
+
+// Eigen-decomposition of the symmetric b = [b00 b01 b02; . b11 b12; . . b22]
+// by cyclic Jacobi sweeps.  On return lam[k] are the eigenvalues and column k
+// of U (U[i*3+k]) the matching unit eigenvector.
+__device__ __forceinline__ void eig_sym3(float b00, float b01, float b02, float b11, float b12, float b22, float U[9],
+                                         float lam[3]) {
+    float u00 = 1, u01 = 0, u02 = 0, u10 = 0, u11 = 1, u12 = 0, u20 = 0, u21 = 0, u22 = 1;
+#pragma unroll
+    for (int sweep = 0; sweep < 4; ++sweep) {
+        jacobi_rotate(b00, b11, b01, b02, b12, u00, u01, u10, u11, u20, u21);  // (0,1), r = 2
+        jacobi_rotate(b00, b22, b02, b01, b12, u00, u02, u10, u12, u20, u22);  // (0,2), r = 1
+        jacobi_rotate(b11, b22, b12, b01, b02, u01, u02, u11, u12, u21, u22);  // (1,2), r = 0
+    }
+    lam[0] = b00; lam[1] = b11; lam[2] = b22;
+    U[0] = u00; U[1] = u01; U[2] = u02;
+    U[3] = u10; U[4] = u11; U[5] = u12;
+    U[6] = u20; U[7] = u21; U[8] = u22;
+}
+
+__device__ __forceinline__ float det3(const float A[9]) {
+    return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+           A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+
+// out = (I + dt C) A
+__device__ __forceinline__ void advance_gradient(const float C[9], float dt, const float A[9], float out[9]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            out[a * 3 + b] = A[a * 3 + b] +
+                             dt * (C[a * 3 + 0] * A[0 * 3 + b] + C[a * 3 + 1] * A[1 * 3 + b] + C[a * 3 + 2] * A[2 * 3 + b]);
+}
+
+// U diag(d) U^T as the 6 entries (00, 01, 02, 11, 12, 22)
+__device__ __forceinline__ void sym_from_eig(const float U[9], float d0, float d1, float d2, float T[6]) {
+    T[0] = U[0] * U[0] * d0 + U[1] * U[1] * d1 + U[2] * U[2] * d2;
+    T[1] = U[0] * U[3] * d0 + U[1] * U[4] * d1 + U[2] * U[5] * d2;
+    T[2] = U[0] * U[6] * d0 + U[1] * U[7] * d1 + U[2] * U[8] * d2;
+    T[3] = U[3] * U[3] * d0 + U[4] * U[4] * d1 + U[5] * U[5] * d2;
+    T[4] = U[3] * U[6] * d0 + U[4] * U[7] * d1 + U[5] * U[8] * d2;
+    T[5] = U[6] * U[6] * d0 + U[7] * U[7] * d1 + U[8] * U[8] * d2;
+}
+
+// Singular values of F from the eigen-decomposition of b = F F^T, with the
+// sign of det F carried by the smallest one; U holds the left singular vectors.
+__device__ __forceinline__ void left_svd(const float F[9], float U[9], float sig[3], float& J) {
+    const float b00 = F[0] * F[0] + F[1] * F[1] + F[2] * F[2];
+    const float b01 = F[0] * F[3] + F[1] * F[4] + F[2] * F[5];
+    const float b02 = F[0] * F[6] + F[1] * F[7] + F[2] * F[8];
+    const float b11 = F[3] * F[3] + F[4] * F[4] + F[5] * F[5];
+    const float b12 = F[3] * F[6] + F[4] * F[7] + F[5] * F[8];
+    const float b22 = F[6] * F[6] + F[7] * F[7] + F[8] * F[8];
+    float lam[3];
+    eig_sym3(b00, b01, b02, b11, b12, b22, U, lam);
+    sig[0] = sqrtf(fmaxf(lam[0], 0.0f));
+    sig[1] = sqrtf(fmaxf(lam[1], 0.0f));
+    sig[2] = sqrtf(fmaxf(lam[2], 0.0f));
+    J = det3(F);
+    if (J < 0.0f) {  // negate the smallest singular value
+        const int k = (sig[0] <= sig[1]) ? (sig[0] <= sig[2] ? 0 : 2) : (sig[1] <= sig[2] ? 1 : 2);
+        sig[k] = -sig[k];
+    }
+}
+
+// Apply the deferred deformation update of the last G2P (when `pending`),
+// the snow return map, and produce the Kirchhoff stress tau (6 entries).
+// F (9) and s are updated in place.
+__device__ __forceinline__ void material_step(const Mat& M, float dt, int pending, const float C[9], float F[9],
+                                              float& s, float tau[6]) {
+    if (M.kind == MPM_WATER) {
+        if (pending) {
+            float G[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) G[i] = dt * C[i] + ((i % 4 == 0) ? 1.0f : 0.0f);
+            s *= det3(G);
+        }
+        const float p = M.bulk * (s - 1.0f) * s;
+        tau[0] = p; tau[1] = 0.0f; tau[2] = 0.0f; tau[3] = p; tau[4] = 0.0f; tau[5] = p;
+        return;
+    }
+    float Fh[9];
+    if (pending) {
+        advance_gradient(C, dt, F, Fh);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Fh[i] = F[i];
+    }
+    float U[9], sig[3], J;
+    left_svd(Fh, U, sig, J);
+    float mu = M.mu, la = M.la;
+    if (M.kind == MPM_SNOW) {
+        if (pending) {
+            float sc[3], r[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                sc[k] = fminf(fmaxf(sig[k], M.lo), M.hi);
+                r[k] = sc[k] / sig[k];
+            }
+            float R[6];
+            sym_from_eig(U, r[0], r[1], r[2], R);  // F_E' = U diag(sc/sig) U^T Fhat
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const float f0 = Fh[0 * 3 + b], f1 = Fh[1 * 3 + b], f2 = Fh[2 * 3 + b];
+                F[0 * 3 + b] = R[0] * f0 + R[1] * f1 + R[2] * f2;
+                F[1 * 3 + b] = R[1] * f0 + R[3] * f1 + R[4] * f2;
+                F[2 * 3 + b] = R[2] * f0 + R[4] * f1 + R[5] * f2;
+            }
+            const float Jc = sc[0] * sc[1] * sc[2];
+            s = s * J / Jc;
+            J = Jc;
+            sig[0] = sc[0]; sig[1] = sc[1]; sig[2] = sc[2];
+        }
+        const float h = __expf(M.xi * (1.0f - s));
+        mu *= h;
+        la *= h;
+    } else if (pending) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) F[i] = Fh[i];
+    }
+    const float vol = la * (J - 1.0f) * J;
+    sym_from_eig(U, 2.0f * mu * (sig[0] - 1.0f) * sig[0] + vol, 2.0f * mu * (sig[1] - 1.0f) * sig[1] + vol,
+                 2.0f * mu * (sig[2] - 1.0f) * sig[2] + vol, tau);
+}
+
+}  // namespace mpm

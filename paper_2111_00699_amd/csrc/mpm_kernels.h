@@ -1,0 +1,112 @@
+// Device helpers shared by the substep kernels: per-XCD work split, the
+// quadratic B-spline stencil, dense block addressing, overflow-block
+// activation and wave64 reductions.
+#pragma once
+
+#include <limits.h>
+
+#include "mpm_internal.h"
+
+namespace mpm {
+
+inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// Contiguous per-XCD ranges: workgroup w runs on XCD w % 8, so each XCD walks
+// its own contiguous slice of the block-sorted work list.
+__device__ __forceinline__ void xcd_split(int total, int& begin, int& end, int& stride) {
+    const int x = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    stride = gridDim.x >> 3;
+    begin = (int)(((int64_t)total * x) >> 3) + slot;
+    end = (int)(((int64_t)total * (x + 1)) >> 3);
+}
+
+struct Stencil {
+    int base[3];
+    float f[3];
+    float w[3][3];
+};
+
+// Quadratic B-spline stencil: base = floor(x/dx - 1/2), f = x/dx - base,
+// weights 1/2 (3/2 - f)^2, 3/4 - (f - 1)^2, 1/2 (f - 1/2)^2.  Returns false
+// (and sets an error bit) when x is not finite or the stencil leaves [0, n].
+__device__ __forceinline__ bool make_stencil(const float x[3], const Step& P, Stencil& s, unsigned& err) {
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float t = x[a] * P.fn;
+        const float b = floorf(t - 0.5f);
+        if (!(b == b)) {
+            err |= MPM_ERR_NONFINITE;
+            ok = false;
+            s.base[a] = 0;
+            s.f[a] = 1.0f;
+        } else {
+            if (!(b >= 0.0f && b <= (float)(P.n - 2))) {
+                err |= MPM_ERR_DOMAIN;
+                ok = false;
+            }
+            s.base[a] = (int)b;
+            s.f[a] = t - b;
+        }
+        const float f = s.f[a];
+        s.w[a][0] = 0.5f * (1.5f - f) * (1.5f - f);
+        s.w[a][1] = 0.75f - (f - 1.0f) * (f - 1.0f);
+        s.w[a][2] = 0.5f * (f - 0.5f) * (f - 0.5f);
+    }
+    return ok;
+}
+
+// Offsets (in nodes) into the dense block array for the three stencil nodes
+// along one axis: block = (node >> 2) + 1 (padded), local = node & 3.
+__device__ __forceinline__ void axis_offsets(int base, int blockstride, int localshift, int off[3]) {
+#pragma unroll
+    for (int o = 0; o < 3; ++o) {
+        const int node = base + o;
+        off[o] = ((node >> 2) + 1) * blockstride * BLOCK_NODES + ((node & 3) << localshift);
+    }
+}
+
+// Mark the (at most 2x2x2) blocks of a stencil; blocks outside the physical
+// set of the last rebuild are appended once to the overflow list.
+__device__ __forceinline__ void activate_blocks(const Stencil& s, const Step& P, int* brick_state, int* ovf,
+                                                int* ovf_count, int nbricks, unsigned& err) {
+    int lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = (s.base[a] >> 2) + 1;
+        hi[a] = ((s.base[a] + 2) >> 2) + 1;
+    }
+    for (int bz = lo[2]; bz <= hi[2]; ++bz)
+        for (int by = lo[1]; by <= hi[1]; ++by)
+            for (int bx = lo[0]; bx <= hi[0]; ++bx) {
+                const int b = (bz * P.NB + by) * P.NB + bx;
+                if (__hip_atomic_load(&brick_state[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
+                    atomicCAS(&brick_state[b], 0, 2) == 0) {
+                    const int k = atomicAdd(ovf_count, 1);
+                    if (k < nbricks)
+                        ovf[k] = b;
+                    else
+                        err |= MPM_ERR_CAPACITY;
+                }
+            }
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = min(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+__device__ __forceinline__ float wave_maxf(float v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+}  // namespace mpm

@@ -1,0 +1,255 @@
+// P2G on gfx950: particle-to-grid transfer with the deferred deformation
+// update, the snow return map and the Kirchhoff stress fused in (paper,
+// "Merge Kernels": plasticity, SVD and stress computed inside P2G).
+//
+// Avoiding non-native intrinsics ("Avoid non-native intrinsics"): on V100
+// the paper drops shared-memory float atomics because they are emulated.
+// On gfx950 ds_add_f32 exists but runs at about 0.3 lane-ops per clock per
+// CU, while ds_add_f64 runs at about 6.6 and global float atomics at about
+// 0.4 (measured on MI355X), so the same principle leads here to an LDS tile
+// accumulated with FP64 atomics:
+//   * a workgroup takes one chunk (<= 512 particles of one particle block),
+//     one particle per thread;
+//   * phase 1 computes every particle's contribution and the bounding box of
+//     the stencils of the chunk's in-zone particles (block reduction);
+//   * the tile is that box (at most 512 nodes; a particle block's stencils
+//     cover 6^3 = 216 nodes right after a rebuild), four FP64 channels
+//     (sum of weights, three momentum components);
+//   * phase 2 adds every contribution with ds_add_f64;
+//   * the flush scales the weight sum by the particle mass and adds the
+//     non-empty nodes to the dense block grid with global float atomics.
+// Lane mapping: lane l of wave w takes sorted position w + rows*l (a
+// transpose of the chunk), so the lanes of a wave sit about one cell apart
+// and rarely hit one LDS address, where same-address atomics serialize.
+// Particles outside their free zone (before a late rebuild) scatter straight
+// to global atomics and activate the blocks they touch.
+#include "mpm_kernels.h"
+
+namespace mpm {
+
+namespace {
+
+constexpr int P2G_WG = 512;  // threads per workgroup = max particles per chunk
+constexpr int CT = 512;      // compact tile capacity in nodes
+
+template <bool GLOBAL_ONLY>
+__global__ __launch_bounds__(P2G_WG) void k_p2g(float* __restrict__ S, int64_t cap, const Chunk* __restrict__ chunks,
+                                                int* __restrict__ ctl, float* __restrict__ acc,
+                                                int* __restrict__ brick_state, int* __restrict__ ovf, int parity,
+                                                Step P, Mat M, int pending, int nbricks, int transpose_lanes) {
+    __shared__ double tq[GLOBAL_ONLY ? 1 : 4 * CT];
+    __shared__ int red_i[6][P2G_WG / 64];
+    unsigned err = 0;
+    int begin, end, stride;
+    xcd_split(ctl[CTL_NCHUNK], begin, end, stride);
+    const float dx = P.dx, dt = P.dt;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int c = begin; c < end; c += stride) {
+        const Chunk ch = chunks[c];
+        const int count = ch.count;
+        const int B[3] = {ch.block & 1023, (ch.block >> 10) & 1023, ch.block >> 20};
+        int j = tid;
+        if (transpose_lanes) {
+            const int rows = (count + 63) >> 6;
+            j = (wv < rows) ? wv + rows * lane : count;
+        }
+        const bool have = j < count;
+        const int p = ch.start + (have ? j : 0);
+
+        // ---- phase 1: material update, stress and this particle's payload
+        Stencil st;
+        float q[3] = {0.f, 0.f, 0.f}, Ad[9];
+        bool ok = false, in_zone = false;
+        if (have) {
+            float x[3], v[3], C[9], F[9], s;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                x[a] = S[(FX + a) * cap + p];
+                v[a] = S[(FV + a) * cap + p];
+            }
+#pragma unroll
+            for (int k = 0; k < 9; ++k) C[k] = S[(FC + k) * cap + p];
+            s = S[FS * cap + p];
+            if (M.kind != MPM_WATER) {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) F[k] = S[(FF + k) * cap + p];
+            }
+            float tau[6];
+            material_step(M, dt, pending, C, F, s, tau);
+            if (pending) {  // the deferred update of the last G2P lands here
+                if (M.kind != MPM_WATER) {
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) S[(FF + k) * cap + p] = F[k];
+                }
+                if (M.kind != MPM_JELLY) S[FS * cap + p] = s;
+            }
+            ok = make_stencil(x, P, st, err);
+            // A = m C - (4 dt V0 / dx^2) tau;  Ad = dx A;  q = m v - Ad f, so the
+            // momentum sent to stencil node o is w_o (q + Ad o).
+            const float Tf[9] = {tau[0], tau[1], tau[2], tau[1], tau[3], tau[4], tau[2], tau[4], tau[5]};
+#pragma unroll
+            for (int k = 0; k < 9; ++k) Ad[k] = dx * (M.mp * C[k] - M.scale * Tf[k]);
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                q[a] = M.mp * v[a] - (Ad[a * 3 + 0] * st.f[0] + Ad[a * 3 + 1] * st.f[1] + Ad[a * 3 + 2] * st.f[2]);
+            in_zone = ok;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int l = st.base[a] - (4 * B[a] - 4);
+                in_zone = in_zone && l >= 0 && l <= TILE - 3;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) Ad[k] = 0.0f;
+        }
+
+        // ---- the box of the in-zone stencils of the chunk
+        int lo[3] = {0, 0, 0}, ext[3] = {0, 0, 0};
+        int nt = 0;
+        if (!GLOBAL_ONLY) {
+            const bool tiled = have && in_zone;
+            int mn[3], mx[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                mn[a] = wave_min(tiled ? st.base[a] : INT_MAX);
+                mx[a] = wave_max(tiled ? st.base[a] + 2 : INT_MIN);
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    red_i[a][wv] = mn[a];
+                    red_i[3 + a][wv] = mx[a];
+                }
+            }
+            __syncthreads();
+            int hi[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = INT_MAX;
+                hi[a] = INT_MIN;
+            }
+#pragma unroll
+            for (int k = 0; k < P2G_WG / 64; ++k) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = min(lo[a], red_i[a][k]);
+                    hi[a] = max(hi[a], red_i[3 + a][k]);
+                }
+            }
+            if (hi[0] >= lo[0]) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) ext[a] = hi[a] - lo[a] + 1;
+                nt = ext[0] * ext[1] * ext[2];
+            }
+            if (nt > CT) nt = -1;  // does not fit: the chunk goes to global atomics
+            for (int t = tid; t < nt; t += P2G_WG) {
+#pragma unroll
+                for (int ch4 = 0; ch4 < 4; ++ch4) tq[ch4 * CT + t] = 0.0;
+            }
+            __syncthreads();
+        }
+
+        // ---- phase 2: scatter
+        if (have && ok) {
+            if (!GLOBAL_ONLY && in_zone && nt > 0) {
+                const int tb = (st.base[0] - lo[0]) + ext[0] * ((st.base[1] - lo[1]) + ext[1] * (st.base[2] - lo[2]));
+#pragma unroll
+                for (int o2 = 0; o2 < 3; ++o2)
+#pragma unroll
+                    for (int o1 = 0; o1 < 3; ++o1) {
+                        const float wyz = st.w[1][o1] * st.w[2][o2];
+                        float m0 = q[0] + o1 * Ad[1] + o2 * Ad[2];
+                        float m1 = q[1] + o1 * Ad[4] + o2 * Ad[5];
+                        float m2 = q[2] + o1 * Ad[7] + o2 * Ad[8];
+                        const int row = tb + ext[0] * (o1 + ext[1] * o2);
+#pragma unroll
+                        for (int o0 = 0; o0 < 3; ++o0) {
+                            const float w = wyz * st.w[0][o0];
+                            const int t = row + o0;
+                            atomicAdd(&tq[t], (double)w);
+                            atomicAdd(&tq[CT + t], (double)(w * m0));
+                            atomicAdd(&tq[2 * CT + t], (double)(w * m1));
+                            atomicAdd(&tq[3 * CT + t], (double)(w * m2));
+                            m0 += Ad[0];
+                            m1 += Ad[3];
+                            m2 += Ad[6];
+                        }
+                    }
+            } else {
+                if (!in_zone) activate_blocks(st, P, brick_state, ovf, &ctl[CTL_OVF + parity], nbricks, err);
+                int xo[3], yo[3], zo[3];
+                axis_offsets(st.base[0], 1, 0, xo);
+                axis_offsets(st.base[1], P.NB, 2, yo);
+                axis_offsets(st.base[2], P.NB * P.NB, 4, zo);
+#pragma unroll
+                for (int o2 = 0; o2 < 3; ++o2)
+#pragma unroll
+                    for (int o1 = 0; o1 < 3; ++o1) {
+                        const float wyz = st.w[1][o1] * st.w[2][o2];
+                        float m0 = q[0] + o1 * Ad[1] + o2 * Ad[2];
+                        float m1 = q[1] + o1 * Ad[4] + o2 * Ad[5];
+                        float m2 = q[2] + o1 * Ad[7] + o2 * Ad[8];
+#pragma unroll
+                        for (int o0 = 0; o0 < 3; ++o0) {
+                            const float w = wyz * st.w[0][o0];
+                            float* a = acc + 4 * (xo[o0] + yo[o1] + zo[o2]);
+                            unsafeAtomicAdd(a + 0, w * M.mp);
+                            unsafeAtomicAdd(a + 1, w * m0);
+                            unsafeAtomicAdd(a + 2, w * m1);
+                            unsafeAtomicAdd(a + 3, w * m2);
+                            m0 += Ad[0];
+                            m1 += Ad[3];
+                            m2 += Ad[6];
+                        }
+                    }
+            }
+        }
+
+        // ---- flush the box to the dense block grid
+        if (!GLOBAL_ONLY) {
+            __syncthreads();
+            for (int t = tid; t < nt; t += P2G_WG) {
+                const double ws = tq[t];
+                if (ws != 0.0) {
+                    const int tx = t % ext[0], ty = (t / ext[0]) % ext[1], tz = t / (ext[0] * ext[1]);
+                    const int gx = lo[0] + tx, gy = lo[1] + ty, gz = lo[2] + tz;
+                    const int node = (((((gz >> 2) + 1) * P.NB + ((gy >> 2) + 1)) * P.NB + ((gx >> 2) + 1)) << 6) +
+                                     (gx & 3) + ((gy & 3) << 2) + ((gz & 3) << 4);
+                    float* a = acc + 4 * node;
+                    unsafeAtomicAdd(a + 0, (float)(ws * (double)M.mp));
+                    unsafeAtomicAdd(a + 1, (float)tq[CT + t]);
+                    unsafeAtomicAdd(a + 2, (float)tq[2 * CT + t]);
+                    unsafeAtomicAdd(a + 3, (float)tq[3 * CT + t]);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (err) atomicOr(&ctl[CTL_ERROR], (int)err);
+}
+
+}  // namespace
+
+int p2g_grid_size(int cus) {
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_p2g<false>), P2G_WG, 0) !=
+            hipSuccess ||
+        occ <= 0)
+        occ = 1;
+    if (occ > 4) occ = 4;
+    const int g = cus * occ;
+    return g < 8 ? 8 : (g / 8) * 8;
+}
+
+void enqueue_p2g(hipStream_t st, const Launch& L, const Step& P, const Mat& M, float* S, int64_t cap,
+                 const Chunk* chunks, int* ctl, GridBuffers& G, int* brick_state, int pending, int parity,
+                 int global_atomics, int transpose_lanes, int nbricks) {
+    if (global_atomics)
+        hipLaunchKernelGGL(k_p2g<true>, dim3(L.p2g_grid), dim3(P2G_WG), 0, st, S, cap, chunks, ctl, G.acc,
+                           brick_state, G.ovf[parity], parity, P, M, pending, nbricks, transpose_lanes);
+    else
+        hipLaunchKernelGGL(k_p2g<false>, dim3(L.p2g_grid), dim3(P2G_WG), 0, st, S, cap, chunks, ctl, G.acc,
+                           brick_state, G.ovf[parity], parity, P, M, pending, nbricks, transpose_lanes);
+}
+
+}  // namespace mpm

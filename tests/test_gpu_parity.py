@@ -1,0 +1,328 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bars (the same inputs on both sides, generated from seeded scenes):
+  * binning: particle codes, sort permutation, geometric blocks with their
+    ranges and physical blocks are bit-exact;
+  * one substep from a random non-trivial state: every particle field and
+    the grid mass/velocity within 1e-4 normwise relative error
+    (max|gpu - oracle| / max|oracle| per field);
+  * short multi-step runs (20 substeps of the jelly scene) within the same
+    bar, and the analytic free-fall / affine cases within FP32 rounding.
+"""
+import numpy as np
+import pytest
+
+from paper_2111_00699_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.fail("a GPU test ran without a visible GPU")
+    return torch
+
+
+def normwise(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    scale = np.abs(b).max()
+    return np.abs(a - b).max() / (scale if scale > 0 else 1.0)
+
+
+def make_sim(torch_cuda, cfg, **kw):
+    from paper_2111_00699_amd import mpm
+
+    return mpm.Sim(cfg["n"], cfg["dt"], bc=cfg.get("bc", "sticky"), bc_cells=cfg.get("bc_cells", 3),
+                   gravity=cfg.get("gravity", (0.0, -9.8, 0.0)), **kw)
+
+
+def gpu_state(sim):
+    out = sim.read_particles()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def compare_state(gs, os_, kind, tol=TOL, n=None):
+    """Normwise errors per field.  C is measured against max(max|C|, n max|v|):
+    a velocity field that is uniform up to rounding has C = 0 in FP64 while
+    FP32 leaves cancellation noise of order eps |v| / dx, so the scale of C is
+    floored at one velocity unit per cell."""
+    c_scale = np.abs(os_["C"]).max()
+    if n is not None:
+        c_scale = max(c_scale, n * np.abs(os_["v"]).max())
+    errs = {"x": normwise(gs["x"], os_["x"]), "v": normwise(gs["v"], os_["v"]),
+            "C": np.abs(np.asarray(gs["C"], np.float64) - os_["C"]).max() / max(c_scale, 1e-30)}
+    if kind != "water":
+        errs["F"] = normwise(gs["F"], os_["F"])
+    if kind != "jelly":
+        errs["s"] = normwise(gs["s"], os_["s"])
+    bad = {k: e for k, e in errs.items() if not e <= tol}
+    assert not bad, f"normwise errors above {tol}: {bad} (all: {errs})"
+    return errs
+
+
+def print_case(name, **kw):
+    print(f"[case] {name} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+# ------------------------------------------------------------------ binning
+@pytest.mark.parametrize("n,which", [(64, "jelly"), (128, "cloud"), (256, "spheres")])
+def test_binning_is_bit_exact(torch_cuda, oracle, n, which):
+    if which == "jelly":
+        x = scenes.jelly_cube(0)["x"]
+    elif which == "cloud":  # ragged: not a multiple of any tile size
+        x = scenes.uniform(41, 3 * 30001, 0, 0.05, 0.95).reshape(3, -1).astype(np.float32)
+    else:
+        x = scenes.snow_spheres(1, n=n, target=2.0e5, count=6, rmin=0.03, rmax=0.07)["x"]
+    print_case("binning", n=n, which=which, N=x.shape[1])
+    sim = make_sim(torch_cuda, dict(n=n, dt=1e-5))
+    sim.add_particles(scenes.JELLY, x)
+    sim.substep(1)
+    keys, perm = sim.read_binning()
+    blocks = sim.read_blocks()
+    ref = oracle.bin_particles(x, n)
+    assert ref["bad"] == 0
+    assert np.array_equal(keys, ref["sorted"])
+    assert np.array_equal(perm, ref["perm"])
+    assert np.array_equal(blocks["gcode"], ref["gblock"])
+    assert np.array_equal(blocks["gstart"], ref["gstart"])
+    assert np.array_equal(blocks["gcount"], ref["gcount"])
+    assert np.array_equal(blocks["active"], ref["pblock"])
+    sim.close()
+
+
+def test_binning_after_motion_composes(torch_cuda, oracle):
+    """A later rebuild stably sorts the CURRENT (already sorted) order."""
+    sc = scenes.jelly_cube(0)
+    st = scenes.nontrivial_state(sc["x"], seed=7)
+    st["v"] = st["v"] * 40.0  # move several cells
+    cfg = dict(n=64, dt=2e-4, gravity=(0, 0, 0))
+    sim = make_sim(torch_cuda, cfg, flags=0x4)
+    sim.add_particles(dict(scenes.JELLY, E=0.0), st["x"], v=st["v"])
+    sim.substep(10)
+    _, perm0 = sim.read_binning()
+    x_now = gpu_state(sim)["x"].astype(np.float32)
+    sim.rebuild()
+    sim.substep(1)
+    keys1, perm1 = sim.read_binning()
+    # oracle: positions in the previous sorted order, then a stable sort
+    xs = x_now[:, perm0]
+    k, _, _ = oracle.keys(xs, 64)
+    p, srt = oracle.stable_sort(k)
+    assert np.array_equal(keys1, srt)
+    assert np.array_equal(perm1, perm0[p])
+    sim.close()
+
+
+# --------------------------------------------------------- one substep parity
+MATS = {"jelly": (scenes.JELLY, "sticky"), "snow": (scenes.SNOW, "separate"), "water": (scenes.WATER, "slip")}
+
+
+@pytest.mark.parametrize("kind", ["jelly", "snow", "water"])
+@pytest.mark.parametrize("mode", ["tile", "global", "every_step"])
+def test_single_substep_matches_oracle(torch_cuda, oracle, kind, mode):
+    mat, bc = MATS[kind]
+    sc = scenes.jelly_cube(0)
+    st = scenes.nontrivial_state(sc["x"], seed=5, kind=kind)
+    cfg = dict(n=64, dt=1e-4, bc=bc)
+    flags = {"tile": 0, "global": 0x2, "every_step": 0x1}[mode]
+    print_case("substep1", kind=kind, mode=mode, N=st["x"].shape[1])
+    sim = make_sim(torch_cuda, cfg, flags=flags)
+    sim.add_particles(mat, st["x"], v=st["v"], C=st["C"], F=st.get("F"), s=st.get("s"))
+    sim.substep(1)
+    gs = gpu_state(sim)
+    gm, gv = (t.cpu().numpy() for t in sim.read_grid())
+    os_, om, ov, bad = oracle.substep(cfg, mat, st)
+    assert bad == 0
+    compare_state(gs, os_, kind)
+    assert normwise(gm, om) <= TOL
+    assert normwise(gv, ov) <= TOL
+    stats = sim.stats()
+    assert stats["error"] == 0 and stats["rebuilds"] == 1
+    sim.close()
+
+
+def test_ragged_multi_block_substep(torch_cuda, oracle):
+    """30001 particles over many blocks at n=128, small chunks: many partial
+    chunks and tiles, snow with the return map active."""
+    x = scenes.uniform(42, 3 * 30001, 0, 0.1, 0.9).reshape(3, -1).astype(np.float32)
+    st = scenes.nontrivial_state(x, seed=9, kind="snow")
+    cfg = dict(n=128, dt=5e-5, bc="separate")
+    sim = make_sim(torch_cuda, cfg, chunk=64)
+    sim.add_particles(scenes.SNOW, st["x"], v=st["v"], C=st["C"], F=st["F"], s=st["s"])
+    sim.substep(1)
+    gs = gpu_state(sim)
+    os_, om, ov, _ = oracle.substep(cfg, scenes.SNOW, st)
+    compare_state(gs, os_, "snow")
+    sim.close()
+
+
+# --------------------------------------------------------- multi-step runs
+def test_jelly_twenty_substeps(torch_cuda, oracle):
+    sc = scenes.jelly_cube(0)
+    cfg = scenes.jelly_config()
+    st = scenes.nontrivial_state(sc["x"], seed=5)
+    sim = make_sim(torch_cuda, cfg)
+    sim.add_particles(scenes.JELLY, st["x"], v=st["v"], C=st["C"], F=st["F"])
+    sim.substep(20)
+    gs = gpu_state(sim)
+    os_, _, _, _ = oracle.substep(cfg, scenes.JELLY, st, steps=20)
+    compare_state(gs, os_, "jelly")
+    sim.close()
+
+
+def test_free_fall_on_gpu(torch_cuda):
+    sc = scenes.jelly_cube(0)
+    cfg = scenes.jelly_config()
+    sim = make_sim(torch_cuda, cfg)
+    sim.add_particles(scenes.JELLY, sc["x"])
+    steps = 20
+    sim.substep(steps)
+    gs = gpu_state(sim)
+    dt, g = cfg["dt"], -9.8
+    assert np.allclose(gs["v"][1], steps * dt * g, rtol=2e-5, atol=0)
+    assert np.abs(gs["v"][[0, 2]]).max() < 1e-5
+    x0 = sc["x"].astype(np.float64)
+    assert np.abs(gs["x"][1] - (x0[1] + dt * dt * g * steps * (steps + 1) / 2)).max() < 2e-7
+    assert np.abs(gs["C"]).max() < 2e-2  # FP32 cancellation in (4/dx)(M - v f^T)
+    sim.close()
+
+
+def test_affine_field_on_gpu(torch_cuda):
+    n, N = 64, 20000
+    x = scenes.uniform(8, 3 * N, 0, 0.3, 0.7).reshape(3, N).astype(np.float32)
+    a = np.array([0.3, -0.2, 0.1])
+    B = scenes.uniform(8, 9, 1, -2, 2).reshape(3, 3)
+    v = (a[:, None] + B @ x.astype(np.float64)).astype(np.float32)
+    C = np.repeat(B.reshape(9, 1), N, axis=1).astype(np.float32)
+    sim = make_sim(torch_cuda, dict(n=n, dt=1e-4, gravity=(0, 0, 0)))
+    sim.add_particles(dict(scenes.JELLY, E=0.0), x, v=v, C=C)
+    sim.substep(1)
+    gs = gpu_state(sim)
+    assert normwise(gs["v"], v) < 1e-5
+    assert normwise(gs["C"], C) < 1e-3
+    sim.close()
+
+
+def test_mass_and_momentum_on_gpu(torch_cuda, oracle):
+    sc = scenes.jelly_cube(0)
+    st = scenes.nontrivial_state(sc["x"], seed=5)
+    cfg = dict(n=64, dt=1e-4, gravity=(0, 0, 0))
+    sim = make_sim(torch_cuda, cfg)
+    sim.add_particles(scenes.JELLY, st["x"], v=st["v"], C=st["C"], F=st["F"])
+    sim.substep(1)
+    gm, _ = (t.cpu().numpy().astype(np.float64) for t in sim.read_grid())
+    N = st["x"].shape[1]
+    mp = scenes.JELLY["rho"] / 64 ** 3 / 8
+    assert abs(gm.sum() - N * mp) <= 1e-5 * N * mp
+    sim.close()
+
+
+def test_out_of_free_zone_without_rebuild(torch_cuda, oracle):
+    """No rebuild for 40 substeps while particles travel ~5 cells: the
+    overflow path (global atomics + block activation) keeps results exact."""
+    sc = scenes.jelly_cube(0)
+    st = scenes.nontrivial_state(sc["x"], seed=11)
+    st["v"] = (st["v"] * 0.2 + np.array([[4.0], [2.0], [-3.0]])).astype(np.float32)
+    st["C"] = st["C"] * np.float32(0.1)
+    mat = dict(scenes.JELLY, E=100.0)  # soft: elastic CFL 0.32 at this dt
+    cfg = dict(n=64, dt=5e-4, gravity=(0, -9.8, 0))
+    sim = make_sim(torch_cuda, cfg, flags=0x4)
+    sim.add_particles(mat, st["x"], v=st["v"], C=st["C"], F=st["F"])
+    sim.substep(40)  # about 5 cells along x
+    stats = sim.stats()
+    assert stats["rebuilds"] == 1
+    assert stats["overflow_blocks"] > 0
+    gs = gpu_state(sim)
+    os_, _, _, bad = oracle.substep(cfg, mat, st, steps=40)
+    assert bad == 0
+    compare_state(gs, os_, "jelly", tol=2e-4)
+    sim.close()
+
+
+def test_free_zone_triggers_rebuild(torch_cuda):
+    sc = scenes.jelly_cube(0)
+    v = np.zeros_like(sc["x"])
+    v[0] = 3.0
+    sim = make_sim(torch_cuda, dict(n=64, dt=5e-4, gravity=(0, 0, 0)), lag=1)
+    sim.add_particles(dict(scenes.JELLY, E=100.0), sc["x"], v=v)  # elastic CFL 0.32
+    sim.substep(60)  # 3 m/s * 30 ms = 0.09 = 5.8 cells
+    sim.synchronize()
+    stats = sim.stats()
+    assert 2 <= stats["rebuilds"] <= 4, stats
+    sim.close()
+
+
+# ------------------------------------------------------- particle sources
+def test_emission_between_substeps(torch_cuda, oracle):
+    """Fountain-style: particles added between substeps (the deferred
+    deformation update of the old particles is landed first)."""
+    cfg = dict(n=128, dt=1e-4, bc="separate")
+    e0 = scenes.fountain_emission(0)
+    e1 = scenes.fountain_emission(1)
+    e1["x"] = e1["x"] + np.float32(0.2)
+    sim = make_sim(torch_cuda, cfg, capacity=1024)
+    sim.add_particles(scenes.WATER, e0["x"], v=e0["v"])
+    sim.substep(3)
+    sim.add_particles(None, e1["x"], v=e1["v"])
+    sim.substep(2)
+    gs = gpu_state(sim)
+    assert sim.stats()["capacity"] >= 2 * (e0["x"].shape[1] + e1["x"].shape[1])
+    s0, _, _, _ = oracle.substep(cfg, scenes.WATER, e0, steps=3)
+    both = {k: np.concatenate([s0[k], oracle._state(e1)[k]], axis=-1) for k in ("x", "v", "C", "F", "s")}
+    s1, _, _, _ = oracle.substep(cfg, scenes.WATER, both, steps=2)
+    compare_state(gs, s1, "water", n=cfg["n"])
+    sim.close()
+
+
+# ------------------------------------------------------------- fault words
+def test_invalid_particles_raise_state_error(torch_cuda):
+    from paper_2111_00699_amd import mpm
+
+    x = scenes.jelly_cube(0)["x"].copy()
+    x[0, 5] = np.nan
+    x[1, 7] = 1.5
+    sim = make_sim(torch_cuda, dict(n=64, dt=1e-4))
+    sim.add_particles(scenes.JELLY, x)
+    sim.substep(2)
+    with pytest.raises(mpm.MPMError) as e:
+        sim.read_particles()
+    assert e.value.code == mpm.ESTATE
+    st = sim.stats(check=False)
+    assert st["error"] & mpm.ERR_NONFINITE and st["error"] & mpm.ERR_DOMAIN
+    sim.clear_error()
+    assert sim.stats()["error"] == 0
+    sim.close()
+
+
+def test_binding_rejects_bad_arguments(torch_cuda):
+    from paper_2111_00699_amd import mpm
+
+    sim = make_sim(torch_cuda, dict(n=64, dt=1e-4))
+    x = scenes.jelly_cube(0)["x"]
+    with pytest.raises(mpm.MPMError):
+        sim.add_particles(None, x)  # first call needs a material
+    sim.add_particles(scenes.JELLY, x)
+    with pytest.raises(mpm.MPMError):
+        sim.add_particles(scenes.SNOW, x)  # one material per context
+    with pytest.raises(mpm.MPMError):
+        sim.substep(-1)
+    sim.close()
+
+
+def test_profile_counts_launches(torch_cuda):
+    sc = scenes.jelly_cube(0)
+    sim = make_sim(torch_cuda, scenes.jelly_config())
+    sim.add_particles(scenes.JELLY, sc["x"])
+    sim.profile(0xF)
+    sim.substep(5)
+    prof = sim.profile_read()
+    assert prof["p2g"]["launches"] == 5 and prof["g2p"]["launches"] == 5 and prof["grid"]["launches"] == 5
+    assert prof["rebuild"]["launches"] == 1
+    assert all(prof[k]["ms"] > 0 for k in ("p2g", "grid", "g2p"))
+    sim.close()
