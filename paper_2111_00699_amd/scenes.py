@@ -188,3 +188,29 @@ def jelly_config(n: int = 64) -> dict:
 def fountain_config(n: int = 128) -> dict:
     ns, dt = frame_substeps(1e-4)
     return dict(n=n, bc="separate", bc_cells=3, gravity=(0.0, -9.8, 0.0), dt=dt, substeps_per_frame=ns)
+
+
+# ------------------------------------------------------------ surrogate inputs
+MLP_LAYERS = (12, 64, 64, 12)
+
+
+def mlp_init(seed: int = 4) -> np.ndarray:
+    """Seeded initial parameters of the 12-64-64-12 surrogate network as one
+    flat FP32 vector [W1 (64x12), b1, W2 (64x64), b2, W3 (12x64), b3]: weights
+    uniform in +-sqrt(6/(fan_in + fan_out)) (Glorot), biases zero."""
+    parts = []
+    for k, (a, b) in enumerate(zip(MLP_LAYERS[:-1], MLP_LAYERS[1:])):
+        lim = np.sqrt(6.0 / (a + b))
+        parts.append(uniform(seed, a * b, 500 + k, -lim, lim))
+        parts.append(np.zeros(b))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def snow_trial_states(seed: int, count: int, spread: float = 0.02) -> dict:
+    """Seeded trial states for the snow map in principal space: singular values
+    1 + U(-spread, spread) and plastic volumes J_P ~ U(0.85, 1.1).  With the
+    default spread about two thirds of the samples lie outside
+    [1 - 2.5e-2, 1 + 7.5e-3] on some axis, so the clamp is exercised."""
+    s = 1.0 + uniform(seed, 3 * count, 600, -spread, spread).reshape(count, 3)
+    jp = uniform(seed, count, 601, 0.85, 1.1)
+    return {"sig_hat": s, "Jp": jp}

@@ -8,6 +8,7 @@ closed forms of the constitutive laws, Python's stable sort, set algebra for
 the blocks, and the free-zone sizes printed in the paper).
 """
 import os
+import sys
 
 import numpy as np
 import pytest

@@ -1,0 +1,86 @@
+"""Pins of the FP64 surrogate oracle (MLP, Adam, principal-space snow map)."""
+import numpy as np
+
+from oracle import surrogate as S
+from paper_2111_00699_amd import scenes
+
+
+def test_parameter_count_matches_the_configuration():
+    # 12*64 + 64 + 64*64 + 64 + 64*12 + 12
+    assert S.num_params() == 5772
+    assert scenes.mlp_init(4).size == 5772
+
+
+def test_gradient_matches_central_differences():
+    theta = scenes.mlp_init(7).astype(np.float64)
+    theta += scenes.uniform(7, theta.size, 9, -0.05, 0.05)  # non-zero biases too
+    X = scenes.uniform(7, 5 * 12, 1, -1, 1).reshape(5, 12)
+    T = scenes.uniform(7, 5 * 12, 2, -1, 1).reshape(5, 12)
+    g = S.grad(theta, X, T)
+    idx = np.linspace(0, theta.size - 1, 160).astype(int)
+    h = 1e-6
+    for i in idx:
+        e = np.zeros_like(theta)
+        e[i] = h
+        fd = (S.loss(theta + e, X, T) - S.loss(theta - e, X, T)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 + 1e-5 * abs(fd), (i, fd, g[i])
+
+
+def test_forward_of_a_linear_regime_network():
+    """With tiny weights tanh is linear to first order: Y ~ W3 W2 W1 x."""
+    theta = scenes.mlp_init(3).astype(np.float64) * 1e-3
+    W1, b1, W2, b2, W3, b3 = S.unflatten(theta)
+    X = scenes.uniform(3, 4 * 12, 0, -1, 1).reshape(4, 12)
+    Y, _ = S.forward(theta, X)
+    lin = X @ (W3 @ W2 @ W1).T
+    assert np.allclose(Y, lin, rtol=1e-5, atol=1e-14)
+
+
+def test_adam_first_step_is_a_signed_learning_rate_step():
+    theta = np.array([0.5, -0.25, 2.0])
+    g = np.array([3.0, -0.1, 1e-3])
+    t1, m, v = S.adam_step(theta, g, np.zeros(3), np.zeros(3), 1, lr=0.01)
+    assert np.allclose(t1, theta - 0.01 * np.sign(g), atol=1e-7)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_adam_descends_a_small_regression():
+    theta = scenes.mlp_init(11).astype(np.float64)
+    X = scenes.uniform(11, 64 * 12, 1, -1, 1).reshape(64, 12)
+    T = np.tanh(X[:, ::-1]) * 0.5
+    m = np.zeros_like(theta)
+    v = np.zeros_like(theta)
+    l0 = S.loss(theta, X, T)
+    for t in range(1, 201):
+        theta, m, v = S.adam_step(theta, S.grad(theta, X, T), m, v, t, lr=3e-3)
+    assert S.loss(theta, X, T) < 0.2 * l0
+
+
+def test_principal_map_matches_the_svd_oracle(oracle):
+    mat = scenes.SNOW
+    from tests.test_oracle_pins import rot  # seeded rotations
+
+    for i in range(60):
+        s = scenes.uniform(80, 3, i, 0.95, 1.04)
+        F = rot(1300 + i) @ np.diag(s) @ rot(1400 + i).T
+        jp = 0.9 + 0.002 * i
+        Fe, jp_new = oracle.snow_project(mat, F, jp)
+        sn, jpn, tau = S.snow_principal(mat, s[None], np.array([jp]))
+        assert np.allclose(np.sort(np.linalg.svd(Fe, compute_uv=False)), np.sort(sn[0]), atol=1e-12)
+        assert abs(jpn[0] - jp_new) < 1e-12
+        # principal stress = eigenvalues of the world-frame stress of the projected state
+        ev = np.linalg.eigvalsh(oracle.stress(mat, Fe, jp_new))
+        assert np.allclose(np.sort(ev), np.sort(tau[0]), rtol=1e-9, atol=1e-6)
+
+
+def test_targets_conserve_volume_and_vanish_inside_the_yield_surface():
+    mat = scenes.SNOW
+    st = scenes.snow_trial_states(5, 4000)
+    X = S.features(mat, st["sig_hat"], st["Jp"], 1.0, 1.0)
+    Y = S.targets(mat, st["sig_hat"], st["Jp"])
+    assert np.allclose(Y[:, 11] * Y[:, 9] * st["Jp"], X[:, 10] * st["Jp"], rtol=1e-12)
+    lo, hi = 1 - mat["theta_c"], 1 + mat["theta_s"]
+    inside = np.all((X[:, 0:3] >= lo) & (X[:, 0:3] <= hi), axis=1)
+    assert 0.2 < inside.mean() < 0.8
+    assert np.allclose(Y[inside, 3:6], 0) and np.allclose(Y[inside, 9], 1)
+    assert np.all(Y[:, 0:3] >= lo - 1e-15) and np.all(Y[:, 0:3] <= hi + 1e-15)
