@@ -62,12 +62,24 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--flags", type=int, default=0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 4 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
 
     import torch
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read_per_launch": src.numel() * 4,
+                          "bytes_written_per_launch": dst.numel() * 4, "launches": 4}))
+        return
 
     from paper_2111_00699_amd import mpm, scenes
 
@@ -127,7 +139,7 @@ def main():
                                "hardening, 334 substeps of 4.99e-5 s per 1/60 s frame",
                    "particles": N, "grid": cfg["n"], "substeps_per_frame": nsub, "frames_timed": args.steps,
                    "rebuilds_in_timed_frames": rebuilds,
-                   "substeps_per_rebuild": substeps / max(rebuilds, 1), "chunk": args.chunk or 512},
+                   "substeps_per_rebuild": substeps / max(rebuilds, 1), "chunk": args.chunk or 256},
         "roofline": {"kernel": "p2g", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None if P2G_TRAFFIC_BYTES is None else P2G_TRAFFIC_BYTES,

@@ -66,8 +66,10 @@ typedef enum { MPM_BC_STICKY = 0, MPM_BC_SLIP = 1, MPM_BC_SEPARATE = 2 } mpm_bc;
 #define MPM_FLAG_MANUAL_REBUILD 0x4u     /* ignore the free-zone flag: rebuild only after mpm_add_particles
                                             or mpm_rebuild (particles outside their free zone still
                                             transfer exactly, through global atomics) */
-#define MPM_FLAG_P2G_SORTED_LANES 0x8u   /* P2G lanes take chunk particles in sorted order instead of
-                                            the transposed order that spreads a wave over cells */
+#define MPM_FLAG_G2P_GLOBAL_GATHER 0x10u /* G2P gathers every node from the dense grid instead of an LDS
+                                            copy of the chunk's node box */
+#define MPM_FLAG_P2G_SORTED_LANES 0x8u   /* store each chunk in plain sorted order instead of the
+                                            strided order that spreads a wave over cells */
 
 typedef struct {
     int32_t n;          /* cells per axis on the unit cube; power of two, 16 <= n <= 512; dx = 1/n */
@@ -81,7 +83,7 @@ typedef struct {
     uint32_t flags;     /* MPM_FLAG_* */
     int32_t lag;        /* substeps the host may run ahead of the device before it must read the
                            rebuild flag (1..64; 0 selects the default 3) */
-    int32_t chunk;      /* particles per P2G/G2P work chunk: 64..512, multiple of 64 (0 = 512) */
+    int32_t chunk;      /* particles per P2G/G2P work chunk: 64..512, multiple of 64 (0 = 256) */
     int32_t reserved;
 } mpm_config;
 
@@ -170,7 +172,13 @@ int mpm_read_grid(mpm_ctx* ctx, int32_t scene, float* m_dev, float* v_dev);
 
 /* The binning of the last rebuild: keys_dev[count] the sorted particle
  * codes and perm_dev[count] the insertion index of the particle at each
- * sorted position.  count must equal the number of particles.  Synchronizes. */
+ * sorted position (a stable sort: ties keep their storage order before the
+ * rebuild).  Storage layout after a rebuild: geometric blocks in code order,
+ * each cut into chunks of config.chunk particles; inside a chunk of c
+ * particles, slot t holds sorted position (t*K) mod c with K the smallest of
+ * 9, 11, 13, 17 coprime to c (identity with MPM_FLAG_P2G_SORTED_LANES).
+ * count must equal the number of particles at the last rebuild.
+ * Synchronizes.                                                             */
 int mpm_read_binning(mpm_ctx* ctx, int32_t scene, int64_t count, uint32_t* keys_dev, int32_t* perm_dev);
 
 /* Blocks of the last rebuild (host arrays, sized by mpm_get_stats):

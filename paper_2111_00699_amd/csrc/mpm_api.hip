@@ -137,6 +137,13 @@ void free_particle_buffers(mpm_ctx* c) {
     (void)hipFree(c->B.gstart);
     (void)hipFree(c->B.gcode);
     (void)hipFree(c->B.chunks);
+    (void)hipFree(c->B.gchunk);
+    (void)hipFree(c->B.sorted_ids);
+    (void)hipFree(c->G.stage);
+    (void)hipFree(c->G.box);
+    c->B.gchunk = c->B.sorted_ids = nullptr;
+    c->G.stage = nullptr;
+    c->G.box = nullptr;
     c->B.hist = c->B.scan_tiles = c->B.gstart = nullptr;
     c->B.gcode = nullptr;
     c->B.chunks = nullptr;
@@ -150,6 +157,9 @@ int grow(mpm_ctx* c, int64_t newcap) {
     int *hist = nullptr, *tiles = nullptr, *gstart = nullptr;
     uint32_t* gcode = nullptr;
     Chunk* chunks = nullptr;
+    int *gchunk = nullptr, *sorted_ids = nullptr;
+    float4* stage = nullptr;
+    int2* box = nullptr;
     const int64_t rs_tiles = (newcap + 4095) / 4096;
     bool ok = true;
     for (int i = 0; i < 2 && ok; ++i) {
@@ -163,6 +173,10 @@ int grow(mpm_ctx* c, int64_t newcap) {
     ok = ok && hipMalloc(&gstart, sizeof(int) * (newcap + 1)) == hipSuccess;
     ok = ok && hipMalloc(&gcode, sizeof(uint32_t) * (newcap + 1)) == hipSuccess;
     ok = ok && hipMalloc(&chunks, sizeof(Chunk) * (newcap + 1)) == hipSuccess;
+    ok = ok && hipMalloc(&gchunk, sizeof(int) * (newcap + 2)) == hipSuccess;
+    ok = ok && hipMalloc(&sorted_ids, sizeof(int) * newcap) == hipSuccess;
+    ok = ok && hipMalloc(&stage, sizeof(float4) * 27 * newcap) == hipSuccess;
+    ok = ok && hipMalloc(&box, sizeof(int2) * (newcap + 1)) == hipSuccess;
     if (!ok) {
         for (int i = 0; i < 2; ++i) {
             (void)hipFree(S[i]);
@@ -175,6 +189,10 @@ int grow(mpm_ctx* c, int64_t newcap) {
         (void)hipFree(gstart);
         (void)hipFree(gcode);
         (void)hipFree(chunks);
+        (void)hipFree(gchunk);
+        (void)hipFree(sorted_ids);
+        (void)hipFree(stage);
+        (void)hipFree(box);
         (void)hipGetLastError();
         return fail(c, MPM_ENOMEM, "particle buffer allocation failed for capacity " + std::to_string(newcap));
     }
@@ -183,6 +201,7 @@ int grow(mpm_ctx* c, int64_t newcap) {
                                    sizeof(float) * c->N, NF, hipMemcpyDeviceToDevice, c->stream));
         HIP_OK(c, hipMemcpyAsync(ids[0], c->ids[c->cur], sizeof(int) * c->N, hipMemcpyDeviceToDevice, c->stream));
     }
+    HIP_OK(c, hipMemsetAsync(box, 0, sizeof(int2) * (newcap + 1), c->stream));
     HIP_OK(c, hipStreamSynchronize(c->stream));
     free_particle_buffers(c);
     for (int i = 0; i < 2; ++i) {
@@ -196,6 +215,10 @@ int grow(mpm_ctx* c, int64_t newcap) {
     c->B.gstart = gstart;
     c->B.gcode = gcode;
     c->B.chunks = chunks;
+    c->B.gchunk = gchunk;
+    c->B.sorted_ids = sorted_ids;
+    c->G.stage = stage;
+    c->G.box = box;
     c->cur = 0;
     c->cap = newcap;
     c->need_rebuild = true;
@@ -298,7 +321,7 @@ int mpm_create(const mpm_config* cfg, mpm_ctx** out) {
     mpm_ctx* c = new mpm_ctx();
     c->cfg = *cfg;
     if (c->cfg.lag == 0) c->cfg.lag = 3;
-    if (c->cfg.chunk == 0) c->cfg.chunk = 512;
+    if (c->cfg.chunk == 0) c->cfg.chunk = 256;
     c->stream = reinterpret_cast<hipStream_t>(cfg->stream);
     (void)hipGetDevice(&c->device);
     c->P.n = n;
@@ -312,7 +335,7 @@ int mpm_create(const mpm_config* cfg, mpm_ctx** out) {
     c->P.bc = cfg->bc;
     c->P.bc_cells = cfg->bc_cells;
     c->nbricks = c->P.NB * c->P.NB * c->P.NB;
-    query_launch(c->L);
+    query_launch(c->L, c->cfg.chunk);
 
     auto bail = [&](int code) {
         std::string msg = c->err;
@@ -327,6 +350,7 @@ int mpm_create(const mpm_config* cfg, mpm_ctx** out) {
               hipMalloc(&c->G.ovf[1], sizeof(int) * nb) == hipSuccess &&
               hipMalloc(&c->B.brick_state, sizeof(int) * nb) == hipSuccess &&
               hipMalloc(&c->B.active, sizeof(int) * nb) == hipSuccess &&
+              hipMalloc(&c->B.gindex, sizeof(int) * nb) == hipSuccess &&
               hipMalloc(&c->ctl, sizeof(int) * CTL_WORDS) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
@@ -372,6 +396,7 @@ int mpm_destroy(mpm_ctx* c) {
     (void)hipFree(c->G.ovf[1]);
     (void)hipFree(c->B.brick_state);
     (void)hipFree(c->B.active);
+    (void)hipFree(c->B.gindex);
     (void)hipFree(c->ctl);
     if (c->ring) (void)hipHostFree(c->ring);
     for (int i = 0; i < RING; ++i)
@@ -434,7 +459,8 @@ int mpm_substep(mpm_ctx* c, int32_t nsteps) {
             int slot;
             if ((r = prof_begin(c, 0, &slot))) return r;
             enqueue_rebuild(c->stream, c->P, c->S[c->cur], c->S[c->cur ^ 1], c->ids[c->cur], c->ids[c->cur ^ 1],
-                            c->cap, N, c->cfg.chunk, c->B, c->ctl, c->nbricks);
+                            c->cap, N, c->cfg.chunk, (c->cfg.flags & MPM_FLAG_P2G_SORTED_LANES) ? 0 : 1, c->B,
+                            c->ctl, c->nbricks);
             if ((r = prof_end(c, slot))) return r;
             c->cur ^= 1;
             c->need_rebuild = false;
@@ -448,14 +474,15 @@ int mpm_substep(mpm_ctx* c, int32_t nsteps) {
         int slot;
         if ((r = prof_begin(c, 1, &slot))) return r;
         enqueue_p2g(c->stream, c->L, c->P, c->M, c->S[c->cur], c->cap, c->B.chunks, c->ctl, c->G, c->B.brick_state,
-                    c->pending, parity, (c->cfg.flags & MPM_FLAG_P2G_GLOBAL_ATOMICS) ? 1 : 0,
-                    (c->cfg.flags & MPM_FLAG_P2G_SORTED_LANES) ? 0 : 1, c->nbricks);
+                    c->pending, parity, (c->cfg.flags & MPM_FLAG_P2G_GLOBAL_ATOMICS) ? 1 : 0, c->nbricks,
+                    c->cfg.chunk);
         if ((r = prof_end(c, slot))) return r;
         if ((r = prof_begin(c, 2, &slot))) return r;
-        enqueue_grid(c->stream, c->L, c->P, c->B.active, c->ctl, c->G, c->B.brick_state, parity, (int)c->step);
+        enqueue_grid(c->stream, c->L, c->P, c->B, c->ctl, c->G, parity, (int)c->step);
         if ((r = prof_end(c, slot))) return r;
         if ((r = prof_begin(c, 3, &slot))) return r;
-        enqueue_g2p(c->stream, c->L, c->P, c->S[c->cur], c->cap, c->B.chunks, c->ctl, c->G, c->ring_dev + rs);
+        enqueue_g2p(c->stream, c->L, c->P, c->S[c->cur], c->cap, c->B.chunks, c->ctl, c->G, c->ring_dev + rs,
+                    (c->cfg.flags & MPM_FLAG_G2P_GLOBAL_GATHER) ? 0 : 1);
         if ((r = prof_end(c, slot))) return r;
         HIP_OK(c, hipGetLastError());
         HIP_OK(c, hipEventRecord(c->ev[rs], c->stream));
@@ -512,7 +539,7 @@ int mpm_read_binning(mpm_ctx* c, int32_t scene, int64_t count, uint32_t* keys, i
         HIP_OK(c, hipMemcpyAsync(keys, c->B.keys[c->B.sorted], sizeof(uint32_t) * count, hipMemcpyDeviceToDevice,
                                  c->stream));
     if (perm)
-        HIP_OK(c, hipMemcpyAsync(perm, c->ids[c->cur], sizeof(int32_t) * count, hipMemcpyDeviceToDevice, c->stream));
+        HIP_OK(c, hipMemcpyAsync(perm, c->B.sorted_ids, sizeof(int32_t) * count, hipMemcpyDeviceToDevice, c->stream));
     return check_error_word(c);
 }
 

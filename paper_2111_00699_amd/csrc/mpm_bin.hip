@@ -231,6 +231,7 @@ struct OpChunks {
     const int* ctl;
     int N, chunk;
     Chunk* out;
+    int* gchunk;
     __device__ int len(int g) const {
         const int ng = ctl[CTL_NGB];
         const int end = (g + 1 < ng) ? gstart[g + 1] : N;
@@ -244,6 +245,7 @@ struct OpChunks {
         const uint32_t code = gcode[g];
         const int packed = (int)(compact3(code) | (compact3(code >> 1) << 10) | (compact3(code >> 2) << 20));
         const int s0 = gstart[g], l = len(g);
+        gchunk[g] = off;
         for (int i = 0; i < k; ++i) {
             Chunk c;
             c.start = s0 + i * chunk;
@@ -263,15 +265,30 @@ struct OpActive {
 };
 
 // ------------------------------------------------------------ data movement
-__global__ __launch_bounds__(WG) void k_permute(const float* __restrict__ Sin, float* __restrict__ Sout,
-                                                const int* __restrict__ idin, int* __restrict__ idout,
-                                                const uint32_t* __restrict__ src, int64_t cap, int N) {
-    const int j = blockIdx.x * WG + threadIdx.x;
-    if (j >= N) return;
-    const int k = (int)src[j];
+// Gather the whole particle state into sorted order, chunk by chunk; inside a
+// chunk, storage slot t takes sorted position (t * K) mod count (see
+// chunk_stride) unless `spread` is 0.  Also records the insertion ids in
+// plain sorted order for the binning view.
+__global__ __launch_bounds__(WG) void k_permute_chunks(const float* __restrict__ Sin, float* __restrict__ Sout,
+                                                       const int* __restrict__ idin, int* __restrict__ idout,
+                                                       int* __restrict__ sorted_ids, const uint32_t* __restrict__ src,
+                                                       const Chunk* __restrict__ chunks, const int* __restrict__ ctl,
+                                                       int64_t cap, int spread) {
+    const int nch = ctl[CTL_NCHUNK];
+    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+        const Chunk ch = chunks[c];
+        const int K = spread ? chunk_stride(ch.count) : 1;
+        for (int t = threadIdx.x; t < ch.count; t += WG) {
+            const int j = ch.start + (t * K) % ch.count;  // sorted position
+            const int k = (int)src[j];                     // its position before the sort
+            const int dst = ch.start + t;
 #pragma unroll
-    for (int f = 0; f < NF; ++f) Sout[f * cap + j] = Sin[f * cap + k];
-    idout[j] = idin[k];
+            for (int f = 0; f < NF; ++f) Sout[f * cap + dst] = Sin[f * cap + k];
+            const int id = idin[k];
+            idout[dst] = id;
+            sorted_ids[j] = id;
+        }
+    }
 }
 
 __global__ __launch_bounds__(WG) void k_fill(int* __restrict__ p, int v, int n) {
@@ -279,26 +296,32 @@ __global__ __launch_bounds__(WG) void k_fill(int* __restrict__ p, int v, int n) 
     if (i < n) p[i] = v;
 }
 
-// Mark the 3x3x3 neighbourhood of every geometric block as physical.
+// Mark the 3x3x3 neighbourhood of every geometric block as physical and
+// record each geometric block's index at its own (padded) position.
 __global__ __launch_bounds__(WG) void k_dilate(const uint32_t* __restrict__ gcode, const int* __restrict__ ctl,
-                                               int NB, int* __restrict__ state) {
+                                               int NB, int* __restrict__ state, int* __restrict__ gindex) {
     const int total = ctl[CTL_NGB] * 27;
     for (int t = blockIdx.x * WG + threadIdx.x; t < total; t += gridDim.x * WG) {
         const int g = t / 27, o = t % 27;
         const uint32_t code = gcode[g];
-        const int bx = (int)compact3(code) + (o % 3);  // (B - 1) + o + 1 in padded coordinates
-        const int by = (int)compact3(code >> 1) + (o / 3) % 3;
-        const int bz = (int)compact3(code >> 2) + o / 9;
+        const int B0 = (int)compact3(code), B1 = (int)compact3(code >> 1), B2 = (int)compact3(code >> 2);
+        const int bx = B0 + (o % 3);  // (B - 1) + o + 1 in padded coordinates
+        const int by = B1 + (o / 3) % 3;
+        const int bz = B2 + o / 9;
         state[(bz * NB + by) * NB + bx] = 1;
+        if (o == 13) gindex[(bz * NB + by) * NB + bx] = g;  // o = (1,1,1): the block itself
     }
 }
 
-__global__ void k_clear_rebuild(int* ctl) { ctl[CTL_REBUILD] = 0; }
+__global__ void k_finish_rebuild(int* ctl, int* gchunk) {
+    ctl[CTL_REBUILD] = 0;
+    gchunk[ctl[CTL_NGB]] = ctl[CTL_NCHUNK];
+}
 
 }  // namespace
 
 void enqueue_rebuild(hipStream_t st, const Step& P, float* S_cur, float* S_alt, int* id_cur, int* id_alt, int64_t cap,
-                     int N, int chunk, BinBuffers& B, int* ctl, int nbricks) {
+                     int N, int chunk, int spread, BinBuffers& B, int* ctl, int nbricks) {
     const int nb = cdiv(N > 0 ? N : 1, WG);
     // 1. particle codes
     hipLaunchKernelGGL(k_keys, dim3(nb), dim3(WG), 0, st, S_cur, cap, N, P.fn, P.n, B.keys[0], B.vals[0], ctl);
@@ -316,16 +339,19 @@ void enqueue_rebuild(hipStream_t st, const Step& P, float* S_cur, float* S_alt, 
         cur ^= 1;
     }
     B.sorted = cur;  // slot holding the sorted codes and their source positions
-    // 3. gather the whole particle state into sorted order
-    hipLaunchKernelGGL(k_permute, dim3(nb), dim3(WG), 0, st, S_cur, S_alt, id_cur, id_alt, B.vals[cur], cap, N);
-    // 4. geometric blocks and work chunks
+    // 3. geometric blocks and work chunks
     device_scan(st, OpGBlocks{B.keys[cur], N, B.gstart, B.gcode}, N, B.scan_tiles, ctl + CTL_NGB);
-    device_scan(st, OpChunks{B.gstart, B.gcode, ctl, N, chunk, B.chunks}, N, B.scan_tiles, ctl + CTL_NCHUNK);
+    device_scan(st, OpChunks{B.gstart, B.gcode, ctl, N, chunk, B.chunks, B.gchunk}, N, B.scan_tiles,
+                ctl + CTL_NCHUNK);
+    // 4. gather the whole particle state into (chunk-spread) sorted order
+    hipLaunchKernelGGL(k_permute_chunks, dim3(2048), dim3(WG), 0, st, S_cur, S_alt, id_cur, id_alt, B.sorted_ids,
+                       B.vals[cur], B.chunks, ctl, cap, spread);
     // 5. physical blocks: 3x3x3 dilation, compacted in padded linear order
     hipLaunchKernelGGL(k_fill, dim3(cdiv(nbricks, WG)), dim3(WG), 0, st, B.brick_state, 0, nbricks);
-    hipLaunchKernelGGL(k_dilate, dim3(512), dim3(WG), 0, st, B.gcode, ctl, P.NB, B.brick_state);
+    hipLaunchKernelGGL(k_fill, dim3(cdiv(nbricks, WG)), dim3(WG), 0, st, B.gindex, -1, nbricks);
+    hipLaunchKernelGGL(k_dilate, dim3(512), dim3(WG), 0, st, B.gcode, ctl, P.NB, B.brick_state, B.gindex);
     device_scan(st, OpActive{B.brick_state, B.active}, nbricks, B.scan_tiles, ctl + CTL_NACTIVE);
-    hipLaunchKernelGGL(k_clear_rebuild, dim3(1), dim3(1), 0, st, ctl);
+    hipLaunchKernelGGL(k_finish_rebuild, dim3(1), dim3(1), 0, st, ctl, B.gchunk);
 }
 
 }  // namespace mpm

@@ -68,11 +68,22 @@ struct BinBuffers {
     Chunk* chunks;     // [cap]
     int* brick_state;  // [NB^3] 0 idle, 1 physical block of the rebuild, 2 overflow this substep
     int* active;       // [NB^3]
+    int* gindex;       // [NB^3] geometric-block index of each particle block (padded coords), -1 if none
+    int* gchunk;       // [cap + 1] first chunk of each geometric block
+    int* sorted_ids;   // [cap] insertion id of each particle in particle-code order
     int sorted;        // which keys/vals slot holds the last sorted codes (host side)
 };
 
+// Within a chunk, storage slot t holds sorted position (t * K) mod count, K
+// the smallest of 9, 11, 13, 17 coprime to count (so a permutation; count <=
+// 512 < 3*11*13*17 guarantees one): 64 consecutive slots -- one wave -- then
+// sit about one cell apart.
+__host__ __device__ inline int chunk_stride(int count) {
+    return (count % 3) ? 9 : (count % 11) ? 11 : (count % 13) ? 13 : 17;
+}
+
 void enqueue_rebuild(hipStream_t st, const Step& P, float* S_cur, float* S_alt, int* id_cur, int* id_alt,
-                     int64_t cap, int N, int chunk, BinBuffers& B, int* ctl, int nbricks);
+                     int64_t cap, int N, int chunk, int spread, BinBuffers& B, int* ctl, int nbricks);
 
 // Substep kernels (mpm_step.hip).
 struct GridBuffers {
@@ -80,6 +91,8 @@ struct GridBuffers {
     float4* vel;    // [NB^3 * 64] (vx, vy, vz, m) after the grid update
     int* stamp;     // [NB^3] substep index of the last update of each block
     int* ovf[2];    // overflow block lists, by substep parity
+    float4* stage;  // [27 * cap] P2G tile of each chunk, (m, px, py, pz) per node, slot at 27 * chunk.start
+    int2* box;      // [cap] tile box of each chunk: lo packed 10 bits/axis, ext packed 8 bits/axis (0 = none)
 };
 
 struct Launch {
@@ -88,19 +101,19 @@ struct Launch {
 
 void enqueue_p2g(hipStream_t st, const Launch& L, const Step& P, const Mat& M, float* S, int64_t cap,
                  const Chunk* chunks, int* ctl, GridBuffers& G, int* brick_state, int pending, int parity,
-                 int global_atomics, int transpose_lanes, int nbricks);
-int p2g_grid_size(int cus);
-void enqueue_grid(hipStream_t st, const Launch& L, const Step& P, const int* active, int* ctl, GridBuffers& G,
-                  int* brick_state, int parity, int step);
+                 int global_atomics, int nbricks, int chunk);
+int p2g_grid_size(int cus, int chunk);
+void enqueue_grid(hipStream_t st, const Launch& L, const Step& P, const BinBuffers& B, int* ctl, GridBuffers& G,
+                  int parity, int step);
 void enqueue_g2p(hipStream_t st, const Launch& L, const Step& P, float* S, int64_t cap, const Chunk* chunks,
-                 int* ctl, const GridBuffers& G, int* host_flag);
+                 int* ctl, const GridBuffers& G, int* host_flag, int lds_box);
 void enqueue_materialize(hipStream_t st, const Step& P, const Mat& M, float* S, int64_t cap, int N);
 void enqueue_insert(hipStream_t st, float* S, int* ids, int64_t cap, int N0, int count, const float* x,
                     const float* v, const float* C, const float* F, const float* s, int* ctl);
 void enqueue_read(hipStream_t st, const Step& P, const Mat& M, const float* S, const int* ids, int64_t cap, int N,
                   int pending, float* x, float* v, float* C, float* F, float* s);
 void enqueue_read_grid(hipStream_t st, const Step& P, const GridBuffers& G, int step, float* m, float* v);
-void query_launch(Launch& L);
+void query_launch(Launch& L, int chunk);
 
 // ----------------------------------------------------------- device math
 __device__ __forceinline__ uint32_t spread3(uint32_t v) {  // 10 low bits -> every third bit
@@ -127,7 +140,7 @@ __device__ __forceinline__ void jacobi_rotate(float& app, float& aqq, float& apq
                                               float& u0q, float& u1p, float& u1q, float& u2p, float& u2q) {
     const float d = aqq - app;
     const float den = fabsf(d) + sqrtf(d * d + 4.0f * apq * apq);
-    const float t = den > 0.0f ? (d >= 0.0f ? 2.0f * apq : -2.0f * apq) / den : 0.0f;
+    const float t = den > 0.0f ? __fdividef(d >= 0.0f ? 2.0f * apq : -2.0f * apq, den) : 0.0f;
     const float c = rsqrtf(1.0f + t * t);
     const float s = t * c;
     app -= t * apq;
@@ -149,7 +162,7 @@ __device__ __forceinline__ void eig_sym3(float b00, float b01, float b02, float 
                                          float lam[3]) {
     float u00 = 1, u01 = 0, u02 = 0, u10 = 0, u11 = 1, u12 = 0, u20 = 0, u21 = 0, u22 = 1;
 #pragma unroll
-    for (int sweep = 0; sweep < 4; ++sweep) {
+    for (int sweep = 0; sweep < 3; ++sweep) {  // quadratic convergence: 3 sweeps reach FP32 rounding
         jacobi_rotate(b00, b11, b01, b02, b12, u00, u01, u10, u11, u20, u21);  // (0,1), r = 2
         jacobi_rotate(b00, b22, b02, b01, b12, u00, u02, u10, u12, u20, u22);  // (0,2), r = 1
         jacobi_rotate(b11, b22, b12, b01, b02, u01, u02, u11, u12, u21, u22);  // (1,2), r = 0
@@ -238,7 +251,7 @@ __device__ __forceinline__ void material_step(const Mat& M, float dt, int pendin
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 sc[k] = fminf(fmaxf(sig[k], M.lo), M.hi);
-                r[k] = sc[k] / sig[k];
+                r[k] = __fdividef(sc[k], sig[k]);
             }
             float R[6];
             sym_from_eig(U, r[0], r[1], r[2], R);  // F_E' = U diag(sc/sig) U^T Fhat

@@ -5,22 +5,24 @@
 // Avoiding non-native intrinsics ("Avoid non-native intrinsics"): on V100
 // the paper drops shared-memory float atomics because they are emulated.
 // On gfx950 ds_add_f32 exists but runs at about 0.3 lane-ops per clock per
-// CU, while ds_add_f64 runs at about 6.6 and global float atomics at about
-// 0.4 (measured on MI355X), so the same principle leads here to an LDS tile
-// accumulated with FP64 atomics:
-//   * a workgroup takes one chunk (<= 512 particles of one particle block),
-//     one particle per thread;
+// CU, while ds_add_f64 runs at about 6.6, and global float atomics (about
+// 0.4, executed memory-side) move a full write per update.  The same
+// principle -- use only the fast native operations -- leads here to:
+//   * a workgroup takes one chunk (<= 256 or 512 particles of one particle
+//     block), one particle per thread, loads coalesced;
 //   * phase 1 computes every particle's contribution and the bounding box of
 //     the stencils of the chunk's in-zone particles (block reduction);
 //   * the tile is that box (at most 512 nodes; a particle block's stencils
 //     cover 6^3 = 216 nodes right after a rebuild), four FP64 channels
-//     (sum of weights, three momentum components);
-//   * phase 2 adds every contribution with ds_add_f64;
-//   * the flush scales the weight sum by the particle mass and adds the
-//     non-empty nodes to the dense block grid with global float atomics.
-// Lane mapping: lane l of wave w takes sorted position w + rows*l (a
-// transpose of the chunk), so the lanes of a wave sit about one cell apart
-// and rarely hit one LDS address, where same-address atomics serialize.
+//     (weight sum and three momentum components) accumulated with
+//     ds_add_f64;
+//   * the tile is then STORED (plain, coalesced float4 stores) to the
+//     chunk's staging slot, and the grid update gathers each node from the
+//     tiles of the particle blocks around it -- no global atomics, and the
+//     transfer of in-zone particles is deterministic.
+// The rebuild stores each chunk with its sorted order spread by a stride
+// coprime to the count, so the 64 lanes of a wave sit in different cells
+// and rarely hit one LDS address (same-address atomics serialize).
 // Particles outside their free zone (before a late rebuild) scatter straight
 // to global atomics and activate the blocks they touch.
 #include "mpm_kernels.h"
@@ -29,16 +31,17 @@ namespace mpm {
 
 namespace {
 
-constexpr int P2G_WG = 512;  // threads per workgroup = max particles per chunk
-constexpr int CT = 512;      // compact tile capacity in nodes
+constexpr int CT = 512;  // compact tile capacity in nodes
 
-template <bool GLOBAL_ONLY>
-__global__ __launch_bounds__(P2G_WG) void k_p2g(float* __restrict__ S, int64_t cap, const Chunk* __restrict__ chunks,
-                                                int* __restrict__ ctl, float* __restrict__ acc,
-                                                int* __restrict__ brick_state, int* __restrict__ ovf, int parity,
-                                                Step P, Mat M, int pending, int nbricks, int transpose_lanes) {
+// NT threads per workgroup = the largest chunk it takes (256 or 512).
+template <bool GLOBAL_ONLY, int NT>
+__global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, const Chunk* __restrict__ chunks,
+                                            int* __restrict__ ctl, float* __restrict__ acc,
+                                            float4* __restrict__ stage, int2* __restrict__ box,
+                                            int* __restrict__ brick_state, int* __restrict__ ovf, int parity, Step P,
+                                            Mat M, int pending, int nbricks) {
     __shared__ double tq[GLOBAL_ONLY ? 1 : 4 * CT];
-    __shared__ int red_i[6][P2G_WG / 64];
+    __shared__ int red_i[6][NT / 64];
     unsigned err = 0;
     int begin, end, stride;
     xcd_split(ctl[CTL_NCHUNK], begin, end, stride);
@@ -48,13 +51,8 @@ __global__ __launch_bounds__(P2G_WG) void k_p2g(float* __restrict__ S, int64_t c
         const Chunk ch = chunks[c];
         const int count = ch.count;
         const int B[3] = {ch.block & 1023, (ch.block >> 10) & 1023, ch.block >> 20};
-        int j = tid;
-        if (transpose_lanes) {
-            const int rows = (count + 63) >> 6;
-            j = (wv < rows) ? wv + rows * lane : count;
-        }
-        const bool have = j < count;
-        const int p = ch.start + (have ? j : 0);
+        const bool have = tid < count;
+        const int p = ch.start + (have ? tid : 0);
 
         // ---- phase 1: material update, stress and this particle's payload
         Stencil st;
@@ -106,6 +104,7 @@ __global__ __launch_bounds__(P2G_WG) void k_p2g(float* __restrict__ S, int64_t c
         // ---- the box of the in-zone stencils of the chunk
         int lo[3] = {0, 0, 0}, ext[3] = {0, 0, 0};
         int nt = 0;
+        if (GLOBAL_ONLY && tid == 0) box[c] = make_int2(0, 0);
         if (!GLOBAL_ONLY) {
             const bool tiled = have && in_zone;
             int mn[3], mx[3];
@@ -129,7 +128,7 @@ __global__ __launch_bounds__(P2G_WG) void k_p2g(float* __restrict__ S, int64_t c
                 hi[a] = INT_MIN;
             }
 #pragma unroll
-            for (int k = 0; k < P2G_WG / 64; ++k) {
+            for (int k = 0; k < NT / 64; ++k) {
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     lo[a] = min(lo[a], red_i[a][k]);
@@ -141,11 +140,14 @@ __global__ __launch_bounds__(P2G_WG) void k_p2g(float* __restrict__ S, int64_t c
                 for (int a = 0; a < 3; ++a) ext[a] = hi[a] - lo[a] + 1;
                 nt = ext[0] * ext[1] * ext[2];
             }
-            if (nt > CT) nt = -1;  // does not fit: the chunk goes to global atomics
-            for (int t = tid; t < nt; t += P2G_WG) {
+            if (nt > CT || nt > 27 * count) nt = -1;  // no room: the chunk goes to global atomics
+            for (int t = tid; t < nt; t += NT) {
 #pragma unroll
                 for (int ch4 = 0; ch4 < 4; ++ch4) tq[ch4 * CT + t] = 0.0;
             }
+            if (tid == 0)
+                box[c] = nt > 0 ? make_int2(lo[0] | (lo[1] << 10) | (lo[2] << 20), ext[0] | (ext[1] << 8) | (ext[2] << 16))
+                                : make_int2(0, 0);
             __syncthreads();
         }
 
@@ -205,23 +207,13 @@ __global__ __launch_bounds__(P2G_WG) void k_p2g(float* __restrict__ S, int64_t c
             }
         }
 
-        // ---- flush the box to the dense block grid
+        // ---- store the tile to the chunk's staging slot
         if (!GLOBAL_ONLY) {
             __syncthreads();
-            for (int t = tid; t < nt; t += P2G_WG) {
-                const double ws = tq[t];
-                if (ws != 0.0) {
-                    const int tx = t % ext[0], ty = (t / ext[0]) % ext[1], tz = t / (ext[0] * ext[1]);
-                    const int gx = lo[0] + tx, gy = lo[1] + ty, gz = lo[2] + tz;
-                    const int node = (((((gz >> 2) + 1) * P.NB + ((gy >> 2) + 1)) * P.NB + ((gx >> 2) + 1)) << 6) +
-                                     (gx & 3) + ((gy & 3) << 2) + ((gz & 3) << 4);
-                    float* a = acc + 4 * node;
-                    unsafeAtomicAdd(a + 0, (float)(ws * (double)M.mp));
-                    unsafeAtomicAdd(a + 1, (float)tq[CT + t]);
-                    unsafeAtomicAdd(a + 2, (float)tq[2 * CT + t]);
-                    unsafeAtomicAdd(a + 3, (float)tq[3 * CT + t]);
-                }
-            }
+            float4* slot = stage + 27 * (int64_t)ch.start;
+            for (int t = tid; t < nt; t += NT)
+                slot[t] = make_float4((float)(tq[t] * (double)M.mp), (float)tq[CT + t], (float)tq[2 * CT + t],
+                                      (float)tq[3 * CT + t]);
             __syncthreads();
         }
     }
@@ -230,26 +222,29 @@ __global__ __launch_bounds__(P2G_WG) void k_p2g(float* __restrict__ S, int64_t c
 
 }  // namespace
 
-int p2g_grid_size(int cus) {
+int p2g_grid_size(int cus, int chunk) {
     int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_p2g<false>), P2G_WG, 0) !=
-            hipSuccess ||
-        occ <= 0)
+    const void* fn = chunk <= 256 ? reinterpret_cast<const void*>(k_p2g<false, 256>)
+                                  : reinterpret_cast<const void*>(k_p2g<false, 512>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, chunk <= 256 ? 256 : 512, 0) != hipSuccess || occ <= 0)
         occ = 1;
-    if (occ > 4) occ = 4;
+    if (occ > 8) occ = 8;
     const int g = cus * occ;
     return g < 8 ? 8 : (g / 8) * 8;
 }
 
 void enqueue_p2g(hipStream_t st, const Launch& L, const Step& P, const Mat& M, float* S, int64_t cap,
                  const Chunk* chunks, int* ctl, GridBuffers& G, int* brick_state, int pending, int parity,
-                 int global_atomics, int transpose_lanes, int nbricks) {
-    if (global_atomics)
-        hipLaunchKernelGGL(k_p2g<true>, dim3(L.p2g_grid), dim3(P2G_WG), 0, st, S, cap, chunks, ctl, G.acc,
-                           brick_state, G.ovf[parity], parity, P, M, pending, nbricks, transpose_lanes);
-    else
-        hipLaunchKernelGGL(k_p2g<false>, dim3(L.p2g_grid), dim3(P2G_WG), 0, st, S, cap, chunks, ctl, G.acc,
-                           brick_state, G.ovf[parity], parity, P, M, pending, nbricks, transpose_lanes);
+                 int global_atomics, int nbricks, int chunk) {
+#define MPM_LAUNCH_P2G(GO, T)                                                                                \
+    hipLaunchKernelGGL((k_p2g<GO, T>), dim3(L.p2g_grid), dim3(T), 0, st, S, cap, chunks, ctl, G.acc, G.stage, \
+                       G.box, brick_state, G.ovf[parity], parity, P, M, pending, nbricks)
+    if (chunk <= 256) {
+        if (global_atomics) MPM_LAUNCH_P2G(true, 256); else MPM_LAUNCH_P2G(false, 256);
+    } else {
+        if (global_atomics) MPM_LAUNCH_P2G(true, 512); else MPM_LAUNCH_P2G(false, 512);
+    }
+#undef MPM_LAUNCH_P2G
 }
 
 }  // namespace mpm

@@ -27,26 +27,86 @@ namespace mpm {
 namespace {
 
 // ----------------------------------------------------------- grid update
-// One wave64 per 4^3 block: v = p/m + dt g where m > 0 (else 0), then the
-// wall condition; writes (v, m), clears the accumulators, and stamps the block.
+// One wave64 per 4^3 block.  Each node sums the global-path accumulator and
+// the staged P2G tiles of the particle blocks whose 3x3x3 neighbourhood
+// holds it (padded block coordinates b-1..b+1 per axis), then
+// v = p/m + dt g where m > 0 (else 0) and the wall condition; writes (v, m),
+// clears the accumulator, and stamps the block.
 __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, float4* __restrict__ vel,
                                              const int* __restrict__ active, int* __restrict__ ctl,
                                              const int* __restrict__ ovf, int* __restrict__ brick_state,
-                                             int* __restrict__ stamp, int parity, int step, int nbricks, Step P) {
+                                             int* __restrict__ stamp, const int* __restrict__ gindex,
+                                             const int* __restrict__ gchunk, const Chunk* __restrict__ chunks,
+                                             const float4* __restrict__ stage, const int2* __restrict__ box,
+                                             int parity, int step, int nbricks, Step P) {
     const int nact = ctl[CTL_NACTIVE];
     const int total = nact + min(ctl[CTL_OVF + parity], nbricks - nact);
     const int lane = threadIdx.x & 63;
     const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
     const int nwaves = gridDim.x * (WG / 64);
     float4* acc4 = reinterpret_cast<float4*>(acc);
+    const int NB = P.NB;
+    __shared__ int cand[WG / 64][64];
     for (int it = blockIdx.x * (WG / 64) + (threadIdx.x >> 6); it < total; it += nwaves) {
-        const int b = it < nact ? active[it] : ovf[it - nact];
-        const int bx = b % P.NB, by = (b / P.NB) % P.NB, bz = b / (P.NB * P.NB);
+        const int b = __builtin_amdgcn_readfirstlane(it < nact ? active[it] : ovf[it - nact]);
+        const int bx = b % NB, by = (b / NB) % NB, bz = b / (NB * NB);
         const int g[3] = {4 * (bx - 1) + lx, 4 * (by - 1) + ly, 4 * (bz - 1) + lz};
-        const float4 a = acc4[b * 64 + lane];
+        float4 a = acc4[b * 64 + lane];
+        // Lane k < 27 looks up the chunk range of candidate particle block k
+        // (padded offsets -1..1 per axis); the ranges are laid out in LDS as
+        // this wave's candidate list, then every lane sums the staged tile
+        // values that cover its node.
+        int n_k = 0, c0_k = 0;
+        if (lane < 27) {
+            const int px = bx + lane % 3 - 1, py = by + (lane / 3) % 3 - 1, pz = bz + lane / 9 - 1;
+            if (px >= 0 && px < NB && py >= 0 && py < NB && pz >= 0 && pz < NB) {
+                const int gb = gindex[(pz * NB + py) * NB + px];
+                if (gb >= 0) {
+                    c0_k = gchunk[gb];
+                    n_k = gchunk[gb + 1] - c0_k;
+                }
+            }
+        }
+        int incl = n_k;
+#pragma unroll
+        for (int d = 1; d < 32; d <<= 1) {
+            const int t = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += t;
+        }
+        const int total_c = __shfl(incl, 26, 64);
+        int* list = cand[threadIdx.x >> 6];
+        for (int base = 0; base < total_c; base += 64) {
+            // lanes k < 27 write the part of their range that falls in [base, base + 64)
+            for (int i = 0; i < n_k; ++i) {
+                const int slot = incl - n_k + i - base;
+                if (slot >= 0 && slot < 64) list[slot] = c0_k + i;
+            }
+            __builtin_amdgcn_wave_barrier();
+            const int m = min(64, total_c - base);
+            int2 bb = make_int2(0, 0);
+            int st0 = 0;
+            if (lane < m) {
+                const int c = list[lane];
+                bb = box[c];
+                st0 = chunks[c].start;
+            }
+            __builtin_amdgcn_wave_barrier();
+            for (int i = 0; i < m; ++i) {
+                const int bx_ = __shfl(bb.x, i, 64), by_ = __shfl(bb.y, i, 64), s_ = __shfl(st0, i, 64);
+                const int e0 = by_ & 255, e1 = (by_ >> 8) & 255, e2 = by_ >> 16;
+                const int r0 = g[0] - (bx_ & 1023), r1 = g[1] - ((bx_ >> 10) & 1023), r2 = g[2] - (bx_ >> 20);
+                if (r0 >= 0 && r0 < e0 && r1 >= 0 && r1 < e1 && r2 >= 0 && r2 < e2) {
+                    const float4 sv = stage[27 * (int64_t)s_ + r0 + e0 * (r1 + e1 * r2)];
+                    a.x += sv.x;
+                    a.y += sv.y;
+                    a.z += sv.z;
+                    a.w += sv.w;
+                }
+            }
+        }
         float v[3] = {0.0f, 0.0f, 0.0f};
         if (a.x > 0.0f) {
-            const float inv = 1.0f / a.x;
+            const float inv = __frcp_rn(a.x);
             v[0] = a.y * inv + P.dt * P.g0;
             v[1] = a.z * inv + P.dt * P.g1;
             v[2] = a.w * inv + P.dt * P.g2;
@@ -85,17 +145,44 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, float4* __
 }
 
 // -------------------------------------------------------------------- G2P
+// A chunk's in-zone stencils lie in the node box its P2G tile used this
+// substep (box[c]); the grid velocities of that box are loaded once, coalesced,
+// into LDS and the 27-node gathers read LDS.  Particles whose stencil leaves
+// the box gather from the dense grid.
+constexpr int G2P_BOX = 512;
+
+template <bool LDS_BOX>
 __global__ __launch_bounds__(WG) void k_g2p(float* __restrict__ S, int64_t cap, const Chunk* __restrict__ chunks,
                                             int* __restrict__ ctl, const float4* __restrict__ vel,
-                                            int* __restrict__ host_flag, Step P) {
+                                            const int2* __restrict__ box, int* __restrict__ host_flag, Step P) {
+    __shared__ float4 tv[LDS_BOX ? G2P_BOX : 1];
     unsigned err = 0;
     bool left = false;
     int begin, end, stride;
     xcd_split(ctl[CTL_NCHUNK], begin, end, stride);
     const float c4 = 4.0f * P.fn;  // (4/dx^2) * dx
+    const int NB = P.NB;
     for (int c = begin; c < end; c += stride) {
         const Chunk ch = chunks[c];
         const int B[3] = {ch.block & 1023, (ch.block >> 10) & 1023, ch.block >> 20};
+        int lo[3] = {0, 0, 0}, e[3] = {0, 0, 0}, nt = 0;
+        if (LDS_BOX) {
+            const int2 bb = box[c];
+            e[0] = bb.y & 255;
+            e[1] = (bb.y >> 8) & 255;
+            e[2] = bb.y >> 16;
+            lo[0] = bb.x & 1023;
+            lo[1] = (bb.x >> 10) & 1023;
+            lo[2] = bb.x >> 20;
+            nt = e[0] * e[1] * e[2];
+            if (nt > G2P_BOX) nt = 0;
+            for (int t = threadIdx.x; t < nt; t += WG) {
+                const int gx = lo[0] + t % e[0], gy = lo[1] + (t / e[0]) % e[1], gz = lo[2] + t / (e[0] * e[1]);
+                tv[t] = vel[((((gz >> 2) + 1) * NB + ((gy >> 2) + 1)) * NB + ((gx >> 2) + 1)) * 64 + (gx & 3) +
+                            ((gy & 3) << 2) + ((gz & 3) << 4)];
+            }
+            __syncthreads();
+        }
         for (int i = threadIdx.x; i < ch.count; i += WG) {
             const int p = ch.start + i;
             float x[3];
@@ -103,36 +190,68 @@ __global__ __launch_bounds__(WG) void k_g2p(float* __restrict__ S, int64_t cap, 
             for (int a = 0; a < 3; ++a) x[a] = S[(FX + a) * cap + p];
             Stencil st;
             if (!make_stencil(x, P, st, err)) continue;
-            int xo[3], yo[3], zo[3];
-            axis_offsets(st.base[0], 1, 0, xo);
-            axis_offsets(st.base[1], P.NB, 2, yo);
-            axis_offsets(st.base[2], P.NB * P.NB, 4, zo);
+            int r[3];
+            bool inbox = nt > 0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                r[a] = st.base[a] - lo[a];
+                inbox = inbox && r[a] >= 0 && r[a] + 2 < e[a];
+            }
             float vp[3] = {0, 0, 0};
             float Mo[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // sum w v_a o_b
+            if (inbox) {
+                const int tb = r[0] + e[0] * (r[1] + e[1] * r[2]);
 #pragma unroll
-            for (int o2 = 0; o2 < 3; ++o2)
+                for (int o2 = 0; o2 < 3; ++o2)
 #pragma unroll
-                for (int o1 = 0; o1 < 3; ++o1) {
-                    const float wyz = st.w[1][o1] * st.w[2][o2];
+                    for (int o1 = 0; o1 < 3; ++o1) {
+                        const float wyz = st.w[1][o1] * st.w[2][o2];
+                        const int row = tb + e[0] * (o1 + e[1] * o2);
 #pragma unroll
-                    for (int o0 = 0; o0 < 3; ++o0) {
-                        const float w = wyz * st.w[0][o0];
-                        const float4 g = vel[xo[o0] + yo[o1] + zo[o2]];
-                        const float wv[3] = {w * g.x, w * g.y, w * g.z};
+                        for (int o0 = 0; o0 < 3; ++o0) {
+                            const float w = wyz * st.w[0][o0];
+                            const float4 g = tv[row + o0];
+                            const float wv[3] = {w * g.x, w * g.y, w * g.z};
 #pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            vp[a] += wv[a];
-                            Mo[a * 3 + 0] += o0 * wv[a];
-                            Mo[a * 3 + 1] += o1 * wv[a];
-                            Mo[a * 3 + 2] += o2 * wv[a];
+                            for (int a = 0; a < 3; ++a) {
+                                vp[a] += wv[a];
+                                Mo[a * 3 + 0] += o0 * wv[a];
+                                Mo[a * 3 + 1] += o1 * wv[a];
+                                Mo[a * 3 + 2] += o2 * wv[a];
+                            }
                         }
                     }
-                }
+            } else {
+                int xo[3], yo[3], zo[3];
+                axis_offsets(st.base[0], 1, 0, xo);
+                axis_offsets(st.base[1], NB, 2, yo);
+                axis_offsets(st.base[2], NB * NB, 4, zo);
+#pragma unroll
+                for (int o2 = 0; o2 < 3; ++o2)
+#pragma unroll
+                    for (int o1 = 0; o1 < 3; ++o1) {
+                        const float wyz = st.w[1][o1] * st.w[2][o2];
+#pragma unroll
+                        for (int o0 = 0; o0 < 3; ++o0) {
+                            const float w = wyz * st.w[0][o0];
+                            const float4 g = vel[xo[o0] + yo[o1] + zo[o2]];
+                            const float wv[3] = {w * g.x, w * g.y, w * g.z};
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) {
+                                vp[a] += wv[a];
+                                Mo[a * 3 + 0] += o0 * wv[a];
+                                Mo[a * 3 + 1] += o1 * wv[a];
+                                Mo[a * 3 + 2] += o2 * wv[a];
+                            }
+                        }
+                    }
+            }
             // C' = 4/dx^2 sum w v (x_i - x_p)^T = (4/dx) (Mo - v' f^T)
 #pragma unroll
             for (int a = 0; a < 3; ++a)
 #pragma unroll
-                for (int b = 0; b < 3; ++b) S[(FC + a * 3 + b) * cap + p] = c4 * (Mo[a * 3 + b] - vp[a] * st.f[b]);
+                for (int b2 = 0; b2 < 3; ++b2)
+                    S[(FC + a * 3 + b2) * cap + p] = c4 * (Mo[a * 3 + b2] - vp[a] * st.f[b2]);
             bool fin = true;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
@@ -146,6 +265,7 @@ __global__ __launch_bounds__(WG) void k_g2p(float* __restrict__ S, int64_t cap, 
             }
             if (!fin) err |= MPM_ERR_NONFINITE;
         }
+        if (LDS_BOX) __syncthreads();
     }
     if (__ballot(left) != 0ull && (threadIdx.x & 63) == 0) {
         if (__hip_atomic_load(&ctl[CTL_REBUILD], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
@@ -244,7 +364,7 @@ __global__ __launch_bounds__(WG) void k_read_grid(const float4* __restrict__ vel
 
 }  // namespace
 
-void query_launch(Launch& L) {
+void query_launch(Launch& L, int chunk) {
     int dev = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&L.cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -256,20 +376,26 @@ void query_launch(Launch& L) {
         int g = L.cus * occ;
         return g < 8 ? 8 : (g / 8) * 8;
     };
-    L.p2g_grid = p2g_grid_size(L.cus);
-    L.g2p_grid = grid_for(reinterpret_cast<const void*>(k_g2p), 8);
+    L.p2g_grid = p2g_grid_size(L.cus, chunk);
+    L.g2p_grid = grid_for(reinterpret_cast<const void*>(k_g2p<true>), 8);
     L.grid_grid = grid_for(reinterpret_cast<const void*>(k_grid), 8);
 }
 
-void enqueue_grid(hipStream_t st, const Launch& L, const Step& P, const int* active, int* ctl, GridBuffers& G,
-                  int* brick_state, int parity, int step) {
-    hipLaunchKernelGGL(k_grid, dim3(L.grid_grid), dim3(WG), 0, st, G.acc, G.vel, active, ctl, G.ovf[parity],
-                       brick_state, G.stamp, parity, step, P.NB * P.NB * P.NB, P);
+void enqueue_grid(hipStream_t st, const Launch& L, const Step& P, const BinBuffers& B, int* ctl, GridBuffers& G,
+                  int parity, int step) {
+    hipLaunchKernelGGL(k_grid, dim3(L.grid_grid), dim3(WG), 0, st, G.acc, G.vel, B.active, ctl, G.ovf[parity],
+                       B.brick_state, G.stamp, B.gindex, B.gchunk, B.chunks, G.stage, G.box, parity, step,
+                       P.NB * P.NB * P.NB, P);
 }
 
 void enqueue_g2p(hipStream_t st, const Launch& L, const Step& P, float* S, int64_t cap, const Chunk* chunks, int* ctl,
-                 const GridBuffers& G, int* host_flag) {
-    hipLaunchKernelGGL(k_g2p, dim3(L.g2p_grid), dim3(WG), 0, st, S, cap, chunks, ctl, G.vel, host_flag, P);
+                 const GridBuffers& G, int* host_flag, int lds_box) {
+    if (lds_box)
+        hipLaunchKernelGGL(k_g2p<true>, dim3(L.g2p_grid), dim3(WG), 0, st, S, cap, chunks, ctl, G.vel, G.box, host_flag,
+                           P);
+    else
+        hipLaunchKernelGGL(k_g2p<false>, dim3(L.g2p_grid), dim3(WG), 0, st, S, cap, chunks, ctl, G.vel, G.box,
+                           host_flag, P);
 }
 
 void enqueue_materialize(hipStream_t st, const Step& P, const Mat& M, float* S, int64_t cap, int N) {

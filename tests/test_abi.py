@@ -104,3 +104,14 @@ def test_binding_refuses_to_run_without_the_library(monkeypatch, tmp_path):
     monkeypatch.setattr(mpm, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         mpm.load()
+
+
+def test_documented_chunk_layout_rule_is_a_permutation():
+    """The storage layout include/mpm.h documents (slot t of a chunk of c
+    particles holds sorted position (t*K) mod c, K the smallest of 9, 11, 13,
+    17 coprime to c) must be a permutation for every chunk size up to 512."""
+    import math
+
+    for c in range(1, 513):
+        K = next(q for q in (9, 11, 13, 17) if math.gcd(q, c) == 1)
+        assert sorted((t * K) % c for t in range(c)) == list(range(c))

@@ -96,8 +96,23 @@ def test_binning_is_bit_exact(torch_cuda, oracle, n, which):
     sim.close()
 
 
+def storage_order(perm, gstart, gcount, chunk=256):
+    """Insertion ids in storage order after a rebuild: geometric blocks are cut
+    into chunks of `chunk`, and inside a chunk of `cnt` particles storage slot
+    t holds sorted position (t * K) mod cnt, K the smallest of 9, 11, 13, 17
+    coprime to cnt (the layout include/mpm.h documents)."""
+    order = np.empty_like(perm)
+    for s0, cnt in zip(gstart.tolist(), gcount.tolist()):
+        for k in range(0, cnt, chunk):
+            c0, cc = s0 + k, min(chunk, cnt - k)
+            K = next(q for q in (9, 11, 13, 17) if np.gcd(q, cc) == 1)
+            t = np.arange(cc)
+            order[c0 + t] = perm[c0 + (t * K) % cc]
+    return order
+
+
 def test_binning_after_motion_composes(torch_cuda, oracle):
-    """A later rebuild stably sorts the CURRENT (already sorted) order."""
+    """A later rebuild stably sorts the CURRENT storage order."""
     sc = scenes.jelly_cube(0)
     st = scenes.nontrivial_state(sc["x"], seed=7)
     st["v"] = st["v"] * 40.0  # move several cells
@@ -106,16 +121,19 @@ def test_binning_after_motion_composes(torch_cuda, oracle):
     sim.add_particles(dict(scenes.JELLY, E=0.0), st["x"], v=st["v"])
     sim.substep(10)
     _, perm0 = sim.read_binning()
+    b0 = sim.read_blocks()
     x_now = gpu_state(sim)["x"].astype(np.float32)
     sim.rebuild()
     sim.substep(1)
     keys1, perm1 = sim.read_binning()
-    # oracle: positions in the previous sorted order, then a stable sort
-    xs = x_now[:, perm0]
+    # oracle: positions in the storage order left by the first rebuild, then a stable sort
+    order0 = storage_order(perm0, b0["gstart"], b0["gcount"])
+    assert np.array_equal(np.sort(order0), np.arange(order0.size))
+    xs = x_now[:, order0]
     k, _, _ = oracle.keys(xs, 64)
     p, srt = oracle.stable_sort(k)
     assert np.array_equal(keys1, srt)
-    assert np.array_equal(perm1, perm0[p])
+    assert np.array_equal(perm1, order0[p])
     sim.close()
 
 
@@ -124,13 +142,13 @@ MATS = {"jelly": (scenes.JELLY, "sticky"), "snow": (scenes.SNOW, "separate"), "w
 
 
 @pytest.mark.parametrize("kind", ["jelly", "snow", "water"])
-@pytest.mark.parametrize("mode", ["tile", "global", "every_step"])
+@pytest.mark.parametrize("mode", ["tile", "global", "every_step", "sorted_lanes", "g2p_global"])
 def test_single_substep_matches_oracle(torch_cuda, oracle, kind, mode):
     mat, bc = MATS[kind]
     sc = scenes.jelly_cube(0)
     st = scenes.nontrivial_state(sc["x"], seed=5, kind=kind)
     cfg = dict(n=64, dt=1e-4, bc=bc)
-    flags = {"tile": 0, "global": 0x2, "every_step": 0x1}[mode]
+    flags = {"tile": 0, "global": 0x2, "every_step": 0x1, "sorted_lanes": 0x8, "g2p_global": 0x10}[mode]
     print_case("substep1", kind=kind, mode=mode, N=st["x"].shape[1])
     sim = make_sim(torch_cuda, cfg, flags=flags)
     sim.add_particles(mat, st["x"], v=st["v"], C=st["C"], F=st.get("F"), s=st.get("s"))
