@@ -30,10 +30,25 @@ HBM_PEAK_GBS = 8000.0
 P2G_BYTES = {"jelly": 132, "snow": 140, "water": 68}
 G2P_BYTES = 72
 
-# HBM bytes per P2G launch measured with rocprofv3 counters (FETCH_SIZE +
-# WRITE_SIZE, KiB per dispatch, scaled by a plain copy kernel's reading); see
-# profiles/.  None until taken for the current kernel.
-P2G_TRAFFIC_BYTES = None
+# HBM bytes per P2G launch measured with rocprofv3 counters (FETCH_SIZE x 2.0
+# + WRITE_SIZE x 1.0, the factors a plain 1 GiB copy reads back, averaged over
+# the 334 launches of the first frame); profiles/substep_snow256_counters.md.
+# The figure belongs to the P2G sources whose hash is stored beside it: after
+# any change to them the bench reports traffic as null until it is measured
+# again.
+P2G_TRAFFIC = {"sources_sha256_16": "8ea0e0db490e6891", "bytes": 197.05e6}
+P2G_SOURCES = ("paper_2111_00699_amd/csrc/mpm_p2g.hip", "paper_2111_00699_amd/csrc/mpm_internal.h",
+               "paper_2111_00699_amd/csrc/mpm_kernels.h")
+
+
+def p2g_traffic_bytes():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in P2G_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return P2G_TRAFFIC["bytes"] if h.hexdigest()[:16] == P2G_TRAFFIC["sources_sha256_16"] else None
 
 
 def log(msg):
@@ -142,7 +157,7 @@ def main():
                    "substeps_per_rebuild": substeps / max(rebuilds, 1), "chunk": args.chunk or 256},
         "roofline": {"kernel": "p2g", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None if P2G_TRAFFIC_BYTES is None else P2G_TRAFFIC_BYTES,
+                     "traffic": p2g_traffic_bytes(), "traffic_unit": "HBM bytes per launch",
                      "avg_launch_us": p2g_avg_ms * 1e3, "launches": p2g["launches"],
                      "bytes_per_particle": P2G_BYTES["snow"]},
         "wall_ms": wall * 1e3,
