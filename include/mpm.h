@@ -109,6 +109,11 @@ typedef struct {
     int64_t overflow_blocks; /* blocks touched outside the physical set in the last substep */
     uint32_t error;          /* sticky MPM_ERR_* bits */
     uint32_t pending_update; /* 1 if the deformation update of the last G2P is deferred to the next P2G */
+    /* running totals since mpm_create (all substeps):                                   */
+    int64_t p2g_fallback_chunks;  /* chunks whose stencil box exceeded the LDS tile; their particles
+                                     scattered with global atomics                          */
+    int64_t p2g_global_particles; /* particle transfers done with global atomics (particles outside
+                                     their free zone, plus those of fallback chunks)        */
 } mpm_stats;
 
 /* Phases that mpm_profile can bracket with HIP events. */

@@ -159,8 +159,12 @@ int grow(mpm_ctx* c, int64_t newcap) {
     Chunk* chunks = nullptr;
     int *gchunk = nullptr, *sorted_ids = nullptr;
     float4* stage = nullptr;
-    int2* box = nullptr;
+    int4* box = nullptr;
     const int64_t rs_tiles = (newcap + 4095) / 4096;
+    // P2G staging: 16 nodes per particle of capacity (a block-sized chunk stages about one node per
+    // particle) plus two full tiles per P2G workgroup, so small systems never run short.
+    int64_t stage_nodes = 16 * newcap + 2 * 512 * (int64_t)c->L.p2g_grid;
+    if (stage_nodes > (int64_t)INT32_MAX - 4096) stage_nodes = (int64_t)INT32_MAX - 4096;
     bool ok = true;
     for (int i = 0; i < 2 && ok; ++i) {
         ok = ok && hipMalloc(&S[i], sizeof(float) * NF * newcap) == hipSuccess;
@@ -175,8 +179,8 @@ int grow(mpm_ctx* c, int64_t newcap) {
     ok = ok && hipMalloc(&chunks, sizeof(Chunk) * (newcap + 1)) == hipSuccess;
     ok = ok && hipMalloc(&gchunk, sizeof(int) * (newcap + 2)) == hipSuccess;
     ok = ok && hipMalloc(&sorted_ids, sizeof(int) * newcap) == hipSuccess;
-    ok = ok && hipMalloc(&stage, sizeof(float4) * 27 * newcap) == hipSuccess;
-    ok = ok && hipMalloc(&box, sizeof(int2) * (newcap + 1)) == hipSuccess;
+    ok = ok && hipMalloc(&stage, sizeof(float4) * stage_nodes) == hipSuccess;
+    ok = ok && hipMalloc(&box, sizeof(int4) * (newcap + 1)) == hipSuccess;
     if (!ok) {
         for (int i = 0; i < 2; ++i) {
             (void)hipFree(S[i]);
@@ -201,7 +205,7 @@ int grow(mpm_ctx* c, int64_t newcap) {
                                    sizeof(float) * c->N, NF, hipMemcpyDeviceToDevice, c->stream));
         HIP_OK(c, hipMemcpyAsync(ids[0], c->ids[c->cur], sizeof(int) * c->N, hipMemcpyDeviceToDevice, c->stream));
     }
-    HIP_OK(c, hipMemsetAsync(box, 0, sizeof(int2) * (newcap + 1), c->stream));
+    HIP_OK(c, hipMemsetAsync(box, 0, sizeof(int4) * (newcap + 1), c->stream));
     HIP_OK(c, hipStreamSynchronize(c->stream));
     free_particle_buffers(c);
     for (int i = 0; i < 2; ++i) {
@@ -218,6 +222,7 @@ int grow(mpm_ctx* c, int64_t newcap) {
     c->B.gchunk = gchunk;
     c->B.sorted_ids = sorted_ids;
     c->G.stage = stage;
+    c->G.stage_nodes = (int)stage_nodes;
     c->G.box = box;
     c->cur = 0;
     c->cap = newcap;
@@ -351,7 +356,7 @@ int mpm_create(const mpm_config* cfg, mpm_ctx** out) {
               hipMalloc(&c->B.brick_state, sizeof(int) * nb) == hipSuccess &&
               hipMalloc(&c->B.active, sizeof(int) * nb) == hipSuccess &&
               hipMalloc(&c->B.gindex, sizeof(int) * nb) == hipSuccess &&
-              hipMalloc(&c->ctl, sizeof(int) * CTL_WORDS) == hipSuccess;
+              hipMalloc(&c->ctl, sizeof(int) * CTL_ALLOC_WORDS) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         c->err = "grid allocation failed";
@@ -361,7 +366,7 @@ int mpm_create(const mpm_config* cfg, mpm_ctx** out) {
         hipMemsetAsync(c->G.vel, 0, sizeof(float4) * 64 * nb, c->stream) != hipSuccess ||
         hipMemsetAsync(c->G.stamp, 0xff, sizeof(int) * nb, c->stream) != hipSuccess ||
         hipMemsetAsync(c->B.brick_state, 0, sizeof(int) * nb, c->stream) != hipSuccess ||
-        hipMemsetAsync(c->ctl, 0, sizeof(int) * CTL_WORDS, c->stream) != hipSuccess) {
+        hipMemsetAsync(c->ctl, 0, sizeof(int) * CTL_ALLOC_WORDS, c->stream) != hipSuccess) {
         c->err = "initialisation failed";
         return bail(MPM_EDEVICE);
     }
@@ -447,6 +452,11 @@ int mpm_add_particles(mpm_ctx* c, int32_t scene, const mpm_material* mat, int64_
     return MPM_OK;
 }
 
+// In-zone particles that may lose their chunk's tile in one substep before
+// the next substep asks for a rebuild (1/256 of the particles).  With
+// MPM_FLAG_MANUAL_REBUILD the request is ignored like the free-zone one.
+int fb_limit(const mpm_ctx* c) { return (int)(c->N >> 8); }
+
 int mpm_substep(mpm_ctx* c, int32_t nsteps) {
     if (!c) return MPM_EINVAL;
     if (nsteps < 0) return fail(c, MPM_EINVAL, "negative step count");
@@ -482,7 +492,7 @@ int mpm_substep(mpm_ctx* c, int32_t nsteps) {
         if ((r = prof_end(c, slot))) return r;
         if ((r = prof_begin(c, 3, &slot))) return r;
         enqueue_g2p(c->stream, c->L, c->P, c->S[c->cur], c->cap, c->B.chunks, c->ctl, c->G, c->ring_dev + rs,
-                    (c->cfg.flags & MPM_FLAG_G2P_GLOBAL_GATHER) ? 0 : 1);
+                    (c->cfg.flags & MPM_FLAG_G2P_GLOBAL_GATHER) ? 0 : 1, parity, fb_limit(c), c->cfg.chunk);
         if ((r = prof_end(c, slot))) return r;
         HIP_OK(c, hipGetLastError());
         HIP_OK(c, hipEventRecord(c->ev[rs], c->stream));
@@ -566,7 +576,7 @@ int mpm_read_blocks(mpm_ctx* c, int32_t scene, uint32_t* gcode, int32_t* gstart,
 
 int mpm_get_stats(mpm_ctx* c, mpm_stats* o) {
     if (!c || !o) return MPM_EINVAL;
-    int h[CTL_WORDS];
+    int h[CTL_ALLOC_WORDS];
     HIP_OK(c, hipMemcpyAsync(h, c->ctl, sizeof h, hipMemcpyDeviceToHost, c->stream));
     HIP_OK(c, hipStreamSynchronize(c->stream));
     int r = poll_flags(c, c->step);
@@ -582,6 +592,10 @@ int mpm_get_stats(mpm_ctx* c, mpm_stats* o) {
     o->overflow_blocks = c->step > 0 ? h[CTL_OVF + ((c->step - 1) & 1)] : 0;
     o->error = (uint32_t)h[CTL_ERROR];
     o->pending_update = (uint32_t)c->pending;
+    unsigned long long c64[CTL64_WORDS];
+    memcpy(c64, h + CTL_WORDS, sizeof c64);
+    o->p2g_fallback_chunks = (int64_t)c64[CTL64_FALLBACK_CHUNKS];
+    o->p2g_global_particles = (int64_t)c64[CTL64_GLOBAL_PARTICLES];
     return o->error ? fail(c, MPM_ESTATE, "device error word set") : MPM_OK;
 }
 

@@ -27,8 +27,18 @@ enum Ctl : int {
     CTL_ERROR = 4,     // sticky MPM_ERR_* bits
     CTL_OVF = 5,       // overflow-block counts, two slots by substep parity
     CTL_SCAN = 8,      // scratch total of a device scan
-    CTL_WORDS = 16
+    CTL_FB = 9,        // in-zone particles of chunks whose tile did not fit, two slots by substep parity
+    CTL_WORDS = 16,
+    // 64-bit running counters follow the 16 words (byte offset 64):
+    CTL64_FALLBACK_CHUNKS = 0,     // P2G chunks whose node box did not fit the LDS tile
+    CTL64_GLOBAL_PARTICLES = 1,    // particles P2G scattered with global atomics
+    CTL64_WORDS = 2,
+    CTL_ALLOC_WORDS = CTL_WORDS + 2 * CTL64_WORDS
 };
+
+__host__ __device__ inline unsigned long long* ctl64(int* ctl) {
+    return reinterpret_cast<unsigned long long*>(ctl + CTL_WORDS);
+}
 
 // Derived material constants.
 struct Mat {
@@ -91,22 +101,32 @@ struct GridBuffers {
     float4* vel;    // [NB^3 * 64] (vx, vy, vz, m) after the grid update
     int* stamp;     // [NB^3] substep index of the last update of each block
     int* ovf[2];    // overflow block lists, by substep parity
-    float4* stage;  // [27 * cap] P2G tile of each chunk, (m, px, py, pz) per node, slot at 27 * chunk.start
-    int2* box;      // [cap] tile box of each chunk: lo packed 10 bits/axis, ext packed 8 bits/axis (0 = none)
+    float4* stage;  // [stage_nodes] P2G tiles, (m, px, py, pz) per node; each P2G workgroup owns an
+                    // equal slice and packs the tiles of its chunks there
+    int4* box;      // [cap] per chunk: x = tile origin packed 10 bits/axis, y = extent packed 8 bits/axis
+                    // (0 = no tile), z = offset of the tile in `stage` (nodes)
+    int stage_nodes;
 };
 
 struct Launch {
     int p2g_grid, g2p_grid, grid_grid, cus;
 };
 
+// Threads per P2G/G2P workgroup for a chunk size: one particle per thread.
+inline int chunk_threads(int chunk) { return chunk <= 128 ? 128 : chunk <= 256 ? 256 : 512; }
+
 void enqueue_p2g(hipStream_t st, const Launch& L, const Step& P, const Mat& M, float* S, int64_t cap,
                  const Chunk* chunks, int* ctl, GridBuffers& G, int* brick_state, int pending, int parity,
                  int global_atomics, int nbricks, int chunk);
 int p2g_grid_size(int cus, int chunk);
+// Workgroups of `threads` threads that fit on one compute unit at once, from
+// the kernel's register and LDS use (gfx950: 512 VGPRs per lane and SIMD,
+// 8 waves per SIMD, 4 SIMDs, `lds_per_cu` bytes of LDS).
+int wgs_per_cu(const void* fn, int threads);
 void enqueue_grid(hipStream_t st, const Launch& L, const Step& P, const BinBuffers& B, int* ctl, GridBuffers& G,
                   int parity, int step);
 void enqueue_g2p(hipStream_t st, const Launch& L, const Step& P, float* S, int64_t cap, const Chunk* chunks,
-                 int* ctl, const GridBuffers& G, int* host_flag, int lds_box);
+                 int* ctl, const GridBuffers& G, int* host_flag, int lds_box, int parity, int fb_limit, int chunk);
 void enqueue_materialize(hipStream_t st, const Step& P, const Mat& M, float* S, int64_t cap, int N);
 void enqueue_insert(hipStream_t st, float* S, int* ids, int64_t cap, int N0, int count, const float* x,
                     const float* v, const float* C, const float* F, const float* s, int* ctl);

@@ -17,9 +17,11 @@
 //     (weight sum and three momentum components) accumulated with
 //     ds_add_f64;
 //   * the tile is then STORED (plain, coalesced float4 stores) to the
-//     chunk's staging slot, and the grid update gathers each node from the
-//     tiles of the particle blocks around it -- no global atomics, and the
-//     transfer of in-zone particles is deterministic.
+//     staging buffer, and the grid update gathers each node from the tiles
+//     of the particle blocks around it -- no global atomics, and the
+//     transfer of in-zone particles is deterministic.  Each workgroup owns an
+//     equal slice of the staging buffer and packs its chunks' tiles there
+//     (offset recorded per chunk), so no allocation is shared.
 // The rebuild stores each chunk with its sorted order spread by a stride
 // coprime to the count, so the 64 lanes of a wave sit in different cells
 // and rarely hit one LDS address (same-address atomics serialize).
@@ -37,7 +39,7 @@ constexpr int CT = 512;  // compact tile capacity in nodes
 template <bool GLOBAL_ONLY, int NT>
 __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, const Chunk* __restrict__ chunks,
                                             int* __restrict__ ctl, float* __restrict__ acc,
-                                            float4* __restrict__ stage, int2* __restrict__ box,
+                                            float4* __restrict__ stage, int stage_nodes, int4* __restrict__ box,
                                             int* __restrict__ brick_state, int* __restrict__ ovf, int parity, Step P,
                                             Mat M, int pending, int nbricks) {
     __shared__ double tq[GLOBAL_ONLY ? 1 : 4 * CT];
@@ -47,6 +49,10 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
     xcd_split(ctl[CTL_NCHUNK], begin, end, stride);
     const float dx = P.dx, dt = P.dt;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    // this workgroup's slice of the staging buffer, filled front to back
+    const int slice = (int)((int64_t)stage_nodes / gridDim.x);
+    const int slice0 = slice * (int)blockIdx.x;
+    int used = 0;
     for (int c = begin; c < end; c += stride) {
         const Chunk ch = chunks[c];
         const int count = ch.count;
@@ -103,8 +109,8 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
 
         // ---- the box of the in-zone stencils of the chunk
         int lo[3] = {0, 0, 0}, ext[3] = {0, 0, 0};
-        int nt = 0;
-        if (GLOBAL_ONLY && tid == 0) box[c] = make_int2(0, 0);
+        int nt = 0, off = 0;
+        if (GLOBAL_ONLY && tid == 0) box[c] = make_int4(0, 0, 0, 0);
         if (!GLOBAL_ONLY) {
             const bool tiled = have && in_zone;
             int mn[3], mx[3];
@@ -140,18 +146,30 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
                 for (int a = 0; a < 3; ++a) ext[a] = hi[a] - lo[a] + 1;
                 nt = ext[0] * ext[1] * ext[2];
             }
-            if (nt > CT || nt > 27 * count) nt = -1;  // no room: the chunk goes to global atomics
+            // no room in the tile or in this workgroup's staging slice: the chunk goes to global atomics
+            if (nt > CT || used + nt > slice) nt = -1;
+            if (nt < 0 && tid == 0) atomicAdd(&ctl64(ctl)[CTL64_FALLBACK_CHUNKS], 1ull);
+            off = slice0 + used;
+            if (nt > 0) used += nt;
             for (int t = tid; t < nt; t += NT) {
 #pragma unroll
                 for (int ch4 = 0; ch4 < 4; ++ch4) tq[ch4 * CT + t] = 0.0;
             }
             if (tid == 0)
-                box[c] = nt > 0 ? make_int2(lo[0] | (lo[1] << 10) | (lo[2] << 20), ext[0] | (ext[1] << 8) | (ext[2] << 16))
-                                : make_int2(0, 0);
+                box[c] = nt > 0 ? make_int4(lo[0] | (lo[1] << 10) | (lo[2] << 20), ext[0] | (ext[1] << 8) | (ext[2] << 16),
+                                            off, 0)
+                                : make_int4(0, 0, 0, 0);
             __syncthreads();
         }
 
         // ---- phase 2: scatter
+        {
+            const unsigned long long g = __ballot(have && ok && (GLOBAL_ONLY || !in_zone || nt <= 0));
+            if (g && lane == 0) atomicAdd(&ctl64(ctl)[CTL64_GLOBAL_PARTICLES], (unsigned long long)__popcll(g));
+            // in-zone particles that lost the tile: a rebuild would shrink their chunk's box again
+            const unsigned long long fb = __ballot(have && ok && !GLOBAL_ONLY && in_zone && nt <= 0);
+            if (fb && lane == 0) atomicAdd(&ctl[CTL_FB + parity], (int)__popcll(fb));
+        }
         if (have && ok) {
             if (!GLOBAL_ONLY && in_zone && nt > 0) {
                 const int tb = (st.base[0] - lo[0]) + ext[0] * ((st.base[1] - lo[1]) + ext[1] * (st.base[2] - lo[2]));
@@ -210,7 +228,7 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
         // ---- store the tile to the chunk's staging slot
         if (!GLOBAL_ONLY) {
             __syncthreads();
-            float4* slot = stage + 27 * (int64_t)ch.start;
+            float4* slot = stage + off;
             for (int t = tid; t < nt; t += NT)
                 slot[t] = make_float4((float)(tq[t] * (double)M.mp), (float)tq[CT + t], (float)tq[2 * CT + t],
                                       (float)tq[3 * CT + t]);
@@ -223,12 +241,14 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
 }  // namespace
 
 int p2g_grid_size(int cus, int chunk) {
-    int occ = 0;
-    const void* fn = chunk <= 256 ? reinterpret_cast<const void*>(k_p2g<false, 256>)
-                                  : reinterpret_cast<const void*>(k_p2g<false, 512>);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, chunk <= 256 ? 256 : 512, 0) != hipSuccess || occ <= 0)
-        occ = 1;
-    if (occ > 8) occ = 8;
+    const int nt = chunk_threads(chunk);
+    const void* fn = nt == 128   ? reinterpret_cast<const void*>(k_p2g<false, 128>)
+                     : nt == 256 ? reinterpret_cast<const void*>(k_p2g<false, 256>)
+                                 : reinterpret_cast<const void*>(k_p2g<false, 512>);
+    // Twice the resident workgroups: chunks differ in size, and a second wave
+    // of workgroups evens out the per-XCD work split.
+    int occ = 2 * wgs_per_cu(fn, nt);
+    if (occ > 4096 / nt) occ = 4096 / nt;
     const int g = cus * occ;
     return g < 8 ? 8 : (g / 8) * 8;
 }
@@ -238,8 +258,11 @@ void enqueue_p2g(hipStream_t st, const Launch& L, const Step& P, const Mat& M, f
                  int global_atomics, int nbricks, int chunk) {
 #define MPM_LAUNCH_P2G(GO, T)                                                                                \
     hipLaunchKernelGGL((k_p2g<GO, T>), dim3(L.p2g_grid), dim3(T), 0, st, S, cap, chunks, ctl, G.acc, G.stage, \
-                       G.box, brick_state, G.ovf[parity], parity, P, M, pending, nbricks)
-    if (chunk <= 256) {
+                       G.stage_nodes, G.box, brick_state, G.ovf[parity], parity, P, M, pending, nbricks)
+    const int nt = chunk_threads(chunk);
+    if (nt == 128) {
+        if (global_atomics) MPM_LAUNCH_P2G(true, 128); else MPM_LAUNCH_P2G(false, 128);
+    } else if (nt == 256) {
         if (global_atomics) MPM_LAUNCH_P2G(true, 256); else MPM_LAUNCH_P2G(false, 256);
     } else {
         if (global_atomics) MPM_LAUNCH_P2G(true, 512); else MPM_LAUNCH_P2G(false, 512);

@@ -36,9 +36,9 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, float4* __
                                              const int* __restrict__ active, int* __restrict__ ctl,
                                              const int* __restrict__ ovf, int* __restrict__ brick_state,
                                              int* __restrict__ stamp, const int* __restrict__ gindex,
-                                             const int* __restrict__ gchunk, const Chunk* __restrict__ chunks,
-                                             const float4* __restrict__ stage, const int2* __restrict__ box,
-                                             int parity, int step, int nbricks, Step P) {
+                                             const int* __restrict__ gchunk, const float4* __restrict__ stage,
+                                             const int4* __restrict__ box, int parity, int step, int nbricks,
+                                             Step P) {
     const int nact = ctl[CTL_NACTIVE];
     const int total = nact + min(ctl[CTL_OVF + parity], nbricks - nact);
     const int lane = threadIdx.x & 63;
@@ -83,20 +83,15 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, float4* __
             }
             __builtin_amdgcn_wave_barrier();
             const int m = min(64, total_c - base);
-            int2 bb = make_int2(0, 0);
-            int st0 = 0;
-            if (lane < m) {
-                const int c = list[lane];
-                bb = box[c];
-                st0 = chunks[c].start;
-            }
+            int4 bb = make_int4(0, 0, 0, 0);
+            if (lane < m) bb = box[list[lane]];
             __builtin_amdgcn_wave_barrier();
             for (int i = 0; i < m; ++i) {
-                const int bx_ = __shfl(bb.x, i, 64), by_ = __shfl(bb.y, i, 64), s_ = __shfl(st0, i, 64);
+                const int bx_ = __shfl(bb.x, i, 64), by_ = __shfl(bb.y, i, 64), s_ = __shfl(bb.z, i, 64);
                 const int e0 = by_ & 255, e1 = (by_ >> 8) & 255, e2 = by_ >> 16;
                 const int r0 = g[0] - (bx_ & 1023), r1 = g[1] - ((bx_ >> 10) & 1023), r2 = g[2] - (bx_ >> 20);
                 if (r0 >= 0 && r0 < e0 && r1 >= 0 && r1 < e1 && r2 >= 0 && r2 < e2) {
-                    const float4 sv = stage[27 * (int64_t)s_ + r0 + e0 * (r1 + e1 * r2)];
+                    const float4 sv = stage[s_ + r0 + e0 * (r1 + e1 * r2)];
                     a.x += sv.x;
                     a.y += sv.y;
                     a.z += sv.z;
@@ -141,7 +136,10 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, float4* __
             if (it >= nact) brick_state[b] = 0;
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctl[CTL_OVF + (parity ^ 1)] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl[CTL_OVF + (parity ^ 1)] = 0;
+        ctl[CTL_FB + (parity ^ 1)] = 0;
+    }
 }
 
 // -------------------------------------------------------------------- G2P
@@ -149,15 +147,19 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, float4* __
 // substep (box[c]); the grid velocities of that box are loaded once, coalesced,
 // into LDS and the 27-node gathers read LDS.  Particles whose stencil leaves
 // the box gather from the dense grid.
+// The free-zone test sets the rebuild request; so does a P2G that had to
+// send more than `fb_limit` in-zone particles to global atomics because
+// their chunk's box outgrew the tile (a rebuild shrinks the boxes again).
 constexpr int G2P_BOX = 512;
 
-template <bool LDS_BOX>
-__global__ __launch_bounds__(WG) void k_g2p(float* __restrict__ S, int64_t cap, const Chunk* __restrict__ chunks,
+template <bool LDS_BOX, int NT>
+__global__ __launch_bounds__(NT) void k_g2p(float* __restrict__ S, int64_t cap, const Chunk* __restrict__ chunks,
                                             int* __restrict__ ctl, const float4* __restrict__ vel,
-                                            const int2* __restrict__ box, int* __restrict__ host_flag, Step P) {
+                                            const int4* __restrict__ box, int* __restrict__ host_flag, int parity,
+                                            int fb_limit, Step P) {
     __shared__ float4 tv[LDS_BOX ? G2P_BOX : 1];
     unsigned err = 0;
-    bool left = false;
+    bool left = blockIdx.x == 0 && threadIdx.x == 0 && ctl[CTL_FB + parity] > fb_limit;
     int begin, end, stride;
     xcd_split(ctl[CTL_NCHUNK], begin, end, stride);
     const float c4 = 4.0f * P.fn;  // (4/dx^2) * dx
@@ -167,7 +169,7 @@ __global__ __launch_bounds__(WG) void k_g2p(float* __restrict__ S, int64_t cap, 
         const int B[3] = {ch.block & 1023, (ch.block >> 10) & 1023, ch.block >> 20};
         int lo[3] = {0, 0, 0}, e[3] = {0, 0, 0}, nt = 0;
         if (LDS_BOX) {
-            const int2 bb = box[c];
+            const int4 bb = box[c];
             e[0] = bb.y & 255;
             e[1] = (bb.y >> 8) & 255;
             e[2] = bb.y >> 16;
@@ -176,14 +178,14 @@ __global__ __launch_bounds__(WG) void k_g2p(float* __restrict__ S, int64_t cap, 
             lo[2] = bb.x >> 20;
             nt = e[0] * e[1] * e[2];
             if (nt > G2P_BOX) nt = 0;
-            for (int t = threadIdx.x; t < nt; t += WG) {
+            for (int t = threadIdx.x; t < nt; t += NT) {
                 const int gx = lo[0] + t % e[0], gy = lo[1] + (t / e[0]) % e[1], gz = lo[2] + t / (e[0] * e[1]);
                 tv[t] = vel[((((gz >> 2) + 1) * NB + ((gy >> 2) + 1)) * NB + ((gx >> 2) + 1)) * 64 + (gx & 3) +
                             ((gy & 3) << 2) + ((gz & 3) << 4)];
             }
             __syncthreads();
         }
-        for (int i = threadIdx.x; i < ch.count; i += WG) {
+        for (int i = threadIdx.x; i < ch.count; i += NT) {
             const int p = ch.start + i;
             float x[3];
 #pragma unroll
@@ -364,38 +366,74 @@ __global__ __launch_bounds__(WG) void k_read_grid(const float4* __restrict__ vel
 
 }  // namespace
 
+int wgs_per_cu(const void* fn, int threads) {
+    int dev = 0, lds_cu = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+        lds_cu <= 0)
+        lds_cu = 160 * 1024;
+    hipFuncAttributes a;
+    if (hipFuncGetAttributes(&a, fn) != hipSuccess) return 2;
+    const int waves = (threads + 63) / 64;
+    const int vgpr = a.numRegs > 0 ? (a.numRegs + 7) / 8 * 8 : 512;
+    int per_simd = 512 / vgpr;
+    if (per_simd > 8) per_simd = 8;
+    int occ = per_simd * 4 / waves;
+    if (a.sharedSizeBytes > 0) {
+        const int by_lds = lds_cu / (int)a.sharedSizeBytes;
+        if (by_lds < occ) occ = by_lds;
+    }
+    return occ < 1 ? 1 : occ;
+}
+
+namespace {
+const void* g2p_fn(bool lds_box, int nt) {
+    if (lds_box)
+        return nt == 128   ? reinterpret_cast<const void*>(k_g2p<true, 128>)
+               : nt == 256 ? reinterpret_cast<const void*>(k_g2p<true, 256>)
+                           : reinterpret_cast<const void*>(k_g2p<true, 512>);
+    return nt == 128   ? reinterpret_cast<const void*>(k_g2p<false, 128>)
+           : nt == 256 ? reinterpret_cast<const void*>(k_g2p<false, 256>)
+                       : reinterpret_cast<const void*>(k_g2p<false, 512>);
+}
+}  // namespace
+
 void query_launch(Launch& L, int chunk) {
     int dev = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&L.cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (L.cus <= 0) L.cus = 256;
-    auto grid_for = [&](const void* fn, int cap_per_cu) {
-        int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, WG, 0) != hipSuccess || occ <= 0) occ = 2;
+    auto grid_for = [&](const void* fn, int threads, int cap_per_cu) {
+        int occ = wgs_per_cu(fn, threads);
         occ = occ > cap_per_cu ? cap_per_cu : occ;
-        int g = L.cus * occ;
+        const int g = L.cus * occ;
         return g < 8 ? 8 : (g / 8) * 8;
     };
+    const int nt = chunk_threads(chunk);
     L.p2g_grid = p2g_grid_size(L.cus, chunk);
-    L.g2p_grid = grid_for(reinterpret_cast<const void*>(k_g2p<true>), 8);
-    L.grid_grid = grid_for(reinterpret_cast<const void*>(k_grid), 8);
+    L.g2p_grid = grid_for(g2p_fn(true, nt), nt, 8 * 256 / nt);
+    L.grid_grid = grid_for(reinterpret_cast<const void*>(k_grid), WG, 8);
 }
 
 void enqueue_grid(hipStream_t st, const Launch& L, const Step& P, const BinBuffers& B, int* ctl, GridBuffers& G,
                   int parity, int step) {
     hipLaunchKernelGGL(k_grid, dim3(L.grid_grid), dim3(WG), 0, st, G.acc, G.vel, B.active, ctl, G.ovf[parity],
-                       B.brick_state, G.stamp, B.gindex, B.gchunk, B.chunks, G.stage, G.box, parity, step,
+                       B.brick_state, G.stamp, B.gindex, B.gchunk, G.stage, G.box, parity, step,
                        P.NB * P.NB * P.NB, P);
 }
 
 void enqueue_g2p(hipStream_t st, const Launch& L, const Step& P, float* S, int64_t cap, const Chunk* chunks, int* ctl,
-                 const GridBuffers& G, int* host_flag, int lds_box) {
-    if (lds_box)
-        hipLaunchKernelGGL(k_g2p<true>, dim3(L.g2p_grid), dim3(WG), 0, st, S, cap, chunks, ctl, G.vel, G.box, host_flag,
-                           P);
-    else
-        hipLaunchKernelGGL(k_g2p<false>, dim3(L.g2p_grid), dim3(WG), 0, st, S, cap, chunks, ctl, G.vel, G.box,
-                           host_flag, P);
+                 const GridBuffers& G, int* host_flag, int lds_box, int parity, int fb_limit, int chunk) {
+#define MPM_LAUNCH_G2P(LB, T)                                                                                   \
+    hipLaunchKernelGGL((k_g2p<LB, T>), dim3(L.g2p_grid), dim3(T), 0, st, S, cap, chunks, ctl, G.vel, G.box, host_flag, \
+                       parity, fb_limit, P)
+    const int nt = chunk_threads(chunk);
+    if (lds_box) {
+        if (nt == 128) MPM_LAUNCH_G2P(true, 128); else if (nt == 256) MPM_LAUNCH_G2P(true, 256); else MPM_LAUNCH_G2P(true, 512);
+    } else {
+        if (nt == 128) MPM_LAUNCH_G2P(false, 128); else if (nt == 256) MPM_LAUNCH_G2P(false, 256); else MPM_LAUNCH_G2P(false, 512);
+    }
+#undef MPM_LAUNCH_G2P
 }
 
 void enqueue_materialize(hipStream_t st, const Step& P, const Mat& M, float* S, int64_t cap, int N) {

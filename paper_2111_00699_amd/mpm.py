@@ -40,7 +40,8 @@ class Material(ct.Structure):
 class Stats(ct.Structure):
     _fields_ = [(k, ct.c_int64) for k in ("num_particles", "capacity", "substeps", "rebuilds", "gblocks",
                                           "active_blocks", "chunks", "overflow_blocks")] + \
-               [("error", ct.c_uint32), ("pending_update", ct.c_uint32)]
+               [("error", ct.c_uint32), ("pending_update", ct.c_uint32)] + \
+               [("p2g_fallback_chunks", ct.c_int64), ("p2g_global_particles", ct.c_int64)]
 
 
 class ProfileData(ct.Structure):

@@ -142,15 +142,16 @@ MATS = {"jelly": (scenes.JELLY, "sticky"), "snow": (scenes.SNOW, "separate"), "w
 
 
 @pytest.mark.parametrize("kind", ["jelly", "snow", "water"])
-@pytest.mark.parametrize("mode", ["tile", "global", "every_step", "sorted_lanes", "g2p_global"])
+@pytest.mark.parametrize("mode", ["tile", "global", "every_step", "sorted_lanes", "g2p_global", "chunk128", "chunk512"])
 def test_single_substep_matches_oracle(torch_cuda, oracle, kind, mode):
     mat, bc = MATS[kind]
     sc = scenes.jelly_cube(0)
     st = scenes.nontrivial_state(sc["x"], seed=5, kind=kind)
     cfg = dict(n=64, dt=1e-4, bc=bc)
-    flags = {"tile": 0, "global": 0x2, "every_step": 0x1, "sorted_lanes": 0x8, "g2p_global": 0x10}[mode]
+    flags = {"global": 0x2, "every_step": 0x1, "sorted_lanes": 0x8, "g2p_global": 0x10}.get(mode, 0)
+    chunk = {"chunk128": 128, "chunk512": 512}.get(mode, 0)
     print_case("substep1", kind=kind, mode=mode, N=st["x"].shape[1])
-    sim = make_sim(torch_cuda, cfg, flags=flags)
+    sim = make_sim(torch_cuda, cfg, flags=flags, chunk=chunk)
     sim.add_particles(mat, st["x"], v=st["v"], C=st["C"], F=st.get("F"), s=st.get("s"))
     sim.substep(1)
     gs = gpu_state(sim)
@@ -258,6 +259,31 @@ def test_out_of_free_zone_without_rebuild(torch_cuda, oracle):
     assert stats["overflow_blocks"] > 0
     gs = gpu_state(sim)
     os_, _, _, bad = oracle.substep(cfg, mat, st, steps=40)
+    assert bad == 0
+    compare_state(gs, os_, "jelly", tol=2e-4)
+    sim.close()
+
+
+def test_expanding_cloud_overflows_tiles(torch_cuda, oracle):
+    """A cube expanding at 50/s with rebuilds switched off: blocks spread to
+    twice their width, chunk boxes outgrow the LDS tile and whole chunks fall
+    back to global atomics, while the result still matches the oracle."""
+    sc = scenes.jelly_cube(0)
+    st = scenes.nontrivial_state(sc["x"], seed=13)
+    st["v"] = (50.0 * (st["x"] - np.float32(0.5)) + 0.05 * st["v"]).astype(np.float32)
+    st["C"] = (np.eye(3, dtype=np.float32).reshape(9, 1) * np.float32(50.0) + 0.01 * st["C"]).astype(np.float32)
+    mat = dict(scenes.JELLY, E=1.0)  # nearly free expansion
+    cfg = dict(n=64, dt=5e-4, gravity=(0, 0, 0))
+    print_case("expanding", N=st["x"].shape[1])
+    sim = make_sim(torch_cuda, cfg, flags=0x4)
+    sim.add_particles(mat, st["x"], v=st["v"], C=st["C"], F=st["F"])
+    sim.substep(30)
+    stats = sim.stats()
+    assert stats["rebuilds"] == 1
+    assert stats["p2g_fallback_chunks"] > 0, stats
+    assert stats["p2g_global_particles"] > 0, stats
+    gs = gpu_state(sim)
+    os_, _, _, bad = oracle.substep(cfg, mat, st, steps=30)
     assert bad == 0
     compare_state(gs, os_, "jelly", tol=2e-4)
     sim.close()
