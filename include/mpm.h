@@ -28,6 +28,11 @@
  *     ignored for jelly).
  *   - A context is single-threaded: do not call into one context from two
  *     threads at once.  Different contexts are independent.
+ *   - A context holds 1..256 independent scenes (config.num_scenes).  Each
+ *     scene has its own grid, time step, material and particles; a batched
+ *     context advances all of them with one launch per phase per substep
+ *     (the particle code carries the scene in its top bits, so one sort and
+ *     one work list cover every scene).
  *   - Faults the device detects (non-finite state, a particle stencil
  *     leaving the grid, capacity exceeded) set a sticky error word; the next
  *     mpm_read_* or mpm_get_stats call returns MPM_ESTATE, and the word stays
@@ -70,12 +75,29 @@ typedef enum { MPM_BC_STICKY = 0, MPM_BC_SLIP = 1, MPM_BC_SEPARATE = 2 } mpm_bc;
                                             copy of the chunk's node box */
 #define MPM_FLAG_P2G_SORTED_LANES 0x8u   /* store each chunk in plain sorted order instead of the
                                             strided order that spreads a wave over cells */
+#define MPM_FLAG_FRAME_GRAPHS 0x20u      /* mpm_frame records a whole frame (one rebuild at its start, then
+                                            every scene's substeps) as a HIP graph per particle-buffer
+                                            parity and replays it; within a frame the free-zone flag is not
+                                            read (particles that leave their zone transfer through global
+                                            atomics).  Needs config.stream != 0.  A graph is recorded again
+                                            after mpm_add_particles, a new frame_dt or a new chunk size. */
+
+#define MPM_MAX_SCENES 256
+
+/* Grid and time step of one scene of a batched context. */
+typedef struct {
+    int32_t n;        /* cells per axis, power of two in [16, 512] */
+    int32_t bc;       /* mpm_bc */
+    int32_t bc_cells; /* wall thickness in cells */
+    float gravity[3];
+    float dt;         /* substep length of this scene (> 0) */
+} mpm_scene;
 
 typedef struct {
     int32_t n;          /* cells per axis on the unit cube; power of two, 16 <= n <= 512; dx = 1/n */
     int32_t bc;         /* mpm_bc applied on nodes with a coordinate < bc_cells or > n - bc_cells */
     int32_t bc_cells;   /* wall thickness in cells (>= 0) */
-    int32_t num_scenes; /* must be 1 */
+    int32_t num_scenes; /* 1..MPM_MAX_SCENES; with S scenes and largest n = 2^L, 3L + ceil(log2 S) <= 32 */
     float gravity[3];   /* m/s^2 */
     float dt;           /* substep length in seconds (> 0) */
     int64_t capacity;   /* initial particle reservation; grows 4x when more than half full */
@@ -85,6 +107,8 @@ typedef struct {
                            rebuild flag (1..64; 0 selects the default 3) */
     int32_t chunk;      /* particles per P2G/G2P work chunk: 64..512, multiple of 64 (0 = 256) */
     int32_t reserved;
+    const mpm_scene* scenes; /* num_scenes descriptors (copied), or NULL: every scene takes n, bc,
+                                bc_cells, gravity and dt from this struct */
 } mpm_config;
 
 /* Material constants.  Lame parameters mu = E/(2(1+nu)), lambda = E nu/((1+nu)(1-2nu));
@@ -114,6 +138,8 @@ typedef struct {
                                      scattered with global atomics                          */
     int64_t p2g_global_particles; /* particle transfers done with global atomics (particles outside
                                      their free zone, plus those of fallback chunks)        */
+    int64_t surrogate_particles;  /* snow return maps done without SVD (mpm_use_surrogate)  */
+    int64_t surrogate_fallbacks;  /* ... that fell back to the exact map                    */
 } mpm_stats;
 
 /* Phases that mpm_profile can bracket with HIP events. */
@@ -127,33 +153,39 @@ typedef struct {
     double ms[4];        /* summed event-measured device time per phase */
 } mpm_profile_data;
 
-/* Create a context on the current HIP device.  cfg is copied.  Fails with
- * MPM_EINVAL on a bad field, MPM_ENOMEM if the dense block grid
- * ((n/4+2)^3 blocks x 64 nodes x 32 B) or the particle buffers do not fit. */
+/* Create a context on the current HIP device.  cfg (and cfg->scenes) is
+ * copied.  Fails with MPM_EINVAL on a bad field, MPM_ENOMEM if the dense
+ * block grids (per scene (n/4+2)^3 blocks x 64 nodes x 32 B) or the particle
+ * buffers do not fit. */
 int mpm_create(const mpm_config* cfg, mpm_ctx** out);
 
 /* Synchronize the stream and free everything the context owns.  NULL is OK. */
 int mpm_destroy(mpm_ctx* ctx);
 
-/* Append `count` particles to `scene` (must be 0).  x_dev is required;
- * v_dev, C_dev, F_dev, s_dev may be NULL (defaults 0, 0, I, 1).  The first
- * call fixes the context's material; later calls must pass the same
- * constants or NULL.  Particles are numbered in insertion order (0, 1, ...),
- * the order mpm_read_particles returns.  Grows capacity 4x when the total
- * exceeds half of it (no other call allocates).  Forces a rebuild before
- * the next substep.  Particle generation ("Fountain": a per-frame source) is
- * done by calling this between substeps.                                    */
+/* Append `count` particles to `scene` (0 <= scene < num_scenes).  x_dev is
+ * required; v_dev, C_dev, F_dev, s_dev may be NULL (defaults 0, 0, I, 1).
+ * The first call for a scene fixes that scene's material; later calls must
+ * pass the same constants or NULL.  Particles of a scene are numbered in
+ * insertion order (0, 1, ...), the order mpm_read_particles returns.  Grows
+ * capacity 4x when the total exceeds half of it (no other call allocates,
+ * except graph recording in mpm_frame).  Forces a rebuild before the next
+ * substep.  Particle generation ("Fountain": a per-frame source) is done by
+ * calling this between substeps.                                            */
 int mpm_add_particles(mpm_ctx* ctx, int32_t scene, const mpm_material* mat, int64_t count,
                       const float* x_dev, const float* v_dev, const float* C_dev, const float* F_dev,
                       const float* s_dev);
 
-/* Enqueue `nsteps` substeps.  Each is: [rebuild-mapping + sort when a particle
- * left its free zone] -> P2G -> grid update -> G2P.  The host waits for the
- * device only to keep at most `lag` substeps in flight, so that it can read
- * the device's rebuild flag; it never drains the stream.                    */
+/* Enqueue `nsteps` substeps of every scene.  Each is: [rebuild-mapping + sort
+ * when a particle left its free zone] -> P2G -> grid update -> G2P, one launch
+ * per phase for all scenes.  The host waits for the device only to keep at
+ * most `lag` substeps in flight, so that it can read the device's rebuild
+ * flag; it never drains the stream.                                         */
 int mpm_substep(mpm_ctx* ctx, int32_t nsteps);
 
-/* Advance one frame: ceil(frame_dt/dt) substeps (frame_dt > 0).          */
+/* Advance one frame (frame_dt > 0): scene s runs ceil(frame_dt/dt_s)
+ * substeps.  The frame takes as many launches per phase as the longest
+ * scene needs; scenes that are done sit out the remaining launches.  With
+ * MPM_FLAG_FRAME_GRAPHS the frame is a replayed HIP graph.                  */
 int mpm_frame(mpm_ctx* ctx, float frame_dt);
 
 /* Force rebuild-mapping and sorting before the next substep.              */
@@ -163,40 +195,63 @@ int mpm_rebuild(mpm_ctx* ctx);
 int mpm_synchronize(mpm_ctx* ctx);
 
 /* Copy the particles of `scene` into caller device arrays, in insertion
- * order.  count must equal the number of particles.  Any output may be
+ * order.  count must equal the scene's particle count.  Any output may be
  * NULL.  F/s are the state after the last G2P's deformation update (the
  * update is applied on the fly when it is still deferred).  Synchronizes.  */
 int mpm_read_particles(mpm_ctx* ctx, int32_t scene, int64_t count, float* x_dev, float* v_dev, float* C_dev,
                        float* F_dev, float* s_dev);
 
-/* Dense view of the grid of the last substep (test/debug use): m_dev
- * [(n+1)^3] node masses and v_dev [3][(n+1)^3] updated node velocities,
+/* Dense view of the scene's grid after its last substep (test/debug use):
+ * m_dev [(n+1)^3] node masses and v_dev [3][(n+1)^3] updated node velocities,
  * node (i,j,k) at ((i*(n+1))+j)*(n+1)+k, i along x.  Nodes the last substep
  * did not touch read as zero.  Either pointer may be NULL.  Synchronizes.  */
 int mpm_read_grid(mpm_ctx* ctx, int32_t scene, float* m_dev, float* v_dev);
 
-/* The binning of the last rebuild: keys_dev[count] the sorted particle
- * codes and perm_dev[count] the insertion index of the particle at each
+/* The binning of the scene at the last rebuild: keys_dev[count] the sorted
+ * particle codes (the scene's Morton code, without scene bits) and
+ * perm_dev[count] the scene-local insertion index of the particle at each
  * sorted position (a stable sort: ties keep their storage order before the
- * rebuild).  Storage layout after a rebuild: geometric blocks in code order,
+ * rebuild).  Storage layout after a rebuild: scenes in order of increasing dt
+ * (ties by scene index), inside a scene geometric blocks in code order,
  * each cut into chunks of config.chunk particles; inside a chunk of c
  * particles, slot t holds sorted position (t*K) mod c with K the smallest of
  * 9, 11, 13, 17 coprime to c (identity with MPM_FLAG_P2G_SORTED_LANES).
- * count must equal the number of particles at the last rebuild.
+ * count must equal the scene's particle count at the last rebuild.
  * Synchronizes.                                                             */
 int mpm_read_binning(mpm_ctx* ctx, int32_t scene, int64_t count, uint32_t* keys_dev, int32_t* perm_dev);
 
-/* Blocks of the last rebuild (host arrays, sized by mpm_get_stats):
- * gcode[gblocks] block codes (particle code >> 6) ascending, gstart/gcount
- * their sorted-particle ranges, active[active_blocks] the physical blocks
- * as padded linear codes ((bz*NB)+by)*NB+bx with b = block coordinate + 1
- * and NB = n/4 + 2, ascending.  Any pointer may be NULL.  Synchronizes.     */
+/* Blocks of the scene at the last rebuild (host arrays, sized by
+ * mpm_get_scene_stats): gcode[gblocks] block codes (particle code >> 6)
+ * ascending, gstart/gcount their ranges in the scene's sorted order,
+ * active[active_blocks] the physical blocks as padded linear codes
+ * ((bz*NB)+by)*NB+bx with b = block coordinate + 1 and NB = n/4 + 2,
+ * ascending.  Any pointer may be NULL.  Synchronizes.                       */
 int mpm_read_blocks(mpm_ctx* ctx, int32_t scene, uint32_t* gcode, int32_t* gstart, int32_t* gcount,
                     int32_t* active);
 
-/* Synchronize and report counters.  Returns MPM_ESTATE if the error word is set
- * (the struct is still filled).                                             */
+/* Synchronize and report counters (totals over all scenes).  Returns
+ * MPM_ESTATE if the error word is set (the struct is still filled).         */
 int mpm_get_stats(mpm_ctx* ctx, mpm_stats* out);
+
+typedef struct {
+    int64_t num_particles;
+    int64_t substeps;      /* substeps this scene has taken */
+    int64_t gblocks;       /* at the last rebuild */
+    int64_t active_blocks; /* at the last rebuild */
+    int32_t n;
+    float dt;
+} mpm_scene_stats;
+
+/* Per-scene counters.  Synchronizes.                                        */
+int mpm_get_scene_stats(mpm_ctx* ctx, int32_t scene, mpm_scene_stats* out);
+
+/* Pick the chunk size (particles per P2G/G2P workgroup: 128, 256 or 512)
+ * that advances the current state fastest: each candidate runs `frames`
+ * frames of frame_dt from a device copy of the current state, timed with
+ * HIP events; the state and counters are then restored and the winner kept
+ * (written to *chunk_out if not NULL).  The copy takes one more particle
+ * buffer of device memory for the duration of the call.  Synchronizes.     */
+int mpm_autotune(mpm_ctx* ctx, float frame_dt, int32_t frames, int32_t* chunk_out);
 
 /* Clear the sticky device error word.                                      */
 int mpm_clear_error(mpm_ctx* ctx);
@@ -213,6 +268,73 @@ int mpm_profile_read(mpm_ctx* ctx, mpm_profile_data* out);
 /* Message for the last failed call on ctx (or of mpm_create when ctx is
  * NULL).  Owned by the library; valid until the next call on that context. */
 const char* mpm_last_error(const mpm_ctx* ctx);
+
+/* ------------------------------------------------ learned snow surrogate
+ * An MLP 12 -> 64 -> 64 -> 12 (tanh hidden layers, linear output) standing
+ * in for the snow return map and stress in principal space.  Inputs, for
+ * trial singular values s (descending) and plastic volume J_P:
+ *   [s1..s3, ln s1..s3, J_P, ln J_P, exp(xi (1 - J_P)), dt/dt_ref, s1 s2 s3, 1]
+ * targets: [s'1..s'3, ln(s'/s)1..3, tau1..3 / E, J_P'/J_P, exp(xi (1 - J_P')), s'1 s'2 s'3]
+ * with s' the projected singular values and tau the principal Kirchhoff
+ * stress.  The network works on z-scored inputs and targets (means and
+ * standard deviations held with the parameters).  Rows are [count][12] FP32.
+ * Parameters: flat FP32 [W1 (64x12), b1, W2 (64x64), b2, W3 (12x64), b3],
+ * weights row-major (output, input).  All pointers are device pointers. */
+typedef struct mpm_surrogate mpm_surrogate;
+
+#define MPM_SUR_IN 12
+#define MPM_SUR_OUT 12
+#define MPM_SUR_PARAMS 5772
+#define MPM_SUR_NORM 48 /* input means, input sds, output means, output sds (12 each) */
+#define MPM_SUR_FP32 0  /* FP32 operands (gradient checking) */
+#define MPM_SUR_BF16 1  /* BF16 operands, FP32 accumulation (MFMA) */
+
+/* Create on the current device, work enqueued on `stream` (0 = null
+ * stream).  Parameters start at zero and the normalisation at identity. */
+int mpm_surrogate_create(uint64_t stream, mpm_surrogate** out);
+int mpm_surrogate_destroy(mpm_surrogate* s);
+/* Copy parameters / normalisation in or out; either pointer may be NULL. */
+int mpm_surrogate_set(mpm_surrogate* s, const float* theta_dev, const float* norm_dev);
+int mpm_surrogate_get(mpm_surrogate* s, float* theta_dev, float* norm_dev);
+/* Y = network(X) in physical (de-normalised) units.                          */
+int mpm_surrogate_forward(mpm_surrogate* s, int32_t precision, int64_t count, const float* X_dev, float* Y_dev);
+/* Mean over the rows of 1/2 |y~ - t~|^2 in z-scored units into loss_dev[0]
+ * and its gradient into grad_dev[MPM_SUR_PARAMS].                          */
+int mpm_surrogate_loss_grad(mpm_surrogate* s, int32_t precision, int64_t count, const float* X_dev,
+                            const float* T_dev, float* grad_dev, float* loss_dev);
+/* Set the normalisation to the column means and standard deviations
+ * (floored at 1e-6) of X and T.                                             */
+int mpm_surrogate_fit_norm(mpm_surrogate* s, int64_t count, const float* X_dev, const float* T_dev);
+/* `steps` Adam steps (lr, betas 0.9 / 0.999, eps 1e-8; the step counter
+ * continues across calls) on minibatches of `batch` rows drawn uniformly
+ * with replacement by a counter-based generator (splitmix64 of seed, step
+ * and row), BF16 MFMA forward/backward.  loss_host (may be NULL) receives the
+ * minibatch loss of every step.  Synchronizes.                            */
+int mpm_surrogate_train(mpm_surrogate* s, int64_t count, const float* X_dev, const float* T_dev, int32_t steps,
+                        int32_t batch, float lr, uint64_t seed, float* loss_host);
+/* Training pairs from the current state of a snow scene: for every particle
+ * (in storage order), the trial state of its next return map (the deferred
+ * deformation update applied) through the exact return map, as inputs and
+ * targets above.  Writes min(particles, max_count) rows; *written gets the
+ * count.                                                                    */
+/* Choose how P2G maps a snow scene's trial state (mode):
+ *   0  exact: singular values by Jacobi rotations, clamp, stress (default);
+ *   1  the surrogate s predicts the projected singular values (as ln(s'/s)),
+ *      the principal stress and J_P'/J_P; F_E' and tau are rebuilt from the
+ *      eigenvalues of F^ F^T by Sylvester's formula (no eigenvectors);
+ *   2  the same eigenvector-free path with the exact clamp instead of the
+ *      network (the method without the network).
+ * Modes 1 and 2 fall back to mode 0 per particle when two eigenvalues of
+ * F^ F^T are closer than 0.1 of their spread or the particle is inverted;
+ * mode 1 also when a predicted singular value leaves [1 - theta_c,
+ * 1 + theta_s] by more than tol or the total volume J_P det F_E changes by
+ * more than tol (log).  dt_ref: the time step the surrogate was trained at.
+ * The surrogate must outlive its use by ctx; one surrogate per context (the
+ * last one passed).  Counts go to mpm_stats.surrogate_*.                   */
+int mpm_use_surrogate(mpm_ctx* ctx, int32_t scene, const mpm_surrogate* s, int32_t mode, float tol, float dt_ref);
+
+int mpm_surrogate_sample(mpm_ctx* ctx, int32_t scene, float dt_ref, int64_t max_count, float* X_dev, float* T_dev,
+                         int64_t* written);
 
 #ifdef __cplusplus
 }

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmpm.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["mpm_bin.hip", "mpm_p2g.hip", "mpm_step.hip", "mpm_api.hip"]
+SOURCES = ["mpm_bin.hip", "mpm_p2g.hip", "mpm_step.hip", "mpm_surrogate.hip", "mpm_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",

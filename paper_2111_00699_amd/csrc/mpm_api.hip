@@ -3,7 +3,8 @@
 // Capacity: particle buffers grow 4x once more than half full, and only in
 // mpm_add_particles (paper, "Principles": a vector that reserves ahead
 // avoids reallocation during the simulation; scan/sort scratch is allocated
-// up front).  The dense block grid is allocated once at creation.
+// up front).  The dense block grids of all scenes are allocated once at
+// creation, in one brick space laid out in rank order.
 //
 // Rebuild scheduling without draining the stream: G2P sets a device flag when
 // a particle leaves its free zone and, the first time, writes it to a pinned
@@ -13,13 +14,23 @@
 // substeps queued.  A particle that leaves its free zone before the rebuild
 // lands is still transferred exactly (through global atomics), so the lag
 // costs speed, never correctness.
+//
+// Batched scenes: every scene is a rank in one particle-code order, so each
+// phase of a substep is one launch over all scenes; a frame gives scene s
+// ceil(frame_dt / dt_s) substeps, and because ranks follow increasing dt the
+// scenes still running at a given substep of the frame are a prefix of the
+// ranks (`act`).  With MPM_FLAG_FRAME_GRAPHS a frame -- rebuild, then all
+// substeps -- is recorded once per particle-buffer parity as a HIP graph and
+// replayed.
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
 #include "mpm_internal.h"
+#include "mpm_surrogate.h"
 
 using namespace mpm;
 
@@ -30,16 +41,39 @@ constexpr int PROF_SLOTS = 4096;
 
 std::string g_create_error;
 
+struct SceneHost {
+    mpm_scene desc{};
+    mpm_material mat{};
+    bool has_mat = false;
+    int64_t N = 0;             // particles of the scene
+    int64_t N_at_rebuild = 0;  // ... at the last rebuild
+    int64_t substeps = 0;
+    int64_t last_step = -2;    // index of its last substep (stamp of the blocks it updated)
+};
+
+struct FrameGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t N = -1;
+    float frame_dt = 0.0f;
+    int chunk = 0;
+};
+
 }  // namespace
 
 struct mpm_ctx {
     mpm_config cfg{};
     hipStream_t stream = nullptr;
     int device = 0;
-    Step P{};
-    Mat M{};
-    mpm_material mat{};
-    bool has_mat = false;
+    int nsc = 1;                      // scenes
+    std::vector<SceneHost> sh;        // by scene index
+    std::vector<int> rank_scene;      // scene index of each rank
+    std::vector<Scene> table;         // host copy of the device scene table
+    Scene* scene_dev = nullptr;
+    int* rank_scene_dev = nullptr;
+    int* rank_brick_dev = nullptr;    // [S + 1]
+    int* rank_end_dev = nullptr;      // [4 S]
+    int shift = 0, key_bits = 0;
     int nbricks = 0;
     Launch L{};
 
@@ -56,9 +90,16 @@ struct mpm_ctx {
     hipEvent_t ev[RING] = {};
 
     int64_t step = 0, checked = 0, last_rebuild = -1, rebuilds = 0;
+    int64_t parity_ctr = 0;  // parity of the next substep (overflow-list slot)
     int64_t n_at_rebuild = 0;
     bool need_rebuild = true;
     int pending = 0;
+    FrameGraph graphs[2];
+    // snow return map without SVD (see mpm_use_surrogate)
+    const float* sur_theta = nullptr;
+    const float* sur_norm = nullptr;
+    float sur_tol = 1e-3f, sur_dt_ref = 1.0f;
+    int sur_any = 0;
 
     // profiling
     uint32_t prof_mask = 0;
@@ -112,6 +153,46 @@ Mat derive_material(const mpm_material& m, const Step& P) {
 bool same_material(const mpm_material& a, const mpm_material& b) {
     return a.kind == b.kind && a.E == b.E && a.nu == b.nu && a.rho == b.rho && a.ppc == b.ppc &&
            a.theta_c == b.theta_c && a.theta_s == b.theta_s && a.xi == b.xi && a.bulk == b.bulk;
+}
+
+Step make_step(const mpm_scene& d) {
+    Step P{};
+    P.n = d.n;
+    P.NB = d.n / 4 + 2;
+    P.fn = (float)d.n;
+    P.dx = 1.0f / (float)d.n;
+    P.dt = d.dt;
+    P.g0 = d.gravity[0];
+    P.g1 = d.gravity[1];
+    P.g2 = d.gravity[2];
+    P.bc = d.bc;
+    P.bc_cells = d.bc_cells;
+    return P;
+}
+
+const char* check_scene(const mpm_scene& d) {
+    if (d.n < 16 || d.n > 512 || (d.n & (d.n - 1))) return "n must be a power of two in [16, 512]";
+    if (d.bc < 0 || d.bc > 2) return "bad bc";
+    if (d.bc_cells < 0 || d.bc_cells > d.n / 2) return "bad bc_cells";
+    if (!(d.dt > 0.0f)) return "dt must be positive";
+    return nullptr;
+}
+
+int log2i(int v) {
+    int b = 0;
+    while ((1 << b) < v) ++b;
+    return b;
+}
+
+Scenes tables(const mpm_ctx* c) {
+    Scenes T{c->scene_dev, c->rank_scene_dev, c->rank_brick_dev, c->rank_end_dev, c->nsc, c->shift};
+    T.sur_theta = c->sur_theta;
+    T.sur_norm = c->sur_norm;
+    T.sur_tol = c->sur_tol;
+    T.sur_gap = 0.1f;
+    T.sur_dt_ref = c->sur_dt_ref;
+    T.sur_any = c->sur_any;
+    return T;
 }
 
 int scan_tiles_needed(int64_t cap, int nbricks) {
@@ -294,6 +375,65 @@ int poll_flags(mpm_ctx* c, int64_t must_upto) {
     return MPM_OK;
 }
 
+
+void drop_graphs(mpm_ctx* c) {
+    for (auto& g : c->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+        g = FrameGraph{};
+    }
+}
+
+// Substeps each rank takes in a frame of length frame_dt (non-increasing in
+// rank, since ranks follow increasing dt).
+std::vector<int> frame_substeps(const mpm_ctx* c, float frame_dt) {
+    std::vector<int> ns(c->nsc);
+    for (int r = 0; r < c->nsc; ++r) {
+        const double q = (double)frame_dt / (double)c->sh[c->rank_scene[r]].desc.dt;
+        int n = (int)q;
+        if (q - n > 1e-4) ++n;
+        ns[r] = n < 1 ? 1 : n;
+    }
+    return ns;
+}
+
+int active_ranks(const std::vector<int>& ns, int k) {
+    int a = 0;
+    while (a < (int)ns.size() && ns[a] > k) ++a;
+    return a;
+}
+
+// In-zone particles that may lose their chunk's tile in one substep before
+// the next substep asks for a rebuild (1/256 of the particles).  With
+// MPM_FLAG_MANUAL_REBUILD the request is ignored like the free-zone one.
+int fb_limit(const mpm_ctx* c) { return (int)(c->N >> 8); }
+
+void enqueue_rebuild_into_alt(mpm_ctx* c) {
+    enqueue_rebuild(c->stream, tables(c), c->S[c->cur], c->S[c->cur ^ 1], c->ids[c->cur], c->ids[c->cur ^ 1], c->cap,
+                    (int)c->N, c->cfg.chunk, (c->cfg.flags & MPM_FLAG_P2G_SORTED_LANES) ? 0 : 1, c->B, c->ctl,
+                    c->nbricks, c->key_bits);
+}
+
+void note_rebuild(mpm_ctx* c) {
+    c->cur ^= 1;
+    c->need_rebuild = false;
+    c->last_rebuild = c->step;
+    c->n_at_rebuild = c->N;
+    for (auto& s : c->sh) s.N_at_rebuild = s.N;
+    ++c->rebuilds;
+}
+
+void note_substep(mpm_ctx* c, int act) {
+    for (int r = 0; r < act; ++r) {
+        SceneHost& s = c->sh[c->rank_scene[r]];
+        s.substeps += 1;
+        s.last_step = c->step;
+    }
+    c->pending = 1;
+    ++c->step;
+    ++c->parity_ctr;
+}
+
 int check_error_word(mpm_ctx* c) {
     int h[CTL_WORDS];
     HIP_OK(c, hipMemcpyAsync(h, c->ctl, sizeof h, hipMemcpyDeviceToHost, c->stream));
@@ -306,6 +446,118 @@ int check_error_word(mpm_ctx* c) {
     return MPM_OK;
 }
 
+// One substep of the first `act` ranks, enqueued directly (host-lagged
+// rebuild decision, optional phase events).
+int substep_one(mpm_ctx* c, int act) {
+    int r = poll_flags(c, c->step - c->cfg.lag);
+    if (r) return r;
+    int slot;
+    if (c->need_rebuild || (c->cfg.flags & MPM_FLAG_REBUILD_EVERY_STEP)) {
+        if ((r = prof_begin(c, 0, &slot))) return r;
+        enqueue_rebuild_into_alt(c);
+        if ((r = prof_end(c, slot))) return r;
+        note_rebuild(c);
+    }
+    const int rs = (int)(c->step % RING);
+    c->ring[rs] = 0;
+    const int parity = (int)(c->parity_ctr & 1);
+    const Scenes T = tables(c);
+    if ((r = prof_begin(c, 1, &slot))) return r;
+    enqueue_p2g(c->stream, c->L, T, c->S[c->cur], c->cap, c->B.chunks, c->ctl, c->G, c->B.brick_state, c->pending,
+                parity, (c->cfg.flags & MPM_FLAG_P2G_GLOBAL_ATOMICS) ? 1 : 0, c->nbricks, c->cfg.chunk, act);
+    if ((r = prof_end(c, slot))) return r;
+    if ((r = prof_begin(c, 2, &slot))) return r;
+    enqueue_grid(c->stream, c->L, T, c->B, c->ctl, c->G, parity, c->nbricks, act);
+    if ((r = prof_end(c, slot))) return r;
+    if ((r = prof_begin(c, 3, &slot))) return r;
+    enqueue_g2p(c->stream, c->L, T, c->S[c->cur], c->cap, c->B.chunks, c->ctl, c->G, c->ring_dev + rs,
+                (c->cfg.flags & MPM_FLAG_G2P_GLOBAL_GATHER) ? 0 : 1, parity, fb_limit(c), c->cfg.chunk, act);
+    if ((r = prof_end(c, slot))) return r;
+    HIP_OK(c, hipGetLastError());
+    HIP_OK(c, hipEventRecord(c->ev[rs], c->stream));
+    note_substep(c, act);
+    return MPM_OK;
+}
+
+// A frame as a replayed graph: rebuild from buffer `cur` into the other one,
+// then every substep of the frame on it.  Recorded on first use for this
+// parity, particle count, frame length and chunk size.
+int graph_frame(mpm_ctx* c, float frame_dt, const std::vector<int>& ns) {
+    FrameGraph& g = c->graphs[c->cur];
+    if (!(g.exec && g.N == c->N && g.frame_dt == frame_dt && g.chunk == c->cfg.chunk)) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+        g = FrameGraph{};
+        HIP_OK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        enqueue_rebuild_into_alt(c);
+        const int other = c->cur ^ 1;
+        const Scenes T = tables(c);
+        for (int k = 0; k < ns[0]; ++k) {
+            const int act = active_ranks(ns, k);
+            const int parity = k & 1;  // the rebuild cleared both overflow slots
+            enqueue_p2g(c->stream, c->L, T, c->S[other], c->cap, c->B.chunks, c->ctl, c->G, c->B.brick_state, 1,
+                        parity, (c->cfg.flags & MPM_FLAG_P2G_GLOBAL_ATOMICS) ? 1 : 0, c->nbricks, c->cfg.chunk,
+                        act);
+            enqueue_grid(c->stream, c->L, T, c->B, c->ctl, c->G, parity, c->nbricks, act);
+            enqueue_g2p(c->stream, c->L, T, c->S[other], c->cap, c->B.chunks, c->ctl, c->G, nullptr,
+                        (c->cfg.flags & MPM_FLAG_G2P_GLOBAL_GATHER) ? 0 : 1, parity, fb_limit(c), c->cfg.chunk,
+                        act);
+        }
+        hipGraph_t graph = nullptr;
+        const hipError_t e1 = hipGetLastError();
+        const hipError_t e2 = hipStreamEndCapture(c->stream, &graph);
+        if (e1 != hipSuccess || e2 != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(c, MPM_EDEVICE, std::string("frame graph capture: ") +
+                                            hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+        }
+        g.graph = graph;
+        HIP_OK(c, hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+        g.N = c->N;
+        g.frame_dt = frame_dt;
+        g.chunk = c->cfg.chunk;
+    }
+    HIP_OK(c, hipGraphLaunch(g.exec, c->stream));
+    note_rebuild(c);
+    c->parity_ctr = 0;
+    for (int k = 0; k < ns[0]; ++k) note_substep(c, active_ranks(ns, k));
+    c->checked = c->step;  // graph frames leave no host flags to read
+    return MPM_OK;
+}
+
+int run_frame(mpm_ctx* c, float frame_dt) {
+    if (c->N == 0) return MPM_OK;
+    const std::vector<int> ns = frame_substeps(c, frame_dt);
+    if ((c->cfg.flags & MPM_FLAG_FRAME_GRAPHS) && c->pending && !(c->cfg.flags & MPM_FLAG_REBUILD_EVERY_STEP)) {
+        int r = poll_flags(c, c->step);  // the ring is idle across a graph frame
+        if (r) return r;
+        return graph_frame(c, frame_dt, ns);
+    }
+    for (int k = 0; k < ns[0]; ++k) {
+        int r = substep_one(c, active_ranks(ns, k));
+        if (r) return r;
+    }
+    return MPM_OK;
+}
+
+// Per-rank list ends of the last rebuild (host copy).
+int read_rank_ends(mpm_ctx* c, std::vector<int>& e) {
+    e.assign(4 * c->nsc, 0);
+    HIP_OK(c, hipMemcpyAsync(e.data(), c->rank_end_dev, sizeof(int) * 4 * c->nsc, hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    return MPM_OK;
+}
+
+void rank_range(const std::vector<int>& e, int S, int kind, int r, int& b, int& en) {
+    b = r > 0 ? e[kind * S + r - 1] : 0;
+    en = e[kind * S + r];
+}
+
+int scene_arg(mpm_ctx* c, int32_t scene) {
+    if (scene < 0 || scene >= c->nsc) return fail(c, MPM_EINVAL, "scene index out of range");
+    return MPM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -313,33 +565,65 @@ extern "C" {
 int mpm_create(const mpm_config* cfg, mpm_ctx** out) {
     if (!cfg || !out) return fail(nullptr, MPM_EINVAL, "null argument");
     *out = nullptr;
-    const int n = cfg->n;
-    if (n < 16 || n > 512 || (n & (n - 1))) return fail(nullptr, MPM_EINVAL, "n must be a power of two in [16, 512]");
-    if (cfg->bc < 0 || cfg->bc > 2) return fail(nullptr, MPM_EINVAL, "bad bc");
-    if (cfg->bc_cells < 0 || cfg->bc_cells > n / 2) return fail(nullptr, MPM_EINVAL, "bad bc_cells");
-    if (cfg->num_scenes != 1) return fail(nullptr, MPM_EINVAL, "num_scenes must be 1");
-    if (!(cfg->dt > 0.0f)) return fail(nullptr, MPM_EINVAL, "dt must be positive");
+    if (cfg->num_scenes < 1 || cfg->num_scenes > MPM_MAX_SCENES)
+        return fail(nullptr, MPM_EINVAL, "num_scenes must be in [1, 256]");
+    const int S = cfg->num_scenes;
+    std::vector<mpm_scene> desc(S);
+    for (int s = 0; s < S; ++s) {
+        if (cfg->scenes) {
+            desc[s] = cfg->scenes[s];
+        } else {
+            desc[s].n = cfg->n;
+            desc[s].bc = cfg->bc;
+            desc[s].bc_cells = cfg->bc_cells;
+            for (int a = 0; a < 3; ++a) desc[s].gravity[a] = cfg->gravity[a];
+            desc[s].dt = cfg->dt;
+        }
+        if (const char* why = check_scene(desc[s])) return fail(nullptr, MPM_EINVAL, why);
+    }
     if (cfg->capacity < 0) return fail(nullptr, MPM_EINVAL, "negative capacity");
     if (cfg->lag < 0 || cfg->lag > 64) return fail(nullptr, MPM_EINVAL, "lag must be in [0, 64]");
     if (cfg->chunk != 0 && (cfg->chunk < 64 || cfg->chunk > 512 || cfg->chunk % 64))
         return fail(nullptr, MPM_EINVAL, "chunk must be a multiple of 64 in [64, 512]");
+    if ((cfg->flags & MPM_FLAG_FRAME_GRAPHS) && cfg->stream == 0)
+        return fail(nullptr, MPM_EINVAL, "frame graphs need a stream other than the null stream");
+    int nmax = 0;
+    for (auto& d : desc) nmax = std::max(nmax, d.n);
+    const int shift = 3 * log2i(nmax), key_bits = shift + log2i(S);
+    if (key_bits > 32) return fail(nullptr, MPM_EINVAL, "too many scenes for the largest grid: 3 log2(n) + log2(S) > 32");
+    int64_t bricks = 0;
+    for (auto& d : desc) bricks += (int64_t)(d.n / 4 + 2) * (d.n / 4 + 2) * (d.n / 4 + 2);
+    if (bricks * BLOCK_NODES > INT32_MAX) return fail(nullptr, MPM_EINVAL, "the scenes' grids exceed 2^31 nodes");
+
     mpm_ctx* c = new mpm_ctx();
     c->cfg = *cfg;
+    c->cfg.scenes = nullptr;  // copied below
     if (c->cfg.lag == 0) c->cfg.lag = 3;
     if (c->cfg.chunk == 0) c->cfg.chunk = 256;
     c->stream = reinterpret_cast<hipStream_t>(cfg->stream);
     (void)hipGetDevice(&c->device);
-    c->P.n = n;
-    c->P.NB = n / 4 + 2;
-    c->P.fn = (float)n;
-    c->P.dx = 1.0f / (float)n;
-    c->P.dt = cfg->dt;
-    c->P.g0 = cfg->gravity[0];
-    c->P.g1 = cfg->gravity[1];
-    c->P.g2 = cfg->gravity[2];
-    c->P.bc = cfg->bc;
-    c->P.bc_cells = cfg->bc_cells;
-    c->nbricks = c->P.NB * c->P.NB * c->P.NB;
+    c->nsc = S;
+    c->shift = shift;
+    c->key_bits = key_bits;
+    c->sh.resize(S);
+    for (int s = 0; s < S; ++s) c->sh[s].desc = desc[s];
+    // ranks: increasing dt, ties by scene index
+    c->rank_scene.resize(S);
+    for (int s = 0; s < S; ++s) c->rank_scene[s] = s;
+    std::stable_sort(c->rank_scene.begin(), c->rank_scene.end(),
+                     [&](int a, int b) { return desc[a].dt < desc[b].dt; });
+    c->table.resize(S);
+    std::vector<int> rank_brick(S + 1, 0);
+    for (int r = 0; r < S; ++r) {
+        const int s = c->rank_scene[r];
+        Scene& t = c->table[s];
+        t.P = make_step(desc[s]);
+        t.M = Mat{};
+        t.rank = r;
+        t.brick_base = rank_brick[r];
+        rank_brick[r + 1] = rank_brick[r] + t.P.NB * t.P.NB * t.P.NB;
+    }
+    c->nbricks = rank_brick[S];
     query_launch(c->L, c->cfg.chunk);
 
     auto bail = [&](int code) {
@@ -356,7 +640,11 @@ int mpm_create(const mpm_config* cfg, mpm_ctx** out) {
               hipMalloc(&c->B.brick_state, sizeof(int) * nb) == hipSuccess &&
               hipMalloc(&c->B.active, sizeof(int) * nb) == hipSuccess &&
               hipMalloc(&c->B.gindex, sizeof(int) * nb) == hipSuccess &&
-              hipMalloc(&c->ctl, sizeof(int) * CTL_ALLOC_WORDS) == hipSuccess;
+              hipMalloc(&c->ctl, sizeof(int) * CTL_ALLOC_WORDS) == hipSuccess &&
+              hipMalloc(&c->scene_dev, sizeof(Scene) * S) == hipSuccess &&
+              hipMalloc(&c->rank_scene_dev, sizeof(int) * S) == hipSuccess &&
+              hipMalloc(&c->rank_brick_dev, sizeof(int) * (S + 1)) == hipSuccess &&
+              hipMalloc(&c->rank_end_dev, sizeof(int) * 4 * S) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         c->err = "grid allocation failed";
@@ -366,7 +654,15 @@ int mpm_create(const mpm_config* cfg, mpm_ctx** out) {
         hipMemsetAsync(c->G.vel, 0, sizeof(float4) * 64 * nb, c->stream) != hipSuccess ||
         hipMemsetAsync(c->G.stamp, 0xff, sizeof(int) * nb, c->stream) != hipSuccess ||
         hipMemsetAsync(c->B.brick_state, 0, sizeof(int) * nb, c->stream) != hipSuccess ||
-        hipMemsetAsync(c->ctl, 0, sizeof(int) * CTL_ALLOC_WORDS, c->stream) != hipSuccess) {
+        hipMemsetAsync(c->ctl, 0, sizeof(int) * CTL_ALLOC_WORDS, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->rank_end_dev, 0, sizeof(int) * 4 * S, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->scene_dev, c->table.data(), sizeof(Scene) * S, hipMemcpyHostToDevice, c->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(c->rank_scene_dev, c->rank_scene.data(), sizeof(int) * S, hipMemcpyHostToDevice, c->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(c->rank_brick_dev, rank_brick.data(), sizeof(int) * (S + 1), hipMemcpyHostToDevice,
+                       c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
         c->err = "initialisation failed";
         return bail(MPM_EDEVICE);
     }
@@ -393,6 +689,7 @@ int mpm_create(const mpm_config* cfg, mpm_ctx** out) {
 int mpm_destroy(mpm_ctx* c) {
     if (!c) return MPM_OK;
     (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
     free_particle_buffers(c);
     (void)hipFree(c->G.acc);
     (void)hipFree(c->G.vel);
@@ -403,6 +700,10 @@ int mpm_destroy(mpm_ctx* c) {
     (void)hipFree(c->B.active);
     (void)hipFree(c->B.gindex);
     (void)hipFree(c->ctl);
+    (void)hipFree(c->scene_dev);
+    (void)hipFree(c->rank_scene_dev);
+    (void)hipFree(c->rank_brick_dev);
+    (void)hipFree(c->rank_end_dev);
     if (c->ring) (void)hipHostFree(c->ring);
     for (int i = 0; i < RING; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
@@ -417,22 +718,25 @@ int mpm_destroy(mpm_ctx* c) {
 int mpm_add_particles(mpm_ctx* c, int32_t scene, const mpm_material* mat, int64_t count, const float* x,
                       const float* v, const float* C, const float* F, const float* s) {
     if (!c) return MPM_EINVAL;
-    if (scene != 0) return fail(c, MPM_EINVAL, "scene must be 0");
+    if (int r = scene_arg(c, scene)) return r;
     if (count < 0 || (count > 0 && !x)) return fail(c, MPM_EINVAL, "bad count or null positions");
     if (c->N + count > (int64_t)1 << 30) return fail(c, MPM_EINVAL, "too many particles");
+    SceneHost& sh = c->sh[scene];
     if (mat) {
         if (mat->kind < 0 || mat->kind > 2) return fail(c, MPM_EINVAL, "bad material kind");
         if (!(mat->ppc > 0) || !(mat->rho > 0)) return fail(c, MPM_EINVAL, "ppc and rho must be positive");
         if (mat->kind != MPM_WATER && !(mat->nu > -1.0f && mat->nu < 0.5f)) return fail(c, MPM_EINVAL, "bad nu");
-        if (c->has_mat && !same_material(c->mat, *mat))
-            return fail(c, MPM_EINVAL, "a context holds one material; pass the same constants or NULL");
-        if (!c->has_mat) {
-            c->mat = *mat;
-            c->has_mat = true;
-            c->M = derive_material(*mat, c->P);
+        if (sh.has_mat && !same_material(sh.mat, *mat))
+            return fail(c, MPM_EINVAL, "a scene holds one material; pass the same constants or NULL");
+        if (!sh.has_mat) {
+            sh.mat = *mat;
+            sh.has_mat = true;
+            c->table[scene].M = derive_material(*mat, c->table[scene].P);
+            HIP_OK(c, hipMemcpyAsync(c->scene_dev + scene, &c->table[scene], sizeof(Scene), hipMemcpyHostToDevice,
+                                     c->stream));
         }
-    } else if (!c->has_mat) {
-        return fail(c, MPM_EINVAL, "the first call must pass a material");
+    } else if (!sh.has_mat) {
+        return fail(c, MPM_EINVAL, "the first call for a scene must pass a material");
     }
     if (count == 0) return MPM_OK;
     if (c->N + count > c->cap / 2) {
@@ -442,62 +746,25 @@ int mpm_add_particles(mpm_ctx* c, int32_t scene, const mpm_material* mat, int64_
         if (r) return r;
     }
     if (c->pending) {  // land the deferred update so old and new particles share one state convention
-        enqueue_materialize(c->stream, c->P, c->M, c->S[c->cur], c->cap, (int)c->N);
+        enqueue_materialize(c->stream, tables(c), c->S[c->cur], c->cap, (int)c->N);
         c->pending = 0;
     }
-    enqueue_insert(c->stream, c->S[c->cur], c->ids[c->cur], c->cap, (int)c->N, (int)count, x, v, C, F, s, c->ctl);
+    enqueue_insert(c->stream, c->S[c->cur], c->ids[c->cur], c->cap, (int)c->N, (int)count, scene, (int)sh.N, x, v, C,
+                   F, s, c->ctl);
     HIP_OK(c, hipGetLastError());
     c->N += count;
+    sh.N += count;
     c->need_rebuild = true;
     return MPM_OK;
 }
-
-// In-zone particles that may lose their chunk's tile in one substep before
-// the next substep asks for a rebuild (1/256 of the particles).  With
-// MPM_FLAG_MANUAL_REBUILD the request is ignored like the free-zone one.
-int fb_limit(const mpm_ctx* c) { return (int)(c->N >> 8); }
 
 int mpm_substep(mpm_ctx* c, int32_t nsteps) {
     if (!c) return MPM_EINVAL;
     if (nsteps < 0) return fail(c, MPM_EINVAL, "negative step count");
     if (c->N == 0) return MPM_OK;
-    const int N = (int)c->N;
     for (int k = 0; k < nsteps; ++k) {
-        int r = poll_flags(c, c->step - c->cfg.lag);
+        int r = substep_one(c, c->nsc);
         if (r) return r;
-        if (c->need_rebuild || (c->cfg.flags & MPM_FLAG_REBUILD_EVERY_STEP)) {
-            int slot;
-            if ((r = prof_begin(c, 0, &slot))) return r;
-            enqueue_rebuild(c->stream, c->P, c->S[c->cur], c->S[c->cur ^ 1], c->ids[c->cur], c->ids[c->cur ^ 1],
-                            c->cap, N, c->cfg.chunk, (c->cfg.flags & MPM_FLAG_P2G_SORTED_LANES) ? 0 : 1, c->B,
-                            c->ctl, c->nbricks);
-            if ((r = prof_end(c, slot))) return r;
-            c->cur ^= 1;
-            c->need_rebuild = false;
-            c->last_rebuild = c->step;
-            c->n_at_rebuild = c->N;
-            ++c->rebuilds;
-        }
-        const int rs = (int)(c->step % RING);
-        c->ring[rs] = 0;
-        const int parity = (int)(c->step & 1);
-        int slot;
-        if ((r = prof_begin(c, 1, &slot))) return r;
-        enqueue_p2g(c->stream, c->L, c->P, c->M, c->S[c->cur], c->cap, c->B.chunks, c->ctl, c->G, c->B.brick_state,
-                    c->pending, parity, (c->cfg.flags & MPM_FLAG_P2G_GLOBAL_ATOMICS) ? 1 : 0, c->nbricks,
-                    c->cfg.chunk);
-        if ((r = prof_end(c, slot))) return r;
-        if ((r = prof_begin(c, 2, &slot))) return r;
-        enqueue_grid(c->stream, c->L, c->P, c->B, c->ctl, c->G, parity, (int)c->step);
-        if ((r = prof_end(c, slot))) return r;
-        if ((r = prof_begin(c, 3, &slot))) return r;
-        enqueue_g2p(c->stream, c->L, c->P, c->S[c->cur], c->cap, c->B.chunks, c->ctl, c->G, c->ring_dev + rs,
-                    (c->cfg.flags & MPM_FLAG_G2P_GLOBAL_GATHER) ? 0 : 1, parity, fb_limit(c), c->cfg.chunk);
-        if ((r = prof_end(c, slot))) return r;
-        HIP_OK(c, hipGetLastError());
-        HIP_OK(c, hipEventRecord(c->ev[rs], c->stream));
-        c->pending = 1;
-        ++c->step;
     }
     return MPM_OK;
 }
@@ -505,11 +772,7 @@ int mpm_substep(mpm_ctx* c, int32_t nsteps) {
 int mpm_frame(mpm_ctx* c, float frame_dt) {
     if (!c) return MPM_EINVAL;
     if (!(frame_dt > 0.0f)) return fail(c, MPM_EINVAL, "frame_dt must be positive");
-    const double ns = (double)frame_dt / (double)c->cfg.dt;
-    int n = (int)ns;
-    if (ns - n > 1e-4) ++n;
-    if (n < 1) n = 1;
-    return mpm_substep(c, n);
+    return run_frame(c, frame_dt);
 }
 
 int mpm_rebuild(mpm_ctx* c) {
@@ -526,52 +789,72 @@ int mpm_synchronize(mpm_ctx* c) {
 
 int mpm_read_particles(mpm_ctx* c, int32_t scene, int64_t count, float* x, float* v, float* C, float* F, float* s) {
     if (!c) return MPM_EINVAL;
-    if (scene != 0 || count != c->N) return fail(c, MPM_EINVAL, "count must equal the particle count of scene 0");
-    enqueue_read(c->stream, c->P, c->M, c->S[c->cur], c->ids[c->cur], c->cap, (int)c->N, c->pending, x, v, C, F, s);
+    if (int r = scene_arg(c, scene)) return r;
+    if (count != c->sh[scene].N) return fail(c, MPM_EINVAL, "count must equal the scene's particle count");
+    enqueue_read(c->stream, tables(c), c->S[c->cur], c->ids[c->cur], c->cap, (int)c->N, scene, (int)count, c->pending,
+                 x, v, C, F, s);
     HIP_OK(c, hipGetLastError());
     return check_error_word(c);
 }
 
 int mpm_read_grid(mpm_ctx* c, int32_t scene, float* m, float* v) {
     if (!c) return MPM_EINVAL;
-    if (scene != 0) return fail(c, MPM_EINVAL, "scene must be 0");
-    enqueue_read_grid(c->stream, c->P, c->G, (int)(c->step - 1), m, v);
+    if (int r = scene_arg(c, scene)) return r;
+    enqueue_read_grid(c->stream, c->table[scene], c->G, (int)c->sh[scene].last_step, m, v);
     HIP_OK(c, hipGetLastError());
     return check_error_word(c);
 }
 
 int mpm_read_binning(mpm_ctx* c, int32_t scene, int64_t count, uint32_t* keys, int32_t* perm) {
     if (!c) return MPM_EINVAL;
-    if (scene != 0) return fail(c, MPM_EINVAL, "scene must be 0");
+    if (int r = scene_arg(c, scene)) return r;
     if (c->last_rebuild < 0) return fail(c, MPM_EINVAL, "no rebuild has run yet");
-    if (count != c->n_at_rebuild) return fail(c, MPM_EINVAL, "count must equal the particle count at the last rebuild");
+    if (count != c->sh[scene].N_at_rebuild)
+        return fail(c, MPM_EINVAL, "count must equal the scene's particle count at the last rebuild");
+    std::vector<int> e;
+    if (int r = read_rank_ends(c, e)) return r;
+    int b, en;
+    rank_range(e, c->nsc, RE_PART, c->table[scene].rank, b, en);
+    if (en - b != count) return fail(c, MPM_EDEVICE, "rank range does not match the particle count");
     if (keys)
-        HIP_OK(c, hipMemcpyAsync(keys, c->B.keys[c->B.sorted], sizeof(uint32_t) * count, hipMemcpyDeviceToDevice,
-                                 c->stream));
+        enqueue_copy_codes(c->stream, keys, c->B.keys[c->B.sorted] + b, (int)count, (1u << c->shift) - 1u);
     if (perm)
-        HIP_OK(c, hipMemcpyAsync(perm, c->B.sorted_ids, sizeof(int32_t) * count, hipMemcpyDeviceToDevice, c->stream));
+        HIP_OK(c, hipMemcpyAsync(perm, c->B.sorted_ids + b, sizeof(int32_t) * count, hipMemcpyDeviceToDevice,
+                                 c->stream));
+    HIP_OK(c, hipGetLastError());
     return check_error_word(c);
 }
 
 int mpm_read_blocks(mpm_ctx* c, int32_t scene, uint32_t* gcode, int32_t* gstart, int32_t* gcount, int32_t* active) {
     if (!c) return MPM_EINVAL;
-    if (scene != 0) return fail(c, MPM_EINVAL, "scene must be 0");
-    int h[CTL_WORDS];
-    HIP_OK(c, hipMemcpyAsync(h, c->ctl, sizeof h, hipMemcpyDeviceToHost, c->stream));
-    HIP_OK(c, hipStreamSynchronize(c->stream));
-    const int ng = h[CTL_NGB], na = h[CTL_NACTIVE];
-    if (gcode) HIP_OK(c, hipMemcpy(gcode, c->B.gcode, sizeof(uint32_t) * ng, hipMemcpyDeviceToHost));
-    if (gstart || gcount) {
+    if (int r = scene_arg(c, scene)) return r;
+    std::vector<int> e;
+    if (int r = read_rank_ends(c, e)) return r;
+    const int rk = c->table[scene].rank;
+    int pb, pe, gb, ge, ab, ae;
+    rank_range(e, c->nsc, RE_PART, rk, pb, pe);
+    rank_range(e, c->nsc, RE_GBLOCK, rk, gb, ge);
+    rank_range(e, c->nsc, RE_ACTIVE, rk, ab, ae);
+    const int ng = ge - gb, na = ae - ab;
+    const uint32_t bmask = (1u << (c->shift - 6)) - 1u;
+    if (ng > 0 && gcode) {
+        HIP_OK(c, hipMemcpy(gcode, c->B.gcode + gb, sizeof(uint32_t) * ng, hipMemcpyDeviceToHost));
+        for (int i = 0; i < ng; ++i) gcode[i] &= bmask;
+    }
+    if (ng > 0 && (gstart || gcount)) {
         std::vector<int> st(ng + 1);
-        HIP_OK(c, hipMemcpy(st.data(), c->B.gstart, sizeof(int) * ng, hipMemcpyDeviceToHost));
-        st[ng] = (int)c->n_at_rebuild;
+        HIP_OK(c, hipMemcpy(st.data(), c->B.gstart + gb, sizeof(int) * ng, hipMemcpyDeviceToHost));
+        st[ng] = pe;
         for (int i = 0; i < ng; ++i) {
-            if (gstart) gstart[i] = st[i];
+            if (gstart) gstart[i] = st[i] - pb;
             if (gcount) gcount[i] = st[i + 1] - st[i];
         }
     }
-    if (active) HIP_OK(c, hipMemcpy(active, c->B.active, sizeof(int) * na, hipMemcpyDeviceToHost));
-    return h[CTL_ERROR] ? fail(c, MPM_ESTATE, "device error word set") : MPM_OK;
+    if (na > 0 && active) {
+        HIP_OK(c, hipMemcpy(active, c->B.active + ab, sizeof(int) * na, hipMemcpyDeviceToHost));
+        for (int i = 0; i < na; ++i) active[i] -= c->table[scene].brick_base;
+    }
+    return check_error_word(c);
 }
 
 int mpm_get_stats(mpm_ctx* c, mpm_stats* o) {
@@ -589,14 +872,35 @@ int mpm_get_stats(mpm_ctx* c, mpm_stats* o) {
     o->gblocks = h[CTL_NGB];
     o->active_blocks = h[CTL_NACTIVE];
     o->chunks = h[CTL_NCHUNK];
-    o->overflow_blocks = c->step > 0 ? h[CTL_OVF + ((c->step - 1) & 1)] : 0;
+    o->overflow_blocks = c->step > 0 ? h[CTL_OVF + ((c->parity_ctr - 1) & 1)] : 0;
     o->error = (uint32_t)h[CTL_ERROR];
     o->pending_update = (uint32_t)c->pending;
     unsigned long long c64[CTL64_WORDS];
     memcpy(c64, h + CTL_WORDS, sizeof c64);
     o->p2g_fallback_chunks = (int64_t)c64[CTL64_FALLBACK_CHUNKS];
     o->p2g_global_particles = (int64_t)c64[CTL64_GLOBAL_PARTICLES];
+    o->surrogate_particles = (int64_t)c64[CTL64_SUR_PARTICLES];
+    o->surrogate_fallbacks = (int64_t)c64[CTL64_SUR_FALLBACKS];
     return o->error ? fail(c, MPM_ESTATE, "device error word set") : MPM_OK;
+}
+
+int mpm_get_scene_stats(mpm_ctx* c, int32_t scene, mpm_scene_stats* o) {
+    if (!c || !o) return MPM_EINVAL;
+    if (int r = scene_arg(c, scene)) return r;
+    std::vector<int> e;
+    if (int r = read_rank_ends(c, e)) return r;
+    const int rk = c->table[scene].rank;
+    int gb, ge, ab, ae;
+    rank_range(e, c->nsc, RE_GBLOCK, rk, gb, ge);
+    rank_range(e, c->nsc, RE_ACTIVE, rk, ab, ae);
+    memset(o, 0, sizeof *o);
+    o->num_particles = c->sh[scene].N;
+    o->substeps = c->sh[scene].substeps;
+    o->gblocks = ge - gb;
+    o->active_blocks = ae - ab;
+    o->n = c->sh[scene].desc.n;
+    o->dt = c->sh[scene].desc.dt;
+    return MPM_OK;
 }
 
 int mpm_clear_error(mpm_ctx* c) {
@@ -604,6 +908,118 @@ int mpm_clear_error(mpm_ctx* c) {
     HIP_OK(c, hipMemsetAsync(c->ctl + CTL_ERROR, 0, sizeof(int), c->stream));
     HIP_OK(c, hipStreamSynchronize(c->stream));
     return MPM_OK;
+}
+
+int mpm_autotune(mpm_ctx* c, float frame_dt, int32_t frames, int32_t* chunk_out) {
+    if (!c) return MPM_EINVAL;
+    if (!(frame_dt > 0.0f) || frames < 1) return fail(c, MPM_EINVAL, "frame_dt must be positive and frames >= 1");
+    const int orig_chunk = c->cfg.chunk;
+    if (c->N == 0) {
+        if (chunk_out) *chunk_out = orig_chunk;
+        return MPM_OK;
+    }
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    if (int r = poll_flags(c, c->step)) return r;
+    // snapshot of the device state and of the host counters
+    float* snap = nullptr;
+    int* snap_ids = nullptr;
+    int snap_ctl[CTL_ALLOC_WORDS];
+    if (hipMalloc(&snap, sizeof(float) * NF * c->cap) != hipSuccess ||
+        hipMalloc(&snap_ids, sizeof(int) * c->cap) != hipSuccess) {
+        (void)hipFree(snap);
+        (void)hipGetLastError();
+        return fail(c, MPM_ENOMEM, "autotune snapshot allocation failed");
+    }
+    const int cur0 = c->cur;
+    auto restore_host = [](mpm_ctx* dst, const mpm_ctx& s) {
+        dst->step = s.step;
+        dst->checked = s.checked;
+        dst->last_rebuild = s.last_rebuild;
+        dst->rebuilds = s.rebuilds;
+        dst->parity_ctr = s.parity_ctr;
+        dst->n_at_rebuild = s.n_at_rebuild;
+        dst->pending = s.pending;
+        dst->sh = s.sh;
+    };
+    mpm_ctx saved;  // host counters only
+    saved.step = c->step;
+    saved.checked = c->checked;
+    saved.last_rebuild = c->last_rebuild;
+    saved.rebuilds = c->rebuilds;
+    saved.parity_ctr = c->parity_ctr;
+    saved.n_at_rebuild = c->n_at_rebuild;
+    saved.pending = c->pending;
+    saved.sh = c->sh;
+    const uint32_t prof_mask = c->prof_mask;
+    c->prof_mask = 0;
+    int rc = MPM_OK;
+    auto copy_state = [&](bool to_snap) -> int {
+        if (to_snap) {
+            HIP_OK(c, hipMemcpyAsync(snap, c->S[cur0], sizeof(float) * NF * c->cap, hipMemcpyDeviceToDevice,
+                                     c->stream));
+            HIP_OK(c, hipMemcpyAsync(snap_ids, c->ids[cur0], sizeof(int) * c->cap, hipMemcpyDeviceToDevice,
+                                     c->stream));
+            HIP_OK(c, hipMemcpyAsync(snap_ctl, c->ctl, sizeof snap_ctl, hipMemcpyDeviceToHost, c->stream));
+        } else {
+            HIP_OK(c, hipMemcpyAsync(c->S[cur0], snap, sizeof(float) * NF * c->cap, hipMemcpyDeviceToDevice,
+                                     c->stream));
+            HIP_OK(c, hipMemcpyAsync(c->ids[cur0], snap_ids, sizeof(int) * c->cap, hipMemcpyDeviceToDevice,
+                                     c->stream));
+            HIP_OK(c, hipMemcpyAsync(c->ctl, snap_ctl, sizeof snap_ctl, hipMemcpyHostToDevice, c->stream));
+        }
+        HIP_OK(c, hipStreamSynchronize(c->stream));
+        return MPM_OK;
+    };
+    rc = copy_state(true);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = fail(c, MPM_EDEVICE, "event creation failed");
+    int best = orig_chunk;
+    float best_ms = -1.0f;
+    const int cand[3] = {128, 256, 512};
+    for (int i = 0; i < 3 && !rc; ++i) {
+        c->cur = cur0;
+        restore_host(c, saved);
+        if ((rc = copy_state(false))) break;
+        c->cfg.chunk = cand[i];
+        query_launch(c->L, c->cfg.chunk);
+        drop_graphs(c);
+        c->need_rebuild = true;
+        if ((rc = run_frame(c, frame_dt))) break;  // warm-up (and graph recording)
+        if (hipEventRecord(e0, c->stream) != hipSuccess) {
+            rc = fail(c, MPM_EDEVICE, "event record failed");
+            break;
+        }
+        for (int f = 0; f < frames && !rc; ++f) rc = run_frame(c, frame_dt);
+        if (rc) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = fail(c, MPM_EDEVICE, "event timing failed");
+            break;
+        }
+        if (best_ms < 0.0f || ms < best_ms) {
+            best_ms = ms;
+            best = cand[i];
+        }
+    }
+    (void)hipStreamSynchronize(c->stream);
+    (void)poll_flags(c, c->step);
+    // put everything back; keep the winner
+    c->cur = cur0;
+    restore_host(c, saved);
+    if (!rc) rc = copy_state(false);
+    c->cfg.chunk = rc ? orig_chunk : best;
+    query_launch(c->L, c->cfg.chunk);
+    drop_graphs(c);
+    c->need_rebuild = true;
+    c->prof_mask = prof_mask;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(snap);
+    (void)hipFree(snap_ids);
+    if (!rc && chunk_out) *chunk_out = c->cfg.chunk;
+    return rc;
 }
 
 int mpm_profile(mpm_ctx* c, uint32_t mask) {
@@ -634,5 +1050,206 @@ int mpm_profile_read(mpm_ctx* c, mpm_profile_data* o) {
 }
 
 const char* mpm_last_error(const mpm_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+}  // extern "C"
+
+// ------------------------------------------------------------- surrogate
+struct mpm_surrogate {
+    hipStream_t stream = nullptr;
+    float* theta = nullptr;  // [SUR_PARAMS] FP32 master parameters
+    float* norm = nullptr;   // [SUR_NORM]
+    float* grad = nullptr;   // [SUR_PARAMS]
+    float* m = nullptr;      // Adam moments
+    float* v = nullptr;
+    float* loss = nullptr;   // [loss_cap] per-step minibatch losses
+    int loss_cap = 0;
+    int* idx = nullptr;      // minibatch rows
+    int idx_cap = 0;
+    int step = 0;            // Adam steps taken
+    unsigned long long* counter = nullptr;
+};
+
+namespace {
+
+int sfail(mpm_surrogate*, int code, const std::string& msg) {
+    g_create_error = msg;
+    return code;
+}
+
+#define SHIP_OK(call)                                                                                  \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            return sfail(nullptr, e_ == hipErrorOutOfMemory ? MPM_ENOMEM : MPM_EDEVICE,                 \
+                         std::string(#call) + ": " + hipGetErrorString(e_));                            \
+    } while (0)
+
+__global__ void k_identity_norm(float* norm) {
+    const int i = threadIdx.x;
+    if (i < SUR_NORM) norm[i] = ((i >= SUR_IN && i < 2 * SUR_IN) || i >= 2 * SUR_IN + SUR_OUT) ? 1.0f : 0.0f;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpm_surrogate_create(uint64_t stream, mpm_surrogate** out) {
+    if (!out) return sfail(nullptr, MPM_EINVAL, "null argument");
+    *out = nullptr;
+    mpm_surrogate* s = new mpm_surrogate();
+    s->stream = reinterpret_cast<hipStream_t>(stream);
+    bool ok = hipMalloc(&s->theta, sizeof(float) * SUR_PARAMS) == hipSuccess &&
+              hipMalloc(&s->norm, sizeof(float) * SUR_NORM) == hipSuccess &&
+              hipMalloc(&s->grad, sizeof(float) * SUR_PARAMS) == hipSuccess &&
+              hipMalloc(&s->m, sizeof(float) * SUR_PARAMS) == hipSuccess &&
+              hipMalloc(&s->v, sizeof(float) * SUR_PARAMS) == hipSuccess &&
+              hipMalloc(&s->counter, sizeof(unsigned long long)) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        mpm_surrogate_destroy(s);
+        return sfail(nullptr, MPM_ENOMEM, "surrogate allocation failed");
+    }
+    sur_zero(s->stream, s->theta, SUR_PARAMS);
+    sur_zero(s->stream, s->grad, SUR_PARAMS);
+    sur_zero(s->stream, s->m, SUR_PARAMS);
+    sur_zero(s->stream, s->v, SUR_PARAMS);
+    hipLaunchKernelGGL(k_identity_norm, dim3(1), dim3(64), 0, s->stream, s->norm);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess) {
+        mpm_surrogate_destroy(s);
+        return sfail(nullptr, MPM_EDEVICE, "surrogate initialisation failed");
+    }
+    *out = s;
+    return MPM_OK;
+}
+
+int mpm_surrogate_destroy(mpm_surrogate* s) {
+    if (!s) return MPM_OK;
+    (void)hipStreamSynchronize(s->stream);
+    (void)hipFree(s->theta);
+    (void)hipFree(s->norm);
+    (void)hipFree(s->grad);
+    (void)hipFree(s->m);
+    (void)hipFree(s->v);
+    (void)hipFree(s->loss);
+    (void)hipFree(s->idx);
+    (void)hipFree(s->counter);
+    delete s;
+    return MPM_OK;
+}
+
+int mpm_surrogate_set(mpm_surrogate* s, const float* theta, const float* norm) {
+    if (!s) return MPM_EINVAL;
+    if (theta) SHIP_OK(hipMemcpyAsync(s->theta, theta, sizeof(float) * SUR_PARAMS, hipMemcpyDeviceToDevice, s->stream));
+    if (norm) SHIP_OK(hipMemcpyAsync(s->norm, norm, sizeof(float) * SUR_NORM, hipMemcpyDeviceToDevice, s->stream));
+    return MPM_OK;
+}
+
+int mpm_surrogate_get(mpm_surrogate* s, float* theta, float* norm) {
+    if (!s) return MPM_EINVAL;
+    if (theta) SHIP_OK(hipMemcpyAsync(theta, s->theta, sizeof(float) * SUR_PARAMS, hipMemcpyDeviceToDevice, s->stream));
+    if (norm) SHIP_OK(hipMemcpyAsync(norm, s->norm, sizeof(float) * SUR_NORM, hipMemcpyDeviceToDevice, s->stream));
+    return MPM_OK;
+}
+
+int mpm_surrogate_forward(mpm_surrogate* s, int32_t precision, int64_t count, const float* X, float* Y) {
+    if (!s || count < 0 || (count > 0 && (!X || !Y)) || (precision != 0 && precision != 1))
+        return sfail(s, MPM_EINVAL, "bad surrogate forward arguments");
+    sur_forward(s->stream, precision, s->theta, s->norm, X, count, Y);
+    SHIP_OK(hipGetLastError());
+    return MPM_OK;
+}
+
+int mpm_surrogate_loss_grad(mpm_surrogate* s, int32_t precision, int64_t count, const float* X, const float* T,
+                            float* grad, float* loss) {
+    if (!s || count < 1 || !X || !T || !grad || !loss || (precision != 0 && precision != 1))
+        return sfail(s, MPM_EINVAL, "bad surrogate gradient arguments");
+    sur_grad(s->stream, precision, s->theta, s->norm, X, T, count, nullptr, grad, loss, true);
+    SHIP_OK(hipGetLastError());
+    return MPM_OK;
+}
+
+int mpm_surrogate_fit_norm(mpm_surrogate* s, int64_t count, const float* X, const float* T) {
+    if (!s || count < 1 || !X || !T) return sfail(s, MPM_EINVAL, "bad normalisation arguments");
+    sur_norm(s->stream, X, T, count, s->norm);
+    SHIP_OK(hipGetLastError());
+    return MPM_OK;
+}
+
+int mpm_surrogate_train(mpm_surrogate* s, int64_t count, const float* X, const float* T, int32_t steps, int32_t batch,
+                        float lr, uint64_t seed, float* loss_host) {
+    if (!s || count < 1 || !X || !T || steps < 0 || batch < 16 || !(lr > 0.0f))
+        return sfail(s, MPM_EINVAL, "bad training arguments");
+    if (count > INT32_MAX) return sfail(s, MPM_EINVAL, "too many training rows");
+    if (batch > s->idx_cap) {
+        (void)hipFree(s->idx);
+        s->idx = nullptr;
+        SHIP_OK(hipMalloc(&s->idx, sizeof(int) * batch));
+        s->idx_cap = batch;
+    }
+    if (steps > s->loss_cap) {
+        (void)hipFree(s->loss);
+        s->loss = nullptr;
+        SHIP_OK(hipMalloc(&s->loss, sizeof(float) * steps));
+        s->loss_cap = steps;
+    }
+    for (int k = 0; k < steps; ++k) {
+        sur_indices(s->stream, seed, s->step, batch, count, s->idx);
+        sur_grad(s->stream, 1, s->theta, s->norm, X, T, batch, s->idx, s->grad, s->loss + k, true);
+        sur_adam(s->stream, s->theta, s->grad, s->m, s->v, s->step + 1, lr);
+        ++s->step;
+    }
+    SHIP_OK(hipGetLastError());
+    if (loss_host && steps > 0)
+        SHIP_OK(hipMemcpyAsync(loss_host, s->loss, sizeof(float) * steps, hipMemcpyDeviceToHost, s->stream));
+    SHIP_OK(hipStreamSynchronize(s->stream));
+    return MPM_OK;
+}
+
+int mpm_use_surrogate(mpm_ctx* c, int32_t scene, const mpm_surrogate* s, int32_t mode, float tol, float dt_ref) {
+    if (!c) return MPM_EINVAL;
+    if (int r = scene_arg(c, scene)) return r;
+    if (mode < 0 || mode > 2) return fail(c, MPM_EINVAL, "mode must be exact (0), surrogate (1) or closed form (2)");
+    if (mode == 1 && !s) return fail(c, MPM_EINVAL, "the surrogate mode needs a surrogate");
+    if (mode == 1 && (!(tol > 0.0f) || !(dt_ref > 0.0f))) return fail(c, MPM_EINVAL, "tol and dt_ref must be positive");
+    if (mode != 0 && (!c->sh[scene].has_mat || c->sh[scene].mat.kind != MPM_SNOW))
+        return fail(c, MPM_EINVAL, "only snow scenes take the surrogate (add the scene's particles first)");
+    if (s) {
+        c->sur_theta = s->theta;
+        c->sur_norm = s->norm;
+        c->sur_tol = tol;
+        c->sur_dt_ref = dt_ref;
+    }
+    c->table[scene].ret = mode;
+    c->table[scene].E = c->sh[scene].has_mat ? c->sh[scene].mat.E : 0.0f;
+    HIP_OK(c, hipMemcpyAsync(c->scene_dev + scene, &c->table[scene], sizeof(Scene), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    c->sur_any = 0;
+    for (int k = 0; k < c->nsc; ++k) c->sur_any |= c->table[k].ret != 0;
+    if (!c->sur_any) c->sur_theta = c->sur_norm = nullptr;
+    if (c->sur_any && !c->sur_theta && mode == 1) return fail(c, MPM_EINVAL, "no surrogate attached");
+    drop_graphs(c);  // recorded kernels carry the old choice
+    return MPM_OK;
+}
+
+int mpm_surrogate_sample(mpm_ctx* c, int32_t scene, float dt_ref, int64_t max_count, float* X, float* T,
+                         int64_t* written) {
+    if (!c) return MPM_EINVAL;
+    if (int r = scene_arg(c, scene)) return r;
+    if (!X || !T || max_count < 0 || !(dt_ref > 0.0f)) return fail(c, MPM_EINVAL, "bad sampling arguments");
+    if (!c->sh[scene].has_mat || c->sh[scene].mat.kind != MPM_SNOW) return fail(c, MPM_EINVAL, "the scene is not snow");
+    unsigned long long* counter = nullptr;
+    HIP_OK(c, hipMalloc(&counter, sizeof(unsigned long long)));
+    sur_zero(c->stream, reinterpret_cast<float*>(counter), 2);
+    sur_sample(c->stream, c->S[c->cur], c->cap, (int)c->N, tables(c), scene, c->pending, c->sh[scene].mat.E, dt_ref,
+               max_count, X, T, counter);
+    unsigned long long n = 0;
+    const hipError_t e1 = hipGetLastError();
+    const hipError_t e2 = hipMemcpyAsync(&n, counter, sizeof n, hipMemcpyDeviceToHost, c->stream);
+    const hipError_t e3 = hipStreamSynchronize(c->stream);
+    (void)hipFree(counter);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return fail(c, MPM_EDEVICE, "sampling failed");
+    if (written) *written = (int64_t)(n < (unsigned long long)max_count ? n : (unsigned long long)max_count);
+    return check_error_word(c);
+}
 
 }  // extern "C"

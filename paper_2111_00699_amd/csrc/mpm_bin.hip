@@ -12,7 +12,11 @@
 // and block activation is a mark + compaction, deterministic and in block
 // order.  Sorting is a stable LSD radix sort with 8-bit digits, ranks taken
 // inside each wave64 from eight ballots (no atomics), so the permutation is
-// exactly a stable sort by particle code.
+// exactly a stable sort by particle code.  A batched context puts the scene's
+// rank above the Morton bits, so one sort orders every scene, scene by
+// scene, and every later list (blocks, chunks, physical blocks) comes out
+// rank-major; the per-rank ends of those lists let a substep run a prefix of
+// the ranks.
 #include "mpm_internal.h"
 
 namespace mpm {
@@ -58,13 +62,17 @@ __device__ __forceinline__ int block_excl_scan(int v, int* total) {
 // ------------------------------------------------------------ particle code
 // c = floor(x/dx + 1/2) = floor(x n - 1/2) + 1 per axis.  For power-of-two
 // n, x*n is exact in FP32 and x*n - 1/2 is exact wherever it matters, so the
-// code is bit-identical to one computed in FP64 from the same FP32 x.
-__global__ __launch_bounds__(WG) void k_keys(const float* __restrict__ S, int64_t cap, int N, float fn, int n,
+// code is bit-identical to one computed in FP64 from the same FP32 x.  The
+// scene's rank goes above the Morton bits.
+__global__ __launch_bounds__(WG) void k_keys(const float* __restrict__ S, int64_t cap, int N, Scenes T,
                                              uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
                                              int* __restrict__ ctl) {
     const int j = blockIdx.x * WG + threadIdx.x;
     if (j >= N) return;
-    uint32_t code = 0;
+    const Scene& sc = T.scene[__float_as_int(S[FSID * cap + j])];
+    const float fn = sc.P.fn;
+    const int n = sc.P.n;
+    uint32_t code = (uint32_t)sc.rank << T.shift;
     unsigned err = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -232,6 +240,7 @@ struct OpChunks {
     int N, chunk;
     Chunk* out;
     int* gchunk;
+    Scenes T;
     __device__ int len(int g) const {
         const int ng = ctl[CTL_NGB];
         const int end = (g + 1 < ng) ? gstart[g + 1] : N;
@@ -242,7 +251,9 @@ struct OpChunks {
         return (len(g) + chunk - 1) / chunk;
     }
     __device__ void emit(int g, int off, int k) const {
-        const uint32_t code = gcode[g];
+        const int bshift = T.shift - 6;
+        const uint32_t code = gcode[g] & ((1u << bshift) - 1u);
+        const int scene = T.rank_scene[gcode[g] >> bshift];
         const int packed = (int)(compact3(code) | (compact3(code >> 1) << 10) | (compact3(code >> 2) << 20));
         const int s0 = gstart[g], l = len(g);
         gchunk[g] = off;
@@ -251,7 +262,7 @@ struct OpChunks {
             c.start = s0 + i * chunk;
             c.count = min(chunk, l - i * chunk);
             c.block = packed;
-            c.pad = g;
+            c.scene = scene;
             out[off + i] = c;
         }
     }
@@ -291,44 +302,88 @@ __global__ __launch_bounds__(WG) void k_permute_chunks(const float* __restrict__
     }
 }
 
+__global__ __launch_bounds__(WG) void k_copy_codes(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src,
+                                                   int n, uint32_t mask) {
+    const int i = blockIdx.x * WG + threadIdx.x;
+    if (i < n) dst[i] = src[i] & mask;
+}
+
 __global__ __launch_bounds__(WG) void k_fill(int* __restrict__ p, int v, int n) {
     const int i = blockIdx.x * WG + threadIdx.x;
     if (i < n) p[i] = v;
 }
 
 // Mark the 3x3x3 neighbourhood of every geometric block as physical and
-// record each geometric block's index at its own (padded) position.
+// record each geometric block's index at its own (padded) position, in the
+// block grid of the block's scene.
 __global__ __launch_bounds__(WG) void k_dilate(const uint32_t* __restrict__ gcode, const int* __restrict__ ctl,
-                                               int NB, int* __restrict__ state, int* __restrict__ gindex) {
+                                               Scenes T, int* __restrict__ state, int* __restrict__ gindex) {
     const int total = ctl[CTL_NGB] * 27;
+    const int bshift = T.shift - 6;
     for (int t = blockIdx.x * WG + threadIdx.x; t < total; t += gridDim.x * WG) {
         const int g = t / 27, o = t % 27;
-        const uint32_t code = gcode[g];
+        const uint32_t code = gcode[g] & ((1u << bshift) - 1u);
+        const Scene& sc = T.scene[T.rank_scene[gcode[g] >> bshift]];
+        const int NB = sc.P.NB;
         const int B0 = (int)compact3(code), B1 = (int)compact3(code >> 1), B2 = (int)compact3(code >> 2);
         const int bx = B0 + (o % 3);  // (B - 1) + o + 1 in padded coordinates
         const int by = B1 + (o / 3) % 3;
         const int bz = B2 + o / 9;
-        state[(bz * NB + by) * NB + bx] = 1;
-        if (o == 13) gindex[(bz * NB + by) * NB + bx] = g;  // o = (1,1,1): the block itself
+        const int b = sc.brick_base + (bz * NB + by) * NB + bx;
+        state[b] = 1;
+        if (o == 13) gindex[b] = g;  // o = (1,1,1): the block itself
     }
 }
 
+// Per-rank ends of the sorted particles, geometric blocks, chunks and
+// physical blocks (binary searches over the rank-major lists).
+__global__ __launch_bounds__(WG) void k_rank_ends(const uint32_t* __restrict__ keys, int N,
+                                                  const uint32_t* __restrict__ gcode, const Chunk* __restrict__ chunks,
+                                                  const int* __restrict__ active, const int* __restrict__ ctl,
+                                                  Scenes T) {
+    for (int r = threadIdx.x; r < T.S; r += WG) {
+        auto upper = [&](int n, auto rank_at) {  // first index whose rank exceeds r
+            int lo = 0, hi = n;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (rank_at(mid) <= r)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            return lo;
+        };
+        T.rank_end[RE_PART * T.S + r] = upper(N, [&](int i) { return (int)(keys[i] >> T.shift); });
+        T.rank_end[RE_GBLOCK * T.S + r] =
+            upper(ctl[CTL_NGB], [&](int i) { return (int)(gcode[i] >> (T.shift - 6)); });
+        T.rank_end[RE_CHUNK * T.S + r] = upper(ctl[CTL_NCHUNK], [&](int i) { return T.scene[chunks[i].scene].rank; });
+        T.rank_end[RE_ACTIVE * T.S + r] =
+            upper(ctl[CTL_NACTIVE], [&](int i) { return active[i] >= T.rank_brick[r + 1] ? r + 1 : r; });
+    }
+}
+
+// The rebuild also starts the overflow lists and fallback counts afresh.
 __global__ void k_finish_rebuild(int* ctl, int* gchunk) {
     ctl[CTL_REBUILD] = 0;
+    ctl[CTL_OVF] = ctl[CTL_OVF + 1] = 0;
+    ctl[CTL_FB] = ctl[CTL_FB + 1] = 0;
     gchunk[ctl[CTL_NGB]] = ctl[CTL_NCHUNK];
 }
 
 }  // namespace
 
-void enqueue_rebuild(hipStream_t st, const Step& P, float* S_cur, float* S_alt, int* id_cur, int* id_alt, int64_t cap,
-                     int N, int chunk, int spread, BinBuffers& B, int* ctl, int nbricks) {
+void enqueue_copy_codes(hipStream_t st, uint32_t* dst, const uint32_t* src, int count, uint32_t mask) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_copy_codes, dim3(cdiv(count, WG)), dim3(WG), 0, st, dst, src, count, mask);
+}
+
+void enqueue_rebuild(hipStream_t st, const Scenes& T, float* S_cur, float* S_alt, int* id_cur, int* id_alt,
+                     int64_t cap, int N, int chunk, int spread, BinBuffers& B, int* ctl, int nbricks, int key_bits) {
     const int nb = cdiv(N > 0 ? N : 1, WG);
     // 1. particle codes
-    hipLaunchKernelGGL(k_keys, dim3(nb), dim3(WG), 0, st, S_cur, cap, N, P.fn, P.n, B.keys[0], B.vals[0], ctl);
+    hipLaunchKernelGGL(k_keys, dim3(nb), dim3(WG), 0, st, S_cur, cap, N, T, B.keys[0], B.vals[0], ctl);
     // 2. stable radix sort of (code, position)
-    int bits = 0;
-    while ((1 << bits) < P.n) ++bits;
-    const int passes = (3 * bits + 7) / 8;
+    const int passes = (key_bits + 7) / 8;
     const int tiles = cdiv(N > 0 ? N : 1, RS_TILE);
     int cur = 0;
     for (int p = 0; p < passes; ++p) {
@@ -341,7 +396,7 @@ void enqueue_rebuild(hipStream_t st, const Step& P, float* S_cur, float* S_alt, 
     B.sorted = cur;  // slot holding the sorted codes and their source positions
     // 3. geometric blocks and work chunks
     device_scan(st, OpGBlocks{B.keys[cur], N, B.gstart, B.gcode}, N, B.scan_tiles, ctl + CTL_NGB);
-    device_scan(st, OpChunks{B.gstart, B.gcode, ctl, N, chunk, B.chunks, B.gchunk}, N, B.scan_tiles,
+    device_scan(st, OpChunks{B.gstart, B.gcode, ctl, N, chunk, B.chunks, B.gchunk, T}, N, B.scan_tiles,
                 ctl + CTL_NCHUNK);
     // 4. gather the whole particle state into (chunk-spread) sorted order
     hipLaunchKernelGGL(k_permute_chunks, dim3(2048), dim3(WG), 0, st, S_cur, S_alt, id_cur, id_alt, B.sorted_ids,
@@ -349,9 +404,10 @@ void enqueue_rebuild(hipStream_t st, const Step& P, float* S_cur, float* S_alt, 
     // 5. physical blocks: 3x3x3 dilation, compacted in padded linear order
     hipLaunchKernelGGL(k_fill, dim3(cdiv(nbricks, WG)), dim3(WG), 0, st, B.brick_state, 0, nbricks);
     hipLaunchKernelGGL(k_fill, dim3(cdiv(nbricks, WG)), dim3(WG), 0, st, B.gindex, -1, nbricks);
-    hipLaunchKernelGGL(k_dilate, dim3(512), dim3(WG), 0, st, B.gcode, ctl, P.NB, B.brick_state, B.gindex);
+    hipLaunchKernelGGL(k_dilate, dim3(512), dim3(WG), 0, st, B.gcode, ctl, T, B.brick_state, B.gindex);
     device_scan(st, OpActive{B.brick_state, B.active}, nbricks, B.scan_tiles, ctl + CTL_NACTIVE);
     hipLaunchKernelGGL(k_finish_rebuild, dim3(1), dim3(1), 0, st, ctl, B.gchunk);
+    hipLaunchKernelGGL(k_rank_ends, dim3(1), dim3(WG), 0, st, B.keys[cur], N, B.gcode, B.chunks, B.active, ctl, T);
 }
 
 }  // namespace mpm

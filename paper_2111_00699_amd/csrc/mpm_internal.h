@@ -11,7 +11,9 @@ namespace mpm {
 
 // ----------------------------------------------------------------- layout
 // Particle state: one FP32 array per scalar field, field f at S + f * cap.
-enum Field : int { FX = 0, FV = 3, FC = 6, FF = 15, FS = 24, NF = 25 };
+// FSID holds the particle's scene index as integer bits; it moves with the
+// particle through the rebuild permutation.
+enum Field : int { FX = 0, FV = 3, FC = 6, FF = 15, FS = 24, FSID = 25, NF = 26 };
 
 constexpr int WG = 256;       // threads per workgroup (four wave64s)
 constexpr int TILE = 12;      // nodes per axis reachable from one particle block (3 blocks)
@@ -28,11 +30,14 @@ enum Ctl : int {
     CTL_OVF = 5,       // overflow-block counts, two slots by substep parity
     CTL_SCAN = 8,      // scratch total of a device scan
     CTL_FB = 9,        // in-zone particles of chunks whose tile did not fit, two slots by substep parity
+    CTL_STEP = 11,     // substeps completed (advanced by G2P; stamps the blocks the grid update touched)
     CTL_WORDS = 16,
     // 64-bit running counters follow the 16 words (byte offset 64):
     CTL64_FALLBACK_CHUNKS = 0,     // P2G chunks whose node box did not fit the LDS tile
     CTL64_GLOBAL_PARTICLES = 1,    // particles P2G scattered with global atomics
-    CTL64_WORDS = 2,
+    CTL64_SUR_PARTICLES = 2,       // snow return maps done by the surrogate / closed-form path
+    CTL64_SUR_FALLBACKS = 3,       // ... that fell back to the exact path
+    CTL64_WORDS = 4,
     CTL_ALLOC_WORDS = CTL_WORDS + 2 * CTL64_WORDS
 };
 
@@ -64,8 +69,60 @@ struct Step {
 struct Chunk {
     int start, count;
     int block;  // packed block coordinates Bx | By << 10 | Bz << 20
-    int pad;
+    int scene;
 };
+
+// One scene of a context: its grid and time step, its material, where its
+// dense block grid starts in the shared brick space, and its rank (position
+// in the particle-code order; scenes are ranked by increasing dt, so the
+// scenes still running late in a frame form a prefix of the ranks).
+struct Scene {
+    Step P;
+    Mat M;
+    int brick_base;
+    int rank;
+    int ret;  // snow return map: 0 exact (Jacobi), 1 learned surrogate, 2 closed form without the network
+    float E;  // Young's modulus (scales the surrogate's stress outputs)
+};
+
+// Device tables of a context's scenes.  `rank_end` is filled at every
+// rebuild: for rank r, rank_end[k*S + r] is the end (exclusive) of the
+// entries of ranks <= r in the sorted particles (k = 0), geometric blocks
+// (k = 1), chunks (k = 2) and physical blocks (k = 3).
+struct Scenes {
+    const Scene* scene;     // [S] by scene index
+    const int* rank_scene;  // [S] scene index of each rank
+    const int* rank_brick;  // [S + 1] first brick of each rank's grid; the brick space is laid out in rank order
+    int* rank_end;          // [4 * S]
+    int S;                  // number of scenes
+    int shift;              // the rank sits at bit `shift` of a particle code (shift = 3 log2(max n))
+    const float* sur_theta;  // surrogate parameters and normalisation (NULL when no scene uses it)
+    const float* sur_norm;
+    float sur_tol;           // residual tolerance of the learned map
+    float sur_gap;           // smallest eigenvalue separation (units of the spread) for the closed form
+    float sur_dt_ref;        // time step the surrogate was trained at
+    int sur_any;             // some scene maps its snow without SVD (ret != 0)
+};
+
+enum RankEnd : int { RE_PART = 0, RE_GBLOCK = 1, RE_CHUNK = 2, RE_ACTIVE = 3 };
+
+// Entries of kind k that belong to the first `act` ranks (act = S: all).
+__device__ __forceinline__ int rank_limit(const Scenes& T, const int* ctl, int act, int k, int ctl_word) {
+    return act >= T.S ? ctl[ctl_word] : T.rank_end[k * T.S + act - 1];
+}
+
+// Rank whose brick range holds brick b (binary search over S + 1 bases).
+__device__ __forceinline__ int rank_of_brick(const Scenes& T, int b) {
+    int lo = 0, hi = T.S - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (T.rank_brick[mid] <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
 
 // ------------------------------------------------------------ launchers
 // Binning and sorting (mpm_bin.hip).
@@ -76,9 +133,9 @@ struct BinBuffers {
     int* gstart;       // [cap + 1]
     uint32_t* gcode;   // [cap]
     Chunk* chunks;     // [cap]
-    int* brick_state;  // [NB^3] 0 idle, 1 physical block of the rebuild, 2 overflow this substep
-    int* active;       // [NB^3]
-    int* gindex;       // [NB^3] geometric-block index of each particle block (padded coords), -1 if none
+    int* brick_state;  // [bricks] 0 idle, 1 physical block of the rebuild, 2 overflow this substep
+    int* active;       // [bricks]
+    int* gindex;       // [bricks] geometric-block index of each particle block (padded coords), -1 if none
     int* gchunk;       // [cap + 1] first chunk of each geometric block
     int* sorted_ids;   // [cap] insertion id of each particle in particle-code order
     int sorted;        // which keys/vals slot holds the last sorted codes (host side)
@@ -92,8 +149,12 @@ __host__ __device__ inline int chunk_stride(int count) {
     return (count % 3) ? 9 : (count % 11) ? 11 : (count % 13) ? 13 : 17;
 }
 
-void enqueue_rebuild(hipStream_t st, const Step& P, float* S_cur, float* S_alt, int* id_cur, int* id_alt,
-                     int64_t cap, int N, int chunk, int spread, BinBuffers& B, int* ctl, int nbricks);
+// Codes, stable radix sort, blocks, chunks and the gather into sorted order
+// for all scenes at once; `key_bits` is the width of the particle codes.
+void enqueue_rebuild(hipStream_t st, const Scenes& T, float* S_cur, float* S_alt, int* id_cur, int* id_alt,
+                     int64_t cap, int N, int chunk, int spread, BinBuffers& B, int* ctl, int nbricks, int key_bits);
+// dst[i] = src[i] & mask (particle codes without the rank bits).
+void enqueue_copy_codes(hipStream_t st, uint32_t* dst, const uint32_t* src, int count, uint32_t mask);
 
 // Substep kernels (mpm_step.hip).
 struct GridBuffers {
@@ -115,24 +176,27 @@ struct Launch {
 // Threads per P2G/G2P workgroup for a chunk size: one particle per thread.
 inline int chunk_threads(int chunk) { return chunk <= 128 ? 128 : chunk <= 256 ? 256 : 512; }
 
-void enqueue_p2g(hipStream_t st, const Launch& L, const Step& P, const Mat& M, float* S, int64_t cap,
-                 const Chunk* chunks, int* ctl, GridBuffers& G, int* brick_state, int pending, int parity,
-                 int global_atomics, int nbricks, int chunk);
+// `act`: the substep advances the scenes of the first `act` ranks only.
+void enqueue_p2g(hipStream_t st, const Launch& L, const Scenes& T, float* S, int64_t cap, const Chunk* chunks,
+                 int* ctl, GridBuffers& G, int* brick_state, int pending, int parity, int global_atomics,
+                 int nbricks, int chunk, int act);
 int p2g_grid_size(int cus, int chunk);
 // Workgroups of `threads` threads that fit on one compute unit at once, from
 // the kernel's register and LDS use (gfx950: 512 VGPRs per lane and SIMD,
 // 8 waves per SIMD, 4 SIMDs, `lds_per_cu` bytes of LDS).
 int wgs_per_cu(const void* fn, int threads);
-void enqueue_grid(hipStream_t st, const Launch& L, const Step& P, const BinBuffers& B, int* ctl, GridBuffers& G,
-                  int parity, int step);
-void enqueue_g2p(hipStream_t st, const Launch& L, const Step& P, float* S, int64_t cap, const Chunk* chunks,
-                 int* ctl, const GridBuffers& G, int* host_flag, int lds_box, int parity, int fb_limit, int chunk);
-void enqueue_materialize(hipStream_t st, const Step& P, const Mat& M, float* S, int64_t cap, int N);
-void enqueue_insert(hipStream_t st, float* S, int* ids, int64_t cap, int N0, int count, const float* x,
-                    const float* v, const float* C, const float* F, const float* s, int* ctl);
-void enqueue_read(hipStream_t st, const Step& P, const Mat& M, const float* S, const int* ids, int64_t cap, int N,
-                  int pending, float* x, float* v, float* C, float* F, float* s);
-void enqueue_read_grid(hipStream_t st, const Step& P, const GridBuffers& G, int step, float* m, float* v);
+void enqueue_grid(hipStream_t st, const Launch& L, const Scenes& T, const BinBuffers& B, int* ctl, GridBuffers& G,
+                  int parity, int nbricks, int act);
+// host_flag may be NULL (graph-recorded frames read no flag).
+void enqueue_g2p(hipStream_t st, const Launch& L, const Scenes& T, float* S, int64_t cap, const Chunk* chunks,
+                 int* ctl, const GridBuffers& G, int* host_flag, int lds_box, int parity, int fb_limit, int chunk,
+                 int act);
+void enqueue_materialize(hipStream_t st, const Scenes& T, float* S, int64_t cap, int N);
+void enqueue_insert(hipStream_t st, float* S, int* ids, int64_t cap, int N0, int count, int scene, int id0,
+                    const float* x, const float* v, const float* C, const float* F, const float* s, int* ctl);
+void enqueue_read(hipStream_t st, const Scenes& T, const float* S, const int* ids, int64_t cap, int N, int scene,
+                  int Ns, int pending, float* x, float* v, float* C, float* F, float* s);
+void enqueue_read_grid(hipStream_t st, const Scene& sc, const GridBuffers& G, int step, float* m, float* v);
 void query_launch(Launch& L, int chunk);
 
 // ----------------------------------------------------------- device math
@@ -271,16 +335,19 @@ __device__ __forceinline__ void material_step(const Mat& M, float dt, int pendin
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 sc[k] = fminf(fmaxf(sig[k], M.lo), M.hi);
-                r[k] = __fdividef(sc[k], sig[k]);
+                r[k] = __fdividef(sc[k], sig[k]) - 1.0f;  // zero inside the yield surface
             }
+            // F_E' = U diag(sc/sig) U^T Fhat = Fhat + U diag(sc/sig - 1) U^T Fhat: the
+            // rounding of U (orthogonal only to FP32 precision) then scales with the
+            // plastic correction instead of adding strain noise to elastic states.
             float R[6];
-            sym_from_eig(U, r[0], r[1], r[2], R);  // F_E' = U diag(sc/sig) U^T Fhat
+            sym_from_eig(U, r[0], r[1], r[2], R);
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
                 const float f0 = Fh[0 * 3 + b], f1 = Fh[1 * 3 + b], f2 = Fh[2 * 3 + b];
-                F[0 * 3 + b] = R[0] * f0 + R[1] * f1 + R[2] * f2;
-                F[1 * 3 + b] = R[1] * f0 + R[3] * f1 + R[4] * f2;
-                F[2 * 3 + b] = R[2] * f0 + R[4] * f1 + R[5] * f2;
+                F[0 * 3 + b] = f0 + (R[0] * f0 + R[1] * f1 + R[2] * f2);
+                F[1 * 3 + b] = f1 + (R[1] * f0 + R[3] * f1 + R[4] * f2);
+                F[2 * 3 + b] = f2 + (R[2] * f0 + R[4] * f1 + R[5] * f2);
             }
             const float Jc = sc[0] * sc[1] * sc[2];
             s = s * J / Jc;

@@ -66,9 +66,10 @@ __device__ __forceinline__ void axis_offsets(int base, int blockstride, int loca
     }
 }
 
-// Mark the (at most 2x2x2) blocks of a stencil; blocks outside the physical
-// set of the last rebuild are appended once to the overflow list.
-__device__ __forceinline__ void activate_blocks(const Stencil& s, const Step& P, int* brick_state, int* ovf,
+// Mark the (at most 2x2x2) blocks of a stencil in the block grid of its
+// scene (NB padded blocks per axis, first brick `base`); blocks outside the
+// physical set of the last rebuild are appended once to the overflow list.
+__device__ __forceinline__ void activate_blocks(const Stencil& s, int NB, int base, int* brick_state, int* ovf,
                                                 int* ovf_count, int nbricks, unsigned& err) {
     int lo[3], hi[3];
 #pragma unroll
@@ -79,7 +80,7 @@ __device__ __forceinline__ void activate_blocks(const Stencil& s, const Step& P,
     for (int bz = lo[2]; bz <= hi[2]; ++bz)
         for (int by = lo[1]; by <= hi[1]; ++by)
             for (int bx = lo[0]; bx <= hi[0]; ++bx) {
-                const int b = (bz * P.NB + by) * P.NB + bx;
+                const int b = base + (bz * NB + by) * NB + bx;
                 if (__hip_atomic_load(&brick_state[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
                     atomicCAS(&brick_state[b], 0, 2) == 0) {
                     const int k = atomicAdd(ovf_count, 1);

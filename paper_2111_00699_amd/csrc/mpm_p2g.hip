@@ -27,7 +27,10 @@
 // and rarely hit one LDS address (same-address atomics serialize).
 // Particles outside their free zone (before a late rebuild) scatter straight
 // to global atomics and activate the blocks they touch.
+#include <type_traits>
+
 #include "mpm_kernels.h"
+#include "mpm_mlp.h"
 
 namespace mpm {
 
@@ -35,19 +38,195 @@ namespace {
 
 constexpr int CT = 512;  // compact tile capacity in nodes
 
-// NT threads per workgroup = the largest chunk it takes (256 or 512).
-template <bool GLOBAL_ONLY, int NT>
+// ------------------------------------------------ snow return map without SVD
+// Eigenvalues of the symmetric b = [b0 b1 b2; . b3 b4; . . b5] as
+// q + p mu_k, mu descending, by the trigonometric solution of the
+// characteristic cubic of the normalised deviator Bn = (b - q I)/p (whose
+// eigenvalues mu satisfy mu^3 - 3 mu - det Bn = 0).  Returns false when b is
+// too close to a multiple of the identity for the deviator to be resolved.
+__device__ __forceinline__ bool eig_closed(const float b[6], float& q, float& p, float mu[3], float Bn[6]) {
+    q = (b[0] + b[3] + b[5]) * (1.0f / 3.0f);
+    const float d0 = b[0] - q, d1 = b[3] - q, d2 = b[5] - q;
+    const float p2 = d0 * d0 + d1 * d1 + d2 * d2 + 2.0f * (b[1] * b[1] + b[2] * b[2] + b[4] * b[4]);
+    p = sqrtf(p2 * (1.0f / 6.0f));
+    if (!(p > 2e-5f * fabsf(q))) return false;
+    const float ip = 1.0f / p;
+    Bn[0] = d0 * ip; Bn[1] = b[1] * ip; Bn[2] = b[2] * ip;
+    Bn[3] = d1 * ip; Bn[4] = b[4] * ip; Bn[5] = d2 * ip;
+    const float det = Bn[0] * (Bn[3] * Bn[5] - Bn[4] * Bn[4]) - Bn[1] * (Bn[1] * Bn[5] - Bn[4] * Bn[2]) +
+                      Bn[2] * (Bn[1] * Bn[4] - Bn[3] * Bn[2]);
+    const float phi = acosf(fminf(fmaxf(0.5f * det, -1.0f), 1.0f)) * (1.0f / 3.0f);
+    mu[0] = 2.0f * cosf(phi);
+    mu[2] = 2.0f * cosf(phi + 2.09439510f);  // + 2 pi / 3
+    mu[1] = -mu[0] - mu[2];
+    return true;
+}
+
+// sum_k c_k L_k(Bn) = A2 Bn^2 + A1 Bn + A0 I, with L_k the Lagrange
+// polynomials on the (distinct) eigenvalues mu: each L_k(Bn) is the
+// projector on eigenvector k (Sylvester's formula), so isotropic functions
+// of b are built without eigenvectors.
+__device__ __forceinline__ void lagrange(const float mu[3], const float c[3], float& A2, float& A1, float& A0) {
+    A2 = A1 = A0 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int i = (k + 1) % 3, j = (k + 2) % 3;
+        const float w = c[k] / ((mu[k] - mu[i]) * (mu[k] - mu[j]));
+        A2 += w;
+        A1 += w * mu[k];  // -(mu_i + mu_j) = mu_k since the mu sum to zero
+        A0 += w * mu[i] * mu[j];
+    }
+}
+
+// The snow return map and Kirchhoff stress of every lane's particle from the
+// eigenvalues of b = F^ F^T alone: F_E' = (I + sum_k delta_k L_k) F^ and
+// tau = tau_bar I + sum_k (tau_k - tau_bar) L_k, with delta_k = s'_k/s_k - 1.
+// The projected values come from the exact clamp (ret = 2) or from the
+// network (ret = 1; all lanes of the wave run it on MFMA).  A lane falls
+// back to the exact (Jacobi) map when its eigenvalues are too close, its
+// particle is inverted, or (network) the prediction leaves the yield
+// surface or changes the total volume by more than the tolerance.
+template <bool NET>
+__device__ void snow_without_svd(const mlp::NetLds& net, float* stage, const Scenes& T, const Scene& sc, float dt,
+                                 int pending, bool have, const float C[9], float F[9], float& s, float tau[6],
+                                 bool& fell_back) {
+    const Mat& M = sc.M;
+    float Fh[9];
+    if (pending) {
+        advance_gradient(C, dt, F, Fh);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Fh[k] = F[k];
+    }
+    float b[6];
+    b[0] = Fh[0] * Fh[0] + Fh[1] * Fh[1] + Fh[2] * Fh[2];
+    b[1] = Fh[0] * Fh[3] + Fh[1] * Fh[4] + Fh[2] * Fh[5];
+    b[2] = Fh[0] * Fh[6] + Fh[1] * Fh[7] + Fh[2] * Fh[8];
+    b[3] = Fh[3] * Fh[3] + Fh[4] * Fh[4] + Fh[5] * Fh[5];
+    b[4] = Fh[3] * Fh[6] + Fh[4] * Fh[7] + Fh[5] * Fh[8];
+    b[5] = Fh[6] * Fh[6] + Fh[7] * Fh[7] + Fh[8] * Fh[8];
+    float q, p, mu[3], Bn[6];
+    bool use = have && eig_closed(b, q, p, mu, Bn) && det3(Fh) > 0.0f;
+    use = use && (mu[0] - mu[1]) >= T.sur_gap && (mu[1] - mu[2]) >= T.sur_gap;
+    float sh[3], sn[3], tk[3], Jpn;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) sh[k] = use ? sqrtf(fmaxf(q + p * mu[k], 1e-30f)) : 1.0f;
+    const float Jp = use ? s : 1.0f;
+    if (NET && pending) {
+        // features [s, ln s, J_P, ln J_P, h, dt/dt_ref, s1 s2 s3, 1], one 16-sample tile at a time
+        float xf[SUR_IN] = {sh[0], sh[1], sh[2], logf(sh[0]), logf(sh[1]), logf(sh[2]), Jp, logf(Jp),
+                            expf(M.xi * (1.0f - Jp)), dt / T.sur_dt_ref, sh[0] * sh[1] * sh[2], 1.0f};
+        const int lane = threadIdx.x & 63, g = lane >> 4, sl = lane & 15;
+        float* xs = stage;        // [16][16]
+        float* ys = stage + 256;  // [16][16]
+        float yv[SUR_OUT];
+        for (int t = 0; t < 4; ++t) {
+            if ((lane >> 4) == t) {
+#pragma unroll
+                for (int f = 0; f < 16; ++f) xs[sl * 16 + f] = f < SUR_IN ? (xf[f] - net.imu[f]) / net.isd[f] : 0.0f;
+            }
+            __builtin_amdgcn_wave_barrier();
+            float h1[4][4], h2[4][4], y[4];
+            mlp::forward_tile<true>(net, xs, h1, h2, y);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) ys[sl * 16 + 4 * g + r] = y[r];
+            __builtin_amdgcn_wave_barrier();
+            if ((lane >> 4) == t) {
+#pragma unroll
+                for (int o = 0; o < SUR_OUT; ++o) yv[o] = ys[sl * 16 + o] * net.osd[o] + net.omu[o];
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        // outputs [s', ln(s'/s), tau/E, J_P'/J_P, h', s1's2's3']
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            sn[k] = sh[k] * expf(yv[3 + k]);
+            tk[k] = yv[6 + k] * sc.E;
+        }
+        Jpn = Jp * yv[9];
+        float res_y = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) res_y = fmaxf(res_y, fmaxf(M.lo - sn[k], sn[k] - M.hi));
+        const float res_v = fabsf(logf(sn[0] * sn[1] * sn[2] * Jpn) - logf(sh[0] * sh[1] * sh[2] * Jp));
+        const bool fin = isfinite(tk[0] + tk[1] + tk[2] + Jpn + sn[0] + sn[1] + sn[2]);
+        use = use && fin && res_y <= T.sur_tol && res_v <= T.sur_tol;
+    } else {
+        // exact clamp; with nothing pending the stored state is already projected
+        // (as in the exact path), so only the stress is evaluated
+#pragma unroll
+        for (int k = 0; k < 3; ++k) sn[k] = pending ? fminf(fmaxf(sh[k], M.lo), M.hi) : sh[k];
+        Jpn = Jp * (sh[0] * sh[1] * sh[2]) / (sn[0] * sn[1] * sn[2]);
+        const float h = expf(M.xi * (1.0f - Jpn));
+        const float Jn = sn[0] * sn[1] * sn[2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) tk[k] = 2.0f * M.mu * h * (sn[k] - 1.0f) * sn[k] + M.la * h * (Jn - 1.0f) * Jn;
+    }
+    fell_back = have && !use;
+    if (!have) return;
+    if (!use) {
+        material_step(M, dt, pending, C, F, s, tau);
+        return;
+    }
+    float B2[6];
+    B2[0] = Bn[0] * Bn[0] + Bn[1] * Bn[1] + Bn[2] * Bn[2];
+    B2[1] = Bn[0] * Bn[1] + Bn[1] * Bn[3] + Bn[2] * Bn[4];
+    B2[2] = Bn[0] * Bn[2] + Bn[1] * Bn[4] + Bn[2] * Bn[5];
+    B2[3] = Bn[1] * Bn[1] + Bn[3] * Bn[3] + Bn[4] * Bn[4];
+    B2[4] = Bn[1] * Bn[2] + Bn[3] * Bn[4] + Bn[4] * Bn[5];
+    B2[5] = Bn[2] * Bn[2] + Bn[4] * Bn[4] + Bn[5] * Bn[5];
+    // F_E' = G F^ with G = I + sum_k delta_k L_k
+    float dl[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dl[k] = sn[k] / sh[k] - 1.0f;
+    float A2, A1, A0;
+    lagrange(mu, dl, A2, A1, A0);
+    float G[6];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) G[e] = A2 * B2[e] + A1 * Bn[e];
+    G[0] += 1.0f + A0;
+    G[3] += 1.0f + A0;
+    G[5] += 1.0f + A0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float f0 = Fh[0 * 3 + c], f1 = Fh[1 * 3 + c], f2 = Fh[2 * 3 + c];
+        F[0 * 3 + c] = G[0] * f0 + G[1] * f1 + G[2] * f2;
+        F[1 * 3 + c] = G[1] * f0 + G[3] * f1 + G[4] * f2;
+        F[2 * 3 + c] = G[2] * f0 + G[4] * f1 + G[5] * f2;
+    }
+    s = Jpn;
+    // tau = tau_bar I + sum_k (tau_k - tau_bar) L_k
+    const float tb = (tk[0] + tk[1] + tk[2]) * (1.0f / 3.0f);
+    const float dt3[3] = {tk[0] - tb, tk[1] - tb, tk[2] - tb};
+    lagrange(mu, dt3, A2, A1, A0);
+#pragma unroll
+    for (int e = 0; e < 6; ++e) tau[e] = A2 * B2[e] + A1 * Bn[e];
+    tau[0] += tb + A0;
+    tau[3] += tb + A0;
+    tau[5] += tb + A0;
+}
+
+// NT threads per workgroup = the largest chunk it takes (128, 256 or 512).
+// SUR: some scene maps its snow without SVD (closed form or network), so the
+// network is staged in LDS.
+template <bool GLOBAL_ONLY, int NT, bool SUR>
 __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, const Chunk* __restrict__ chunks,
                                             int* __restrict__ ctl, float* __restrict__ acc,
                                             float4* __restrict__ stage, int stage_nodes, int4* __restrict__ box,
-                                            int* __restrict__ brick_state, int* __restrict__ ovf, int parity, Step P,
-                                            Mat M, int pending, int nbricks) {
+                                            int* __restrict__ brick_state, int* __restrict__ ovf, int parity,
+                                            Scenes T, int pending, int nbricks, int act) {
     __shared__ double tq[GLOBAL_ONLY ? 1 : 4 * CT];
     __shared__ int red_i[6][NT / 64];
+    struct Empty {};
+    __shared__ typename std::conditional<SUR, mlp::NetLds, Empty>::type net;
+    __shared__ float sur_stage[SUR ? NT / 64 * 512 : 1];
+    if constexpr (SUR) {
+        if (T.sur_theta) mlp::load_net(net, T.sur_theta, T.sur_norm);
+        __syncthreads();
+    }
     unsigned err = 0;
+    unsigned n_sur = 0, n_fb = 0;
     int begin, end, stride;
-    xcd_split(ctl[CTL_NCHUNK], begin, end, stride);
-    const float dx = P.dx, dt = P.dt;
+    xcd_split(rank_limit(T, ctl, act, RE_CHUNK, CTL_NCHUNK), begin, end, stride);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     // this workgroup's slice of the staging buffer, filled front to back
     const int slice = (int)((int64_t)stage_nodes / gridDim.x);
@@ -55,6 +234,10 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
     int used = 0;
     for (int c = begin; c < end; c += stride) {
         const Chunk ch = chunks[c];
+        const Scene& sc = T.scene[ch.scene];
+        const Step P = sc.P;
+        const Mat M = sc.M;
+        const float dx = P.dx, dt = P.dt;
         const int count = ch.count;
         const int B[3] = {ch.block & 1023, (ch.block >> 10) & 1023, ch.block >> 20};
         const bool have = tid < count;
@@ -64,8 +247,13 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
         Stencil st;
         float q[3] = {0.f, 0.f, 0.f}, Ad[9];
         bool ok = false, in_zone = false;
+        float x[3] = {0.5f, 0.5f, 0.5f}, v[3] = {0.f, 0.f, 0.f}, C[9], F[9], s = 1.0f, tau[6];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            C[k] = 0.0f;
+            F[k] = (k % 4 == 0) ? 1.0f : 0.0f;
+        }
         if (have) {
-            float x[3], v[3], C[9], F[9], s;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 x[a] = S[(FX + a) * cap + p];
@@ -78,8 +266,22 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
 #pragma unroll
                 for (int k = 0; k < 9; ++k) F[k] = S[(FF + k) * cap + p];
             }
-            float tau[6];
-            material_step(M, dt, pending, C, F, s, tau);
+        }
+        bool sur_chunk = false;
+        if constexpr (SUR) {
+            sur_chunk = sc.ret != 0 && M.kind == MPM_SNOW;  // uniform over the workgroup
+            if (sur_chunk) {
+                bool fb = false;
+                if (sc.ret == 1)
+                    snow_without_svd<true>(net, sur_stage + wv * 512, T, sc, dt, pending, have, C, F, s, tau, fb);
+                else
+                    snow_without_svd<false>(net, sur_stage + wv * 512, T, sc, dt, pending, have, C, F, s, tau, fb);
+                n_sur += __popcll(__ballot(have && !fb));
+                n_fb += __popcll(__ballot(fb));
+            }
+        }
+        if (!sur_chunk && have) material_step(M, dt, pending, C, F, s, tau);
+        if (have) {
             if (pending) {  // the deferred update of the last G2P lands here
                 if (M.kind != MPM_WATER) {
 #pragma unroll
@@ -196,11 +398,13 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
                         }
                     }
             } else {
-                if (!in_zone) activate_blocks(st, P, brick_state, ovf, &ctl[CTL_OVF + parity], nbricks, err);
+                if (!in_zone)
+                    activate_blocks(st, P.NB, sc.brick_base, brick_state, ovf, &ctl[CTL_OVF + parity], nbricks, err);
                 int xo[3], yo[3], zo[3];
                 axis_offsets(st.base[0], 1, 0, xo);
                 axis_offsets(st.base[1], P.NB, 2, yo);
                 axis_offsets(st.base[2], P.NB * P.NB, 4, zo);
+                float* accs = acc + 4 * (int64_t)sc.brick_base * BLOCK_NODES;
 #pragma unroll
                 for (int o2 = 0; o2 < 3; ++o2)
 #pragma unroll
@@ -212,7 +416,7 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
 #pragma unroll
                         for (int o0 = 0; o0 < 3; ++o0) {
                             const float w = wyz * st.w[0][o0];
-                            float* a = acc + 4 * (xo[o0] + yo[o1] + zo[o2]);
+                            float* a = accs + 4 * (xo[o0] + yo[o1] + zo[o2]);
                             unsafeAtomicAdd(a + 0, w * M.mp);
                             unsafeAtomicAdd(a + 1, w * m0);
                             unsafeAtomicAdd(a + 2, w * m1);
@@ -236,15 +440,19 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
         }
     }
     if (err) atomicOr(&ctl[CTL_ERROR], (int)err);
+    if (SUR && (threadIdx.x & 63) == 0) {
+        if (n_sur) atomicAdd(&ctl64(ctl)[CTL64_SUR_PARTICLES], (unsigned long long)n_sur);
+        if (n_fb) atomicAdd(&ctl64(ctl)[CTL64_SUR_FALLBACKS], (unsigned long long)n_fb);
+    }
 }
 
 }  // namespace
 
 int p2g_grid_size(int cus, int chunk) {
     const int nt = chunk_threads(chunk);
-    const void* fn = nt == 128   ? reinterpret_cast<const void*>(k_p2g<false, 128>)
-                     : nt == 256 ? reinterpret_cast<const void*>(k_p2g<false, 256>)
-                                 : reinterpret_cast<const void*>(k_p2g<false, 512>);
+    const void* fn = nt == 128   ? reinterpret_cast<const void*>(k_p2g<false, 128, false>)
+                     : nt == 256 ? reinterpret_cast<const void*>(k_p2g<false, 256, false>)
+                                 : reinterpret_cast<const void*>(k_p2g<false, 512, false>);
     // Twice the resident workgroups: chunks differ in size, and a second wave
     // of workgroups evens out the per-XCD work split.
     int occ = 2 * wgs_per_cu(fn, nt);
@@ -253,20 +461,29 @@ int p2g_grid_size(int cus, int chunk) {
     return g < 8 ? 8 : (g / 8) * 8;
 }
 
-void enqueue_p2g(hipStream_t st, const Launch& L, const Step& P, const Mat& M, float* S, int64_t cap,
-                 const Chunk* chunks, int* ctl, GridBuffers& G, int* brick_state, int pending, int parity,
-                 int global_atomics, int nbricks, int chunk) {
-#define MPM_LAUNCH_P2G(GO, T)                                                                                \
-    hipLaunchKernelGGL((k_p2g<GO, T>), dim3(L.p2g_grid), dim3(T), 0, st, S, cap, chunks, ctl, G.acc, G.stage, \
-                       G.stage_nodes, G.box, brick_state, G.ovf[parity], parity, P, M, pending, nbricks)
+void enqueue_p2g(hipStream_t st, const Launch& L, const Scenes& T, float* S, int64_t cap, const Chunk* chunks,
+                 int* ctl, GridBuffers& G, int* brick_state, int pending, int parity, int global_atomics,
+                 int nbricks, int chunk, int act) {
+#define MPM_LAUNCH_P2G(GO, NT, SU)                                                                              \
+    hipLaunchKernelGGL((k_p2g<GO, NT, SU>), dim3(L.p2g_grid), dim3(NT), 0, st, S, cap, chunks, ctl, G.acc,        \
+                       G.stage, G.stage_nodes, G.box, brick_state, G.ovf[parity], parity, T, pending, nbricks, act)
+#define MPM_LAUNCH_P2G_NT(GO, SU)                        \
+    do {                                                 \
+        if (nt == 128)                                   \
+            MPM_LAUNCH_P2G(GO, 128, SU);                 \
+        else if (nt == 256)                              \
+            MPM_LAUNCH_P2G(GO, 256, SU);                 \
+        else                                             \
+            MPM_LAUNCH_P2G(GO, 512, SU);                 \
+    } while (0)
     const int nt = chunk_threads(chunk);
-    if (nt == 128) {
-        if (global_atomics) MPM_LAUNCH_P2G(true, 128); else MPM_LAUNCH_P2G(false, 128);
-    } else if (nt == 256) {
-        if (global_atomics) MPM_LAUNCH_P2G(true, 256); else MPM_LAUNCH_P2G(false, 256);
+    const bool sur = T.sur_any != 0;
+    if (global_atomics) {
+        if (sur) MPM_LAUNCH_P2G_NT(true, true); else MPM_LAUNCH_P2G_NT(true, false);
     } else {
-        if (global_atomics) MPM_LAUNCH_P2G(true, 512); else MPM_LAUNCH_P2G(false, 512);
+        if (sur) MPM_LAUNCH_P2G_NT(false, true); else MPM_LAUNCH_P2G_NT(false, false);
     }
+#undef MPM_LAUNCH_P2G_NT
 #undef MPM_LAUNCH_P2G
 }
 

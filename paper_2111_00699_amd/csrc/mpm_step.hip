@@ -5,21 +5,21 @@
 // mpm_p2g.hip.
 //
 // MI355X design:
-//  * Particles are processed in chunks that share one particle block, so
-//    every particle of a chunk inside its free zone scatters into the same
-//    12^3-node tile (the 3x3x3 physical blocks of the "Rebuild-Mapping"
-//    subsection).  The tile lives in LDS and takes native ds_add_f32
-//    atomics; only its non-empty nodes are flushed with native
-//    global_atomic_add_f32.  (The paper drops shared memory on V100 because
-//    float atomics there are emulated with CAS loops; on gfx950 both LDS and
-//    global float adds are native, so the same principle -- use only native
-//    atomics -- leads to an LDS tile.)
-//  * Chunks are dealt to the eight XCDs in contiguous ranges of the
+//  * The grid update is one wave64 per 4^3 block of the physical (and
+//    overflow) block lists.  It gathers each node from the FP64 tiles that
+//    P2G staged for the chunks of the 27 particle blocks around it (no
+//    global atomics on the tiled path), adds the global-path accumulator,
+//    then applies gravity and the wall condition and clears the accumulator.
+//  * G2P takes one chunk per workgroup and loads the chunk's node box (the
+//    box its P2G tile used) into LDS, so the 27-node gathers read LDS.
+//  * Work lists are dealt to the eight XCDs in contiguous ranges of the
 //    block-sorted order so each XCD's L2 sees a compact region of the grid.
-//  * The grid is a dense array of 4^3-node blocks over the padded domain; a
-//    particle that has left its free zone before the next rebuild scatters
-//    straight to global atomics and activates the blocks it touches, so a
-//    late rebuild never costs correctness.
+//  * The grid is a dense array of 4^3-node blocks per scene; a particle
+//    that has left its free zone before the next rebuild scatters straight
+//    to global atomics and activates the blocks it touches, so a late
+//    rebuild never costs correctness.
+//  * Every kernel reads its scene's grid, time step and material from the
+//    scene table, and a substep may run only the first `act` ranks.
 #include "mpm_kernels.h"
 
 namespace mpm {
@@ -37,19 +37,23 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, float4* __
                                              const int* __restrict__ ovf, int* __restrict__ brick_state,
                                              int* __restrict__ stamp, const int* __restrict__ gindex,
                                              const int* __restrict__ gchunk, const float4* __restrict__ stage,
-                                             const int4* __restrict__ box, int parity, int step, int nbricks,
-                                             Step P) {
-    const int nact = ctl[CTL_NACTIVE];
-    const int total = nact + min(ctl[CTL_OVF + parity], nbricks - nact);
+                                             const int4* __restrict__ box, int parity, int nbricks, Scenes T,
+                                             int act) {
+    const int nact = rank_limit(T, ctl, act, RE_ACTIVE, CTL_NACTIVE);
+    const int total = nact + min(ctl[CTL_OVF + parity], nbricks - ctl[CTL_NACTIVE]);
+    const int step = ctl[CTL_STEP];
     const int lane = threadIdx.x & 63;
     const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
     const int nwaves = gridDim.x * (WG / 64);
     float4* acc4 = reinterpret_cast<float4*>(acc);
-    const int NB = P.NB;
     __shared__ int cand[WG / 64][64];
     for (int it = blockIdx.x * (WG / 64) + (threadIdx.x >> 6); it < total; it += nwaves) {
         const int b = __builtin_amdgcn_readfirstlane(it < nact ? active[it] : ovf[it - nact]);
-        const int bx = b % NB, by = (b / NB) % NB, bz = b / (NB * NB);
+        const Scene& sc = T.scene[T.rank_scene[rank_of_brick(T, b)]];
+        const Step P = sc.P;
+        const int NB = P.NB, base = sc.brick_base;
+        const int lb = b - base;
+        const int bx = lb % NB, by = (lb / NB) % NB, bz = lb / (NB * NB);
         const int g[3] = {4 * (bx - 1) + lx, 4 * (by - 1) + ly, 4 * (bz - 1) + lz};
         float4 a = acc4[b * 64 + lane];
         // Lane k < 27 looks up the chunk range of candidate particle block k
@@ -60,7 +64,7 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, float4* __
         if (lane < 27) {
             const int px = bx + lane % 3 - 1, py = by + (lane / 3) % 3 - 1, pz = bz + lane / 9 - 1;
             if (px >= 0 && px < NB && py >= 0 && py < NB && pz >= 0 && pz < NB) {
-                const int gb = gindex[(pz * NB + py) * NB + px];
+                const int gb = gindex[base + (pz * NB + py) * NB + px];
                 if (gb >= 0) {
                     c0_k = gchunk[gb];
                     n_k = gchunk[gb + 1] - c0_k;
@@ -156,16 +160,19 @@ template <bool LDS_BOX, int NT>
 __global__ __launch_bounds__(NT) void k_g2p(float* __restrict__ S, int64_t cap, const Chunk* __restrict__ chunks,
                                             int* __restrict__ ctl, const float4* __restrict__ vel,
                                             const int4* __restrict__ box, int* __restrict__ host_flag, int parity,
-                                            int fb_limit, Step P) {
+                                            int fb_limit, Scenes T, int act) {
     __shared__ float4 tv[LDS_BOX ? G2P_BOX : 1];
     unsigned err = 0;
     bool left = blockIdx.x == 0 && threadIdx.x == 0 && ctl[CTL_FB + parity] > fb_limit;
     int begin, end, stride;
-    xcd_split(ctl[CTL_NCHUNK], begin, end, stride);
-    const float c4 = 4.0f * P.fn;  // (4/dx^2) * dx
-    const int NB = P.NB;
+    xcd_split(rank_limit(T, ctl, act, RE_CHUNK, CTL_NCHUNK), begin, end, stride);
     for (int c = begin; c < end; c += stride) {
         const Chunk ch = chunks[c];
+        const Scene& sc = T.scene[ch.scene];
+        const Step P = sc.P;
+        const float c4 = 4.0f * P.fn;  // (4/dx^2) * dx
+        const int NB = P.NB;
+        const float4* vels = vel + (int64_t)sc.brick_base * BLOCK_NODES;
         const int B[3] = {ch.block & 1023, (ch.block >> 10) & 1023, ch.block >> 20};
         int lo[3] = {0, 0, 0}, e[3] = {0, 0, 0}, nt = 0;
         if (LDS_BOX) {
@@ -180,8 +187,8 @@ __global__ __launch_bounds__(NT) void k_g2p(float* __restrict__ S, int64_t cap, 
             if (nt > G2P_BOX) nt = 0;
             for (int t = threadIdx.x; t < nt; t += NT) {
                 const int gx = lo[0] + t % e[0], gy = lo[1] + (t / e[0]) % e[1], gz = lo[2] + t / (e[0] * e[1]);
-                tv[t] = vel[((((gz >> 2) + 1) * NB + ((gy >> 2) + 1)) * NB + ((gx >> 2) + 1)) * 64 + (gx & 3) +
-                            ((gy & 3) << 2) + ((gz & 3) << 4)];
+                tv[t] = vels[((((gz >> 2) + 1) * NB + ((gy >> 2) + 1)) * NB + ((gx >> 2) + 1)) * 64 + (gx & 3) +
+                             ((gy & 3) << 2) + ((gz & 3) << 4)];
             }
             __syncthreads();
         }
@@ -236,7 +243,7 @@ __global__ __launch_bounds__(NT) void k_g2p(float* __restrict__ S, int64_t cap, 
 #pragma unroll
                         for (int o0 = 0; o0 < 3; ++o0) {
                             const float w = wyz * st.w[0][o0];
-                            const float4 g = vel[xo[o0] + yo[o1] + zo[o2]];
+                            const float4 g = vels[xo[o0] + yo[o1] + zo[o2]];
                             const float wv[3] = {w * g.x, w * g.y, w * g.z};
 #pragma unroll
                             for (int a = 0; a < 3; ++a) {
@@ -271,16 +278,22 @@ __global__ __launch_bounds__(NT) void k_g2p(float* __restrict__ S, int64_t cap, 
     }
     if (__ballot(left) != 0ull && (threadIdx.x & 63) == 0) {
         if (__hip_atomic_load(&ctl[CTL_REBUILD], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
-            atomicExch(&ctl[CTL_REBUILD], 1) == 0)
+            atomicExch(&ctl[CTL_REBUILD], 1) == 0 && host_flag)
             __hip_atomic_store(host_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
     if (err) atomicOr(&ctl[CTL_ERROR], (int)err);
+    // every workgroup has read what it needs; the grid update of the next
+    // substep stamps blocks with the advanced count
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl[CTL_STEP] += 1;
 }
 
 // ------------------------------------------------------------- utilities
-__global__ __launch_bounds__(WG) void k_materialize(float* __restrict__ S, int64_t cap, int N, Step P, Mat M) {
+// Land the deferred deformation update of every particle (with the material
+// and time step of its scene).
+__global__ __launch_bounds__(WG) void k_materialize(float* __restrict__ S, int64_t cap, int N, Scenes T) {
     const int p = blockIdx.x * WG + threadIdx.x;
     if (p >= N) return;
+    const Scene& sc = T.scene[__float_as_int(S[FSID * cap + p])];
     float C[9], F[9], s, tau[6];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
@@ -288,16 +301,19 @@ __global__ __launch_bounds__(WG) void k_materialize(float* __restrict__ S, int64
         F[k] = S[(FF + k) * cap + p];
     }
     s = S[FS * cap + p];
-    material_step(M, P.dt, 1, C, F, s, tau);
+    material_step(sc.M, sc.P.dt, 1, C, F, s, tau);
 #pragma unroll
     for (int k = 0; k < 9; ++k) S[(FF + k) * cap + p] = F[k];
     S[FS * cap + p] = s;
 }
 
+// Append `count` particles of `scene` at storage positions N0.., numbered
+// id0.. inside their scene.
 __global__ __launch_bounds__(WG) void k_insert(float* __restrict__ S, int* __restrict__ ids, int64_t cap, int N0,
-                                               int count, const float* __restrict__ x, const float* __restrict__ v,
-                                               const float* __restrict__ C, const float* __restrict__ F,
-                                               const float* __restrict__ s, int* __restrict__ ctl) {
+                                               int count, int scene, int id0, const float* __restrict__ x,
+                                               const float* __restrict__ v, const float* __restrict__ C,
+                                               const float* __restrict__ F, const float* __restrict__ s,
+                                               int* __restrict__ ctl) {
     const int i = blockIdx.x * WG + threadIdx.x;
     if (i >= count) return;
     const int j = N0 + i;
@@ -316,46 +332,50 @@ __global__ __launch_bounds__(WG) void k_insert(float* __restrict__ S, int* __res
         S[(FF + k) * cap + j] = F ? F[k * (int64_t)count + i] : ((k % 4 == 0) ? 1.0f : 0.0f);
     }
     S[FS * cap + j] = s ? s[i] : 1.0f;
-    ids[j] = j;
+    S[FSID * cap + j] = __int_as_float(scene);
+    ids[j] = id0 + i;
     if (err) atomicOr(&ctl[CTL_ERROR], (int)err);
 }
 
+// Scatter the particles of one scene (Ns of them) to insertion order.
 __global__ __launch_bounds__(WG) void k_read(const float* __restrict__ S, const int* __restrict__ ids, int64_t cap,
-                                             int N, int pending, Step P, Mat M, float* __restrict__ x,
+                                             int N, int scene, int Ns, int pending, Scenes T, float* __restrict__ x,
                                              float* __restrict__ v, float* __restrict__ C, float* __restrict__ F,
                                              float* __restrict__ s) {
     const int j = blockIdx.x * WG + threadIdx.x;
-    if (j >= N) return;
+    if (j >= N || __float_as_int(S[FSID * cap + j]) != scene) return;
+    const Scene& sc = T.scene[scene];
     const int64_t id = ids[j];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (x) x[a * (int64_t)N + id] = S[(FX + a) * cap + j];
-        if (v) v[a * (int64_t)N + id] = S[(FV + a) * cap + j];
+        if (x) x[a * (int64_t)Ns + id] = S[(FX + a) * cap + j];
+        if (v) v[a * (int64_t)Ns + id] = S[(FV + a) * cap + j];
     }
     float Cp[9], Fp[9], sp = S[FS * cap + j], tau[6];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
         Cp[k] = S[(FC + k) * cap + j];
         Fp[k] = S[(FF + k) * cap + j];
-        if (C) C[k * (int64_t)N + id] = Cp[k];
+        if (C) C[k * (int64_t)Ns + id] = Cp[k];
     }
-    if (pending && (F || s)) material_step(M, P.dt, 1, Cp, Fp, sp, tau);
+    if (pending && (F || s)) material_step(sc.M, sc.P.dt, 1, Cp, Fp, sp, tau);
     if (F)
 #pragma unroll
-        for (int k = 0; k < 9; ++k) F[k * (int64_t)N + id] = Fp[k];
+        for (int k = 0; k < 9; ++k) F[k * (int64_t)Ns + id] = Fp[k];
     if (s) s[id] = sp;
 }
 
 __global__ __launch_bounds__(WG) void k_read_grid(const float4* __restrict__ vel, const int* __restrict__ stamp,
-                                                  int step, Step P, float* __restrict__ m, float* __restrict__ v) {
+                                                  int step, Step P, int base, float* __restrict__ m,
+                                                  float* __restrict__ v) {
     const int n1 = P.n + 1;
     const int64_t NN = (int64_t)n1 * n1 * n1;
     const int64_t id = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (id >= NN) return;
     const int i = (int)(id / ((int64_t)n1 * n1)), j = (int)((id / n1) % n1), k = (int)(id % n1);
-    const int b = (((k >> 2) + 1) * P.NB + ((j >> 2) + 1)) * P.NB + ((i >> 2) + 1);
+    const int b = base + (((k >> 2) + 1) * P.NB + ((j >> 2) + 1)) * P.NB + ((i >> 2) + 1);
     float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (stamp[b] == step) g = vel[b * 64 + (i & 3) + ((j & 3) << 2) + ((k & 3) << 4)];
+    if (stamp[b] == step) g = vel[(int64_t)b * 64 + (i & 3) + ((j & 3) << 2) + ((k & 3) << 4)];
     if (m) m[id] = g.w;
     if (v) {
         v[id] = g.x;
@@ -415,18 +435,18 @@ void query_launch(Launch& L, int chunk) {
     L.grid_grid = grid_for(reinterpret_cast<const void*>(k_grid), WG, 8);
 }
 
-void enqueue_grid(hipStream_t st, const Launch& L, const Step& P, const BinBuffers& B, int* ctl, GridBuffers& G,
-                  int parity, int step) {
+void enqueue_grid(hipStream_t st, const Launch& L, const Scenes& T, const BinBuffers& B, int* ctl, GridBuffers& G,
+                  int parity, int nbricks, int act) {
     hipLaunchKernelGGL(k_grid, dim3(L.grid_grid), dim3(WG), 0, st, G.acc, G.vel, B.active, ctl, G.ovf[parity],
-                       B.brick_state, G.stamp, B.gindex, B.gchunk, G.stage, G.box, parity, step,
-                       P.NB * P.NB * P.NB, P);
+                       B.brick_state, G.stamp, B.gindex, B.gchunk, G.stage, G.box, parity, nbricks, T, act);
 }
 
-void enqueue_g2p(hipStream_t st, const Launch& L, const Step& P, float* S, int64_t cap, const Chunk* chunks, int* ctl,
-                 const GridBuffers& G, int* host_flag, int lds_box, int parity, int fb_limit, int chunk) {
-#define MPM_LAUNCH_G2P(LB, T)                                                                                   \
-    hipLaunchKernelGGL((k_g2p<LB, T>), dim3(L.g2p_grid), dim3(T), 0, st, S, cap, chunks, ctl, G.vel, G.box, host_flag, \
-                       parity, fb_limit, P)
+void enqueue_g2p(hipStream_t st, const Launch& L, const Scenes& T, float* S, int64_t cap, const Chunk* chunks,
+                 int* ctl, const GridBuffers& G, int* host_flag, int lds_box, int parity, int fb_limit, int chunk,
+                 int act) {
+#define MPM_LAUNCH_G2P(LB, NT)                                                                                    \
+    hipLaunchKernelGGL((k_g2p<LB, NT>), dim3(L.g2p_grid), dim3(NT), 0, st, S, cap, chunks, ctl, G.vel, G.box, \
+                       host_flag, parity, fb_limit, T, act)
     const int nt = chunk_threads(chunk);
     if (lds_box) {
         if (nt == 128) MPM_LAUNCH_G2P(true, 128); else if (nt == 256) MPM_LAUNCH_G2P(true, 256); else MPM_LAUNCH_G2P(true, 512);
@@ -436,26 +456,29 @@ void enqueue_g2p(hipStream_t st, const Launch& L, const Step& P, float* S, int64
 #undef MPM_LAUNCH_G2P
 }
 
-void enqueue_materialize(hipStream_t st, const Step& P, const Mat& M, float* S, int64_t cap, int N) {
+void enqueue_materialize(hipStream_t st, const Scenes& T, float* S, int64_t cap, int N) {
     if (N <= 0) return;
-    hipLaunchKernelGGL(k_materialize, dim3(cdiv(N, WG)), dim3(WG), 0, st, S, cap, N, P, M);
+    hipLaunchKernelGGL(k_materialize, dim3(cdiv(N, WG)), dim3(WG), 0, st, S, cap, N, T);
 }
 
-void enqueue_insert(hipStream_t st, float* S, int* ids, int64_t cap, int N0, int count, const float* x, const float* v,
-                    const float* C, const float* F, const float* s, int* ctl) {
+void enqueue_insert(hipStream_t st, float* S, int* ids, int64_t cap, int N0, int count, int scene, int id0,
+                    const float* x, const float* v, const float* C, const float* F, const float* s, int* ctl) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_insert, dim3(cdiv(count, WG)), dim3(WG), 0, st, S, ids, cap, N0, count, x, v, C, F, s, ctl);
+    hipLaunchKernelGGL(k_insert, dim3(cdiv(count, WG)), dim3(WG), 0, st, S, ids, cap, N0, count, scene, id0, x, v, C,
+                       F, s, ctl);
 }
 
-void enqueue_read(hipStream_t st, const Step& P, const Mat& M, const float* S, const int* ids, int64_t cap, int N,
-                  int pending, float* x, float* v, float* C, float* F, float* s) {
+void enqueue_read(hipStream_t st, const Scenes& T, const float* S, const int* ids, int64_t cap, int N, int scene,
+                  int Ns, int pending, float* x, float* v, float* C, float* F, float* s) {
     if (N <= 0) return;
-    hipLaunchKernelGGL(k_read, dim3(cdiv(N, WG)), dim3(WG), 0, st, S, ids, cap, N, pending, P, M, x, v, C, F, s);
+    hipLaunchKernelGGL(k_read, dim3(cdiv(N, WG)), dim3(WG), 0, st, S, ids, cap, N, scene, Ns, pending, T, x, v, C, F,
+                       s);
 }
 
-void enqueue_read_grid(hipStream_t st, const Step& P, const GridBuffers& G, int step, float* m, float* v) {
-    const int64_t n1 = P.n + 1;
-    hipLaunchKernelGGL(k_read_grid, dim3(cdiv(n1 * n1 * n1, WG)), dim3(WG), 0, st, G.vel, G.stamp, step, P, m, v);
+void enqueue_read_grid(hipStream_t st, const Scene& sc, const GridBuffers& G, int step, float* m, float* v) {
+    const int64_t n1 = sc.P.n + 1;
+    hipLaunchKernelGGL(k_read_grid, dim3(cdiv(n1 * n1 * n1, WG)), dim3(WG), 0, st, G.vel, G.stamp, step, sc.P,
+                       sc.brick_base, m, v);
 }
 
 }  // namespace mpm

@@ -20,16 +20,27 @@ BC = {"sticky": 0, "slip": 1, "separate": 2}
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -1, -2, -3, -4
 ERR_NONFINITE, ERR_DOMAIN, ERR_CAPACITY = 0x1, 0x2, 0x4
 FLAG_REBUILD_EVERY_STEP, FLAG_P2G_GLOBAL_ATOMICS, FLAG_MANUAL_REBUILD, FLAG_P2G_SORTED_LANES = 0x1, 0x2, 0x4, 0x8
-FLAG_G2P_GLOBAL_GATHER = 0x10
+FLAG_G2P_GLOBAL_GATHER, FLAG_FRAME_GRAPHS = 0x10, 0x20
+MAX_SCENES = 256
 PHASE_REBUILD, PHASE_P2G, PHASE_GRID, PHASE_G2P = 0x1, 0x2, 0x4, 0x8
 PHASES = ("rebuild", "p2g", "grid", "g2p")
+
+
+class SceneDesc(ct.Structure):
+    _fields_ = [("n", ct.c_int32), ("bc", ct.c_int32), ("bc_cells", ct.c_int32), ("gravity", ct.c_float * 3),
+                ("dt", ct.c_float)]
 
 
 class Config(ct.Structure):
     _fields_ = [("n", ct.c_int32), ("bc", ct.c_int32), ("bc_cells", ct.c_int32), ("num_scenes", ct.c_int32),
                 ("gravity", ct.c_float * 3), ("dt", ct.c_float), ("capacity", ct.c_int64),
                 ("stream", ct.c_uint64), ("flags", ct.c_uint32), ("lag", ct.c_int32), ("chunk", ct.c_int32),
-                ("reserved", ct.c_int32)]
+                ("reserved", ct.c_int32), ("scenes", ct.POINTER(SceneDesc))]
+
+
+class SceneStats(ct.Structure):
+    _fields_ = [("num_particles", ct.c_int64), ("substeps", ct.c_int64), ("gblocks", ct.c_int64),
+                ("active_blocks", ct.c_int64), ("n", ct.c_int32), ("dt", ct.c_float)]
 
 
 class Material(ct.Structure):
@@ -41,7 +52,8 @@ class Stats(ct.Structure):
     _fields_ = [(k, ct.c_int64) for k in ("num_particles", "capacity", "substeps", "rebuilds", "gblocks",
                                           "active_blocks", "chunks", "overflow_blocks")] + \
                [("error", ct.c_uint32), ("pending_update", ct.c_uint32)] + \
-               [("p2g_fallback_chunks", ct.c_int64), ("p2g_global_particles", ct.c_int64)]
+               [("p2g_fallback_chunks", ct.c_int64), ("p2g_global_particles", ct.c_int64),
+                ("surrogate_particles", ct.c_int64), ("surrogate_fallbacks", ct.c_int64)]
 
 
 class ProfileData(ct.Structure):
@@ -69,10 +81,22 @@ SIGNATURES = {
     "mpm_read_binning": (ct.c_int, [P, ct.c_int32, ct.c_int64, P, P]),
     "mpm_read_blocks": (ct.c_int, [P, ct.c_int32, P, P, P, P]),
     "mpm_get_stats": (ct.c_int, [P, ct.POINTER(Stats)]),
+    "mpm_get_scene_stats": (ct.c_int, [P, ct.c_int32, ct.POINTER(SceneStats)]),
+    "mpm_autotune": (ct.c_int, [P, ct.c_float, ct.c_int32, ct.POINTER(ct.c_int32)]),
     "mpm_clear_error": (ct.c_int, [P]),
     "mpm_profile": (ct.c_int, [P, ct.c_uint32]),
     "mpm_profile_read": (ct.c_int, [P, ct.POINTER(ProfileData)]),
     "mpm_last_error": (ct.c_char_p, [P]),
+    "mpm_surrogate_create": (ct.c_int, [ct.c_uint64, ct.POINTER(P)]),
+    "mpm_surrogate_destroy": (ct.c_int, [P]),
+    "mpm_surrogate_set": (ct.c_int, [P, P, P]),
+    "mpm_surrogate_get": (ct.c_int, [P, P, P]),
+    "mpm_surrogate_forward": (ct.c_int, [P, ct.c_int32, ct.c_int64, P, P]),
+    "mpm_surrogate_loss_grad": (ct.c_int, [P, ct.c_int32, ct.c_int64, P, P, P, P]),
+    "mpm_surrogate_fit_norm": (ct.c_int, [P, ct.c_int64, P, P]),
+    "mpm_surrogate_train": (ct.c_int, [P, ct.c_int64, P, P, ct.c_int32, ct.c_int32, ct.c_float, ct.c_uint64, P]),
+    "mpm_surrogate_sample": (ct.c_int, [P, ct.c_int32, ct.c_float, ct.c_int64, P, P, ct.POINTER(ct.c_int64)]),
+    "mpm_use_surrogate": (ct.c_int, [P, ct.c_int32, P, ct.c_int32, ct.c_float, ct.c_float]),
 }
 
 _lib = None
@@ -104,27 +128,48 @@ def _ptr(t):
 
 
 class Sim:
-    """One simulation context on the current CUDA (HIP) device."""
+    """One simulation context on the current CUDA (HIP) device.
+
+    `scenes` (optional) is a list of per-scene dicts with keys n, dt and
+    optionally bc, bc_cells, gravity; without it the context holds
+    `num_scenes` copies of the scene given by the other arguments."""
 
     def __init__(self, n: int, dt: float, bc="sticky", bc_cells: int = 3, gravity=(0.0, -9.8, 0.0),
-                 capacity: int = 0, flags: int = 0, lag: int = 0, chunk: int = 0, stream=None):
+                 capacity: int = 0, flags: int = 0, lag: int = 0, chunk: int = 0, stream=None,
+                 scenes: list | None = None, num_scenes: int = 1):
         import torch
 
         self.torch = torch
         self.lib = load()
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        cfg = Config(int(n), bc if isinstance(bc, int) else BC[bc], int(bc_cells), 1,
-                     (ct.c_float * 3)(*map(float, gravity)), float(dt), int(capacity),
-                     int(self.stream.cuda_stream), int(flags), int(lag), int(chunk), 0)
+        bcv = lambda b: b if isinstance(b, int) else BC[b]
+        if scenes is not None:
+            num_scenes = len(scenes)
+            arr = (SceneDesc * num_scenes)()
+            for k, d in enumerate(scenes):
+                arr[k] = SceneDesc(int(d["n"]), bcv(d.get("bc", bc)), int(d.get("bc_cells", bc_cells)),
+                                   (ct.c_float * 3)(*map(float, d.get("gravity", gravity))), float(d["dt"]))
+            self._scene_arr = arr
+            self.ns = [int(d["n"]) for d in scenes]
+        else:
+            arr = None
+            self.ns = [int(n)] * num_scenes
+        cfg = Config(int(n), bcv(bc), int(bc_cells), int(num_scenes), (ct.c_float * 3)(*map(float, gravity)),
+                     float(dt), int(capacity), int(self.stream.cuda_stream), int(flags), int(lag), int(chunk), 0,
+                     ct.cast(arr, ct.POINTER(SceneDesc)) if arr is not None else None)
         self.cfg = cfg
-        self.n = int(n)
+        self.n = self.ns[0]
         h = ct.c_void_p()
         r = self.lib.mpm_create(ct.byref(cfg), ct.byref(h))
         if r != OK:
             raise MPMError(r, self.lib.mpm_last_error(None).decode())
         self.h = h
-        self.N = 0
+        self.counts = [0] * int(num_scenes)
+
+    @property
+    def N(self) -> int:
+        return self.counts[0] if len(self.counts) == 1 else sum(self.counts)
 
     # ------------------------------------------------------------ helpers
     def _check(self, r):
@@ -152,7 +197,7 @@ class Sim:
                                        *(_ptr(t) for t in ts))
         self._keep = ts  # the copies must live until the insert kernel has run
         self._check(r)
-        self.N += count
+        self.counts[scene] += count
 
     def substep(self, n: int = 1):
         self._check(self.lib.mpm_substep(self.h, int(n)))
@@ -166,38 +211,38 @@ class Sim:
     def synchronize(self):
         self._check(self.lib.mpm_synchronize(self.h))
 
-    def read_particles(self, check: bool = True) -> dict:
-        N = self.N
+    def read_particles(self, check: bool = True, scene: int = 0) -> dict:
+        N = self.counts[scene]
         z = lambda r: self.torch.empty((r, N), dtype=self.torch.float32, device=self.device)
         out = {"x": z(3), "v": z(3), "C": z(9), "F": z(9),
                "s": self.torch.empty(N, dtype=self.torch.float32, device=self.device)}
-        r = self.lib.mpm_read_particles(self.h, 0, N, *(_ptr(out[k]) for k in ("x", "v", "C", "F", "s")))
+        r = self.lib.mpm_read_particles(self.h, scene, N, *(_ptr(out[k]) for k in ("x", "v", "C", "F", "s")))
         if check:
             self._check(r)
         return out
 
-    def read_grid(self):
-        n1 = self.n + 1
+    def read_grid(self, scene: int = 0):
+        n1 = self.ns[scene] + 1
         m = self.torch.empty(n1 ** 3, dtype=self.torch.float32, device=self.device)
         v = self.torch.empty((3, n1 ** 3), dtype=self.torch.float32, device=self.device)
-        self._check(self.lib.mpm_read_grid(self.h, 0, _ptr(m), _ptr(v)))
+        self._check(self.lib.mpm_read_grid(self.h, scene, _ptr(m), _ptr(v)))
         return m, v
 
-    def read_binning(self, count=None):
-        count = self.N if count is None else count
+    def read_binning(self, count=None, scene: int = 0):
+        count = self.counts[scene] if count is None else count
         keys = self.torch.empty(count, dtype=self.torch.int32, device=self.device)
         perm = self.torch.empty(count, dtype=self.torch.int32, device=self.device)
-        self._check(self.lib.mpm_read_binning(self.h, 0, count, _ptr(keys), _ptr(perm)))
+        self._check(self.lib.mpm_read_binning(self.h, scene, count, _ptr(keys), _ptr(perm)))
         return keys.cpu().numpy().view(np.uint32), perm.cpu().numpy()
 
-    def read_blocks(self):
-        st = self.stats()
+    def read_blocks(self, scene: int = 0):
+        st = self.scene_stats(scene)
         ng, na = st["gblocks"], st["active_blocks"]
         gcode = np.zeros(max(ng, 1), dtype=np.uint32)
         gstart = np.zeros(max(ng, 1), dtype=np.int32)
         gcount = np.zeros(max(ng, 1), dtype=np.int32)
         active = np.zeros(max(na, 1), dtype=np.int32)
-        self._check(self.lib.mpm_read_blocks(self.h, 0, gcode.ctypes.data, gstart.ctypes.data,
+        self._check(self.lib.mpm_read_blocks(self.h, scene, gcode.ctypes.data, gstart.ctypes.data,
                                              gcount.ctypes.data, active.ctypes.data))
         return {"gcode": gcode[:ng], "gstart": gstart[:ng], "gcount": gcount[:ng], "active": active[:na]}
 
@@ -208,8 +253,24 @@ class Sim:
             self._check(r)
         return {k: getattr(s, k) for k, _ in Stats._fields_}
 
+    def scene_stats(self, scene: int = 0) -> dict:
+        s = SceneStats()
+        self._check(self.lib.mpm_get_scene_stats(self.h, scene, ct.byref(s)))
+        return {k: getattr(s, k) for k, _ in SceneStats._fields_}
+
+    def autotune(self, frame_dt: float, frames: int = 1) -> int:
+        out = ct.c_int32(0)
+        self._check(self.lib.mpm_autotune(self.h, float(frame_dt), int(frames), ct.byref(out)))
+        return out.value
+
     def clear_error(self):
         self._check(self.lib.mpm_clear_error(self.h))
+
+    def use_surrogate(self, mode: int, surrogate=None, tol: float = 1e-3, dt_ref: float = 5e-5, scene: int = 0):
+        """0 exact return map, 1 learned surrogate, 2 closed form without the network."""
+        h = surrogate.h if surrogate is not None else None
+        self._sur = surrogate  # keep it alive while the context uses it
+        self._check(self.lib.mpm_use_surrogate(self.h, scene, h, int(mode), float(tol), float(dt_ref)))
 
     def profile(self, mask: int):
         self._check(self.lib.mpm_profile(self.h, int(mask)))
@@ -235,3 +296,104 @@ class Sim:
 
     def __exit__(self, *a):
         self.close()
+
+
+SUR_IN, SUR_OUT, SUR_PARAMS, SUR_NORM = 12, 12, 5772, 48
+SUR_FP32, SUR_BF16 = 0, 1
+
+
+class Surrogate:
+    """The learned snow return map: an MLP 12 -> 64 -> 64 -> 12 trained and
+    run by the library's kernels (BF16 MFMA with FP32 accumulation; FP32 for
+    gradient checks).  Arrays are torch CUDA tensors or host arrays."""
+
+    def __init__(self, stream=None):
+        import torch
+
+        self.torch = torch
+        self.lib = load()
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ct.c_void_p()
+        r = self.lib.mpm_surrogate_create(int(self.stream.cuda_stream), ct.byref(h))
+        if r != OK:
+            raise MPMError(r, self.lib.mpm_last_error(None).decode())
+        self.h = h
+
+    def _check(self, r):
+        if r != OK:
+            raise MPMError(r, self.lib.mpm_last_error(None).decode())
+
+    def _t(self, a, n=None):
+        t = self.torch.as_tensor(np.asarray(a) if not isinstance(a, self.torch.Tensor) else a,
+                                 dtype=self.torch.float32).to(self.device).contiguous()
+        if n is not None and t.numel() != n:
+            raise ValueError(f"expected {n} values, got {t.numel()}")
+        return t
+
+    def set(self, theta=None, norm=None):
+        th = None if theta is None else self._t(theta, SUR_PARAMS)
+        nm = None if norm is None else self._t(norm, SUR_NORM)
+        self._check(self.lib.mpm_surrogate_set(self.h, _ptr(th), _ptr(nm)))
+        self.synchronize()
+
+    def get(self):
+        th = self.torch.empty(SUR_PARAMS, dtype=self.torch.float32, device=self.device)
+        nm = self.torch.empty(SUR_NORM, dtype=self.torch.float32, device=self.device)
+        self._check(self.lib.mpm_surrogate_get(self.h, _ptr(th), _ptr(nm)))
+        self.synchronize()
+        return th, nm
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def forward(self, X, precision=SUR_BF16):
+        X = self._t(X)
+        n = X.numel() // SUR_IN
+        Y = self.torch.empty((n, SUR_OUT), dtype=self.torch.float32, device=self.device)
+        self._check(self.lib.mpm_surrogate_forward(self.h, int(precision), n, _ptr(X), _ptr(Y)))
+        self.synchronize()
+        return Y
+
+    def loss_grad(self, X, T, precision=SUR_FP32):
+        X, T = self._t(X), self._t(T)
+        n = X.numel() // SUR_IN
+        g = self.torch.empty(SUR_PARAMS, dtype=self.torch.float32, device=self.device)
+        l = self.torch.empty(1, dtype=self.torch.float32, device=self.device)
+        self._check(self.lib.mpm_surrogate_loss_grad(self.h, int(precision), n, _ptr(X), _ptr(T), _ptr(g), _ptr(l)))
+        self.synchronize()
+        return float(l.item()), g
+
+    def fit_norm(self, X, T):
+        X, T = self._t(X), self._t(T)
+        self._check(self.lib.mpm_surrogate_fit_norm(self.h, X.numel() // SUR_IN, _ptr(X), _ptr(T)))
+        self.synchronize()
+
+    def train(self, X, T, steps, batch=4096, lr=1e-3, seed=0):
+        X, T = self._t(X), self._t(T)
+        losses = np.zeros(max(int(steps), 1), dtype=np.float32)
+        self._check(self.lib.mpm_surrogate_train(self.h, X.numel() // SUR_IN, _ptr(X), _ptr(T), int(steps),
+                                                 int(batch), float(lr), int(seed), losses.ctypes.data))
+        return losses[:int(steps)]
+
+    @staticmethod
+    def sample(sim, scene=0, dt_ref=5e-5, max_count=None):
+        """Training pairs (X, T) from the current state of a snow scene."""
+        torch = sim.torch
+        n = sim.counts[scene] if max_count is None else int(max_count)
+        X = torch.empty((max(n, 1), SUR_IN), dtype=torch.float32, device=sim.device)
+        T = torch.empty((max(n, 1), SUR_OUT), dtype=torch.float32, device=sim.device)
+        w = ct.c_int64(0)
+        sim._check(sim.lib.mpm_surrogate_sample(sim.h, scene, float(dt_ref), n, _ptr(X), _ptr(T), ct.byref(w)))
+        return X[:w.value], T[:w.value]
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mpm_surrogate_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

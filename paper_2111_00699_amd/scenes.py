@@ -191,6 +191,36 @@ def fountain_config(n: int = 128) -> dict:
 
 
 # ------------------------------------------------------------ surrogate inputs
+BATCH_MATS = {"jelly": (JELLY, "sticky", 1e-4, 64), "snow": (SNOW, "separate", 5e-5, 256),
+              "water": (WATER, "separate", 1e-4, 128)}
+
+
+def batched_scenes(seed: int = 3, count: int = 256, nmin: int = 2048, nmax: int = 65536,
+                   grids=(64, 128)) -> list[dict]:
+    """Many small, uneven real-time scenes.  Per scene (seeded splitmix64
+    stream k): grid n uniform over `grids`; particle count log-uniform in
+    [nmin, nmax], realised as a cube of k^3 cells at 8 ppc (k = round((N/8)^(1/3)),
+    so N = 8 k^3) centred in x and z with its bottom at y = 0.4; material
+    uniform over jelly / snow / water; dt = dt_ref * n_ref / n with (dt_ref,
+    n_ref) = (1e-4, 64) jelly, (5e-5, 256) snow, (1e-4, 128) water, i.e. the
+    single-scene time steps scaled to the grid, 84 to 334 substeps per 1/60 s
+    frame.  Returns dicts with n, dt, bc, mat, kind, x."""
+    out = []
+    kinds = ("jelly", "snow", "water")
+    for k in range(count):
+        u = uniform(seed, 3, stream=k)
+        n = int(grids[min(int(u[0] * len(grids)), len(grids) - 1)])
+        N = float(np.exp(np.log(nmin) + u[1] * (np.log(nmax) - np.log(nmin))))
+        kind = kinds[min(int(u[2] * 3), 2)]
+        cells = max(2, int(round((N / 8.0) ** (1.0 / 3.0))))
+        cells = min(cells, n // 2 - 6)
+        lo = [(n - cells) // 2, int(0.4 * n), (n - cells) // 2]
+        x = stratified_cells(box_cells(lo, [lo[0] + cells, lo[1] + cells, lo[2] + cells]), n, seed, stream=1000 + k)
+        mat, bc, dt_ref, n_ref = BATCH_MATS[kind]
+        out.append(dict(n=n, dt=dt_ref * n_ref / n, bc=bc, mat=mat, kind=kind, x=x))
+    return out
+
+
 MLP_LAYERS = (12, 64, 64, 12)
 
 

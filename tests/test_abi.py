@@ -55,10 +55,13 @@ def test_struct_layouts_match_the_header():
 #include <stddef.h>
 #include "mpm.h"
 int main(void) {
-  printf("%zu %zu %zu %zu\n", sizeof(mpm_config), sizeof(mpm_material), sizeof(mpm_stats), sizeof(mpm_profile_data));
-  printf("%zu %zu %zu %zu %zu\n", offsetof(mpm_config, dt), offsetof(mpm_config, capacity),
-         offsetof(mpm_config, stream), offsetof(mpm_config, flags), offsetof(mpm_config, chunk));
-  printf("%zu %zu\n", offsetof(mpm_stats, error), offsetof(mpm_profile_data, ms));
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(mpm_config), sizeof(mpm_material), sizeof(mpm_stats),
+         sizeof(mpm_profile_data), sizeof(mpm_scene), sizeof(mpm_scene_stats));
+  printf("%zu %zu %zu %zu %zu %zu\n", offsetof(mpm_config, dt), offsetof(mpm_config, capacity),
+         offsetof(mpm_config, stream), offsetof(mpm_config, flags), offsetof(mpm_config, chunk),
+         offsetof(mpm_config, scenes));
+  printf("%zu %zu %zu %zu\n", offsetof(mpm_stats, error), offsetof(mpm_profile_data, ms),
+         offsetof(mpm_scene, dt), offsetof(mpm_scene_stats, n));
   return 0;
 }'''
     with tempfile.TemporaryDirectory() as d:
@@ -69,11 +72,12 @@ int main(void) {
         lines = subprocess.check_output([exe], text=True).split("\n")
     sizes = list(map(int, lines[0].split()))
     assert sizes == [ct.sizeof(mpm.Config), ct.sizeof(mpm.Material), ct.sizeof(mpm.Stats),
-                     ct.sizeof(mpm.ProfileData)]
+                     ct.sizeof(mpm.ProfileData), ct.sizeof(mpm.SceneDesc), ct.sizeof(mpm.SceneStats)]
     offs = list(map(int, lines[1].split()))
     assert offs == [mpm.Config.dt.offset, mpm.Config.capacity.offset, mpm.Config.stream.offset,
-                    mpm.Config.flags.offset, mpm.Config.chunk.offset]
-    assert list(map(int, lines[2].split())) == [mpm.Stats.error.offset, mpm.ProfileData.ms.offset]
+                    mpm.Config.flags.offset, mpm.Config.chunk.offset, mpm.Config.scenes.offset]
+    assert list(map(int, lines[2].split())) == [mpm.Stats.error.offset, mpm.ProfileData.ms.offset,
+                                                mpm.SceneDesc.dt.offset, mpm.SceneStats.n.offset]
 
 
 def test_create_rejects_bad_configs_without_a_device(lib):
@@ -89,10 +93,19 @@ def test_create_rejects_bad_configs_without_a_device(lib):
         return c
 
     h = ct.c_void_p()
-    for bad in (dict(n=48), dict(n=8), dict(n=1024), dict(bc=7), dict(dt=0.0), dict(num_scenes=2),
-                dict(lag=100), dict(chunk=100), dict(capacity=-1)):
+    for bad in (dict(n=48), dict(n=8), dict(n=1024), dict(bc=7), dict(dt=0.0), dict(num_scenes=0),
+                dict(num_scenes=257), dict(n=512, num_scenes=64),  # 3*9 + 6 key bits > 32
+                dict(lag=100), dict(chunk=100), dict(capacity=-1), dict(flags=0x20)):  # graphs need a stream
         assert lib.mpm_create(ct.byref(cfg(**bad)), ct.byref(h)) == mpm.EINVAL, bad
         assert lib.mpm_last_error(None)
+    # a bad per-scene descriptor
+    arr = (mpm.SceneDesc * 2)()
+    arr[0] = mpm.SceneDesc(64, 0, 3, (ct.c_float * 3)(0, -9.8, 0), 1e-4)
+    arr[1] = mpm.SceneDesc(96, 0, 3, (ct.c_float * 3)(0, -9.8, 0), 1e-4)
+    c = cfg(num_scenes=2)
+    c.scenes = ct.cast(arr, ct.POINTER(mpm.SceneDesc))
+    assert lib.mpm_create(ct.byref(c), ct.byref(h)) == mpm.EINVAL
+    assert b"power of two" in lib.mpm_last_error(None)
     assert lib.mpm_create(None, ct.byref(h)) == mpm.EINVAL
     assert lib.mpm_destroy(None) == mpm.OK
 
