@@ -155,6 +155,104 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_surrogate(args):
+    """The learned snow return map on the snow scene: trained on the GPU from
+    exact-path runs of snow scenes with other sphere seeds (4 and 40), then
+    the seed-1 scene is advanced with the exact map, the learned map and the
+    same eigenvector-free path with the exact clamp (no network); positions
+    are compared with the exact run after the timed frames."""
+    import torch
+
+    from paper_2111_00699_amd import mpm, scenes
+
+    torch.cuda.set_device(0)
+    cfg = scenes.snow_config()
+    nsub = cfg["substeps_per_frame"]
+
+    def make(sc):
+        sim = mpm.Sim(cfg["n"], cfg["dt"], bc=cfg["bc"], bc_cells=cfg["bc_cells"], gravity=cfg["gravity"],
+                      capacity=2 * sc["x"].shape[1] + 256)
+        sim.add_particles(scenes.SNOW, sc["x"])
+        return sim
+
+    # training pairs: states of two other snow scenes every 1/3 frame after they have landed
+    Xs, Ts = [], []
+    t0 = time.perf_counter()
+    for seed in (4, 40):
+        sim = make(scenes.snow_spheres(seed))
+        sim.substep(nsub * args.sur_start_frame)
+        for k in range(args.train_snapshots):
+            sim.substep(nsub // 3)
+            X, T = mpm.Surrogate.sample(sim, dt_ref=cfg["dt"])
+            Xs.append(X.clone())
+            Ts.append(T.clone())
+        sim.close()
+    X = torch.cat(Xs)
+    T = torch.cat(Ts)
+    del Xs, Ts
+    t_sample = time.perf_counter() - t0
+    sur = mpm.Surrogate()
+    sur.set(scenes.mlp_init(4))
+    sur.fit_norm(X, T)
+    t0 = time.perf_counter()
+    losses = sur.train(X, T, steps=args.train_steps, batch=16384, lr=2e-3, seed=7)
+    t_train = time.perf_counter() - t0
+    log(f"[bench] surrogate: {X.shape[0]} pairs in {t_sample:.1f} s, {args.train_steps} Adam steps in {t_train:.1f} s, "
+        f"loss {losses[:10].mean():.3e} -> {losses[-10:].mean():.3e}")
+    # evaluation: the seed-1 scene advanced to the same frame on the exact path, then each mode from there
+    sc = scenes.snow_spheres(1)
+    N = sc["x"].shape[1]
+    sim = make(sc)
+    sim.substep(nsub * args.sur_start_frame)
+    start = sim.read_particles()
+    sim.close()
+    results = {}
+    finals = {}
+    for name, mode in (("exact", 0), ("surrogate", 1), ("closed_form", 2)):
+        sim = mpm.Sim(cfg["n"], cfg["dt"], bc=cfg["bc"], bc_cells=cfg["bc_cells"], gravity=cfg["gravity"],
+                      capacity=2 * N + 256)
+        sim.add_particles(scenes.SNOW, start["x"], v=start["v"], C=start["C"], F=start["F"], s=start["s"])
+        if mode:
+            sim.use_surrogate(mode, sur if mode == 1 else None, tol=args.sur_tol, dt_ref=cfg["dt"])
+        sim.substep(nsub // 3)  # warm-up
+        sim.synchronize()
+        st0 = sim.stats()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            sim.substep(nsub)
+        e1.record()
+        torch.cuda.synchronize()
+        st1 = sim.stats()
+        finals[name] = sim.read_particles()["x"]
+        done = st1["surrogate_particles"] - st0["surrogate_particles"]
+        fb = st1["surrogate_fallbacks"] - st0["surrogate_fallbacks"]
+        results[name] = {"ms_per_frame": e0.elapsed_time(e1) / args.steps,
+                         "fallback_rate": (fb / max(done + fb, 1)) if mode else None}
+        sim.close()
+        log(f"[bench] {name}: {results[name]}")
+    dx = 1.0 / cfg["n"]
+    for name in ("surrogate", "closed_form"):
+        d = (finals[name] - finals["exact"]).norm(dim=0) / dx
+        results[name]["position_error_dx"] = {"mean": float(d.mean()), "max": float(d.max())}
+    ex = results["exact"]["ms_per_frame"]
+    out = {
+        "metric": "particle-substeps/s", "value": N * nsub / (results["surrogate"]["ms_per_frame"] * 1e-3),
+        "unit": "particle-substeps/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": results["surrogate"]["ms_per_frame"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 (MLP bf16 operands, f32 accumulation)", "data": "synthetic",
+        "config": {"workload": "snow scene (seed 1, 1.28M particles, 256^3) from the frame after landing, with the "
+                               "learned return map; trained on pairs from the exact path on sphere seeds 4 and 40",
+                   "frames_timed": args.steps, "start_frame": args.sur_start_frame,
+                   "train_pairs": int(X.shape[0]), "train_steps": args.train_steps,
+                   "final_loss": float(losses[-10:].mean()), "tol": args.sur_tol},
+        "modes": results,
+        "speedup_vs_exact": {k: ex / v["ms_per_frame"] for k, v in results.items()},
+    }
+    sur.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,7 +261,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--flags", type=int, default=0)
-    ap.add_argument("--workload", choices=("snow", "batched"), default="snow")
+    ap.add_argument("--workload", choices=("snow", "batched", "surrogate"), default="snow")
+    ap.add_argument("--train-snapshots", type=int, default=4, help="surrogate: training snapshots per scene")
+    ap.add_argument("--train-steps", type=int, default=2000, help="surrogate: Adam steps")
+    ap.add_argument("--sur-tol", type=float, default=1e-2, help="surrogate: residual tolerance")
+    ap.add_argument("--sur-start-frame", type=int, default=24, help="surrogate: frame the comparison starts at")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 4 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -185,6 +287,9 @@ def main():
 
     if args.workload == "batched":
         bench_batched(args)
+        return
+    if args.workload == "surrogate":
+        bench_surrogate(args)
         return
 
     from paper_2111_00699_amd import mpm, scenes
