@@ -74,7 +74,7 @@ typedef enum { MPM_BC_STICKY = 0, MPM_BC_SLIP = 1, MPM_BC_SEPARATE = 2 } mpm_bc;
 #define MPM_FLAG_G2P_GLOBAL_GATHER 0x10u /* G2P gathers every node from the dense grid instead of an LDS
                                             copy of the chunk's node box */
 #define MPM_FLAG_P2G_SORTED_LANES 0x8u   /* store each chunk in plain sorted order instead of the
-                                            strided order that spreads a wave over cells */
+                                            cell-round order that spreads a wave over cells */
 #define MPM_FLAG_FRAME_GRAPHS 0x20u      /* mpm_frame records a whole frame (one rebuild at its start, then
                                             every scene's substeps) as a HIP graph per particle-buffer
                                             parity and replays it; within a frame the free-zone flag is not
@@ -213,9 +213,11 @@ int mpm_read_grid(mpm_ctx* ctx, int32_t scene, float* m_dev, float* v_dev);
  * sorted position (a stable sort: ties keep their storage order before the
  * rebuild).  Storage layout after a rebuild: scenes in order of increasing dt
  * (ties by scene index), inside a scene geometric blocks in code order,
- * each cut into chunks of config.chunk particles; inside a chunk of c
- * particles, slot t holds sorted position (t*K) mod c with K the smallest of
- * 9, 11, 13, 17 coprime to c (identity with MPM_FLAG_P2G_SORTED_LANES).
+ * each cut into chunks of config.chunk particles; inside a chunk the
+ * particles are stored by cell rounds: the first particle (in sorted order)
+ * of every cell of the chunk in cell-code order, then the second particle of
+ * every cell that has two, and so on (plain sorted order with
+ * MPM_FLAG_P2G_SORTED_LANES).
  * count must equal the scene's particle count at the last rebuild.
  * Synchronizes.                                                             */
 int mpm_read_binning(mpm_ctx* ctx, int32_t scene, int64_t count, uint32_t* keys_dev, int32_t* perm_dev);
@@ -319,9 +321,11 @@ int mpm_surrogate_train(mpm_surrogate* s, int64_t count, const float* X_dev, con
  * count.                                                                    */
 /* Choose how P2G maps a snow scene's trial state (mode):
  *   0  exact: singular values by Jacobi rotations, clamp, stress (default);
- *   1  the surrogate s predicts the projected singular values (as ln(s'/s)),
- *      the principal stress and J_P'/J_P; F_E' and tau are rebuilt from the
- *      eigenvalues of F^ F^T by Sylvester's formula (no eigenvectors);
+ *   1  the surrogate s predicts the projected singular values (as ln(s'/s))
+ *      and J_P'/J_P; the stress is evaluated from that state and must agree
+ *      with the network's principal stress outputs within tol (x E); F_E'
+ *      and tau are rebuilt from the eigenvalues of F^ F^T by Sylvester's
+ *      formula (no eigenvectors);
  *   2  the same eigenvector-free path with the exact clamp instead of the
  *      network (the method without the network).
  * Modes 1 and 2 fall back to mode 0 per particle when two eigenvalues of

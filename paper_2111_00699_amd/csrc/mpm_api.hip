@@ -1223,8 +1223,9 @@ int mpm_use_surrogate(mpm_ctx* c, int32_t scene, const mpm_surrogate* s, int32_t
     c->table[scene].E = c->sh[scene].has_mat ? c->sh[scene].mat.E : 0.0f;
     HIP_OK(c, hipMemcpyAsync(c->scene_dev + scene, &c->table[scene], sizeof(Scene), hipMemcpyHostToDevice, c->stream));
     HIP_OK(c, hipStreamSynchronize(c->stream));
-    c->sur_any = 0;
-    for (int k = 0; k < c->nsc; ++k) c->sur_any |= c->table[k].ret != 0;
+    c->sur_any = 0;  // 2 if some scene runs the network, 1 if only the closed form
+    for (int k = 0; k < c->nsc; ++k)
+        c->sur_any = std::max(c->sur_any, c->table[k].ret == 1 ? 2 : c->table[k].ret == 2 ? 1 : 0);
     if (!c->sur_any) c->sur_theta = c->sur_norm = nullptr;
     if (c->sur_any && !c->sur_theta && mode == 1) return fail(c, MPM_EINVAL, "no surrogate attached");
     drop_graphs(c);  // recorded kernels carry the old choice

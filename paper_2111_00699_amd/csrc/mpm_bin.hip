@@ -276,29 +276,60 @@ struct OpActive {
 };
 
 // ------------------------------------------------------------ data movement
-// Gather the whole particle state into sorted order, chunk by chunk; inside a
-// chunk, storage slot t takes sorted position (t * K) mod count (see
-// chunk_stride) unless `spread` is 0.  Also records the insertion ids in
-// plain sorted order for the binning view.
+// Gather the whole particle state into sorted order, one chunk per
+// workgroup.  Inside a chunk (a sorted run of one block, so its particles are
+// grouped by cell in cell-code order) the storage order is by rounds: the
+// first particle of every cell in cell order, then the second particle of
+// every cell that has two, and so on (unless `spread` is 0: plain sorted
+// order).  A wave then holds about one particle per cell, and the 16 lanes
+// an LDS access serves together hold a 4x2x2 patch of cells.  Also records
+// the insertion ids in plain sorted order for the binning view.
 __global__ __launch_bounds__(WG) void k_permute_chunks(const float* __restrict__ Sin, float* __restrict__ Sout,
                                                        const int* __restrict__ idin, int* __restrict__ idout,
                                                        int* __restrict__ sorted_ids, const uint32_t* __restrict__ src,
+                                                       const uint32_t* __restrict__ keys,
                                                        const Chunk* __restrict__ chunks, const int* __restrict__ ctl,
                                                        int64_t cap, int spread) {
+    __shared__ int cnt[64], first[64];
     const int nch = ctl[CTL_NCHUNK];
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
         const Chunk ch = chunks[c];
-        const int K = spread ? chunk_stride(ch.count) : 1;
+        if (spread) {
+            if (threadIdx.x < 64) {
+                cnt[threadIdx.x] = 0;
+                first[threadIdx.x] = INT32_MAX;
+            }
+            __syncthreads();
+            for (int t = threadIdx.x; t < ch.count; t += WG) {
+                const int cell = (int)(keys[ch.start + t] & 63u);
+                atomicAdd(&cnt[cell], 1);
+                atomicMin(&first[cell], t);
+            }
+            __syncthreads();
+        }
         for (int t = threadIdx.x; t < ch.count; t += WG) {
-            const int j = ch.start + (t * K) % ch.count;  // sorted position
-            const int k = (int)src[j];                     // its position before the sort
-            const int dst = ch.start + t;
+            const int j = ch.start + t;  // sorted position
+            int slot = t;
+            if (spread) {
+                const int cell = (int)(keys[j] & 63u);
+                const int r = t - first[cell];  // rank inside its cell
+                int before = 0, pos = 0;
+                for (int q = 0; q < 64; ++q) {
+                    const int n_q = cnt[q];
+                    before += min(n_q, r);               // particles of the earlier rounds
+                    pos += (q < cell && n_q > r) ? 1 : 0;  // cells ahead in this round
+                }
+                slot = before + pos;
+            }
+            const int k = (int)src[j];  // its position before the sort
+            const int dst = ch.start + slot;
 #pragma unroll
             for (int f = 0; f < NF; ++f) Sout[f * cap + dst] = Sin[f * cap + k];
             const int id = idin[k];
             idout[dst] = id;
             sorted_ids[j] = id;
         }
+        if (spread) __syncthreads();
     }
 }
 
@@ -400,7 +431,7 @@ void enqueue_rebuild(hipStream_t st, const Scenes& T, float* S_cur, float* S_alt
                 ctl + CTL_NCHUNK);
     // 4. gather the whole particle state into (chunk-spread) sorted order
     hipLaunchKernelGGL(k_permute_chunks, dim3(2048), dim3(WG), 0, st, S_cur, S_alt, id_cur, id_alt, B.sorted_ids,
-                       B.vals[cur], B.chunks, ctl, cap, spread);
+                       B.vals[cur], B.keys[cur], B.chunks, ctl, cap, spread);
     // 5. physical blocks: 3x3x3 dilation, compacted in padded linear order
     hipLaunchKernelGGL(k_fill, dim3(cdiv(nbricks, WG)), dim3(WG), 0, st, B.brick_state, 0, nbricks);
     hipLaunchKernelGGL(k_fill, dim3(cdiv(nbricks, WG)), dim3(WG), 0, st, B.gindex, -1, nbricks);

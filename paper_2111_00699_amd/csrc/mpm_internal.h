@@ -101,7 +101,7 @@ struct Scenes {
     float sur_tol;           // residual tolerance of the learned map
     float sur_gap;           // smallest eigenvalue separation (units of the spread) for the closed form
     float sur_dt_ref;        // time step the surrogate was trained at
-    int sur_any;             // some scene maps its snow without SVD (ret != 0)
+    int sur_any;             // 2: some scene runs the network; 1: some the closed form only; 0: none
 };
 
 enum RankEnd : int { RE_PART = 0, RE_GBLOCK = 1, RE_CHUNK = 2, RE_ACTIVE = 3 };
@@ -140,14 +140,6 @@ struct BinBuffers {
     int* sorted_ids;   // [cap] insertion id of each particle in particle-code order
     int sorted;        // which keys/vals slot holds the last sorted codes (host side)
 };
-
-// Within a chunk, storage slot t holds sorted position (t * K) mod count, K
-// the smallest of 9, 11, 13, 17 coprime to count (so a permutation; count <=
-// 512 < 3*11*13*17 guarantees one): 64 consecutive slots -- one wave -- then
-// sit about one cell apart.
-__host__ __device__ inline int chunk_stride(int count) {
-    return (count % 3) ? 9 : (count % 11) ? 11 : (count % 13) ? 13 : 17;
-}
 
 // Codes, stable radix sort, blocks, chunks and the gather into sorted order
 // for all scenes at once; `key_bits` is the width of the particle codes.

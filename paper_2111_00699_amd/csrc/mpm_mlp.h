@@ -13,6 +13,11 @@ namespace mlp {
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// tanh(x) = 1 - 2 / (1 + exp(2x)): one exponential and one division, exact
+// to ~1e-7 absolute, well inside the BF16 operands it feeds (and -> +-1 for
+// large |x| without overflow trouble: exp -> inf gives 1, exp -> 0 gives -1).
+__device__ __forceinline__ float act_tanh(float x) { return 1.0f - 2.0f / (1.0f + __expf(2.0f * x)); }
+
 // Round to nearest even (finite inputs; the network's values are bounded).
 __device__ __forceinline__ short to_bf16(float x) {
     const uint32_t u = __float_as_uint(x);
@@ -125,7 +130,7 @@ __device__ __forceinline__ void forward_tile(const NetLds& L, const float* xin, 
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
         acc = mma_w<BF16>(acc, L.W1, 16, mt, 0, xb);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) h1[mt][r] = tanhf(acc[r] + L.b1[16 * mt + 4 * g + r]);
+        for (int r = 0; r < 4; ++r) h1[mt][r] = act_tanh(acc[r] + L.b1[16 * mt + 4 * g + r]);
     }
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
@@ -133,7 +138,7 @@ __device__ __forceinline__ void forward_tile(const NetLds& L, const float* xin, 
 #pragma unroll
         for (int kt = 0; kt < 4; ++kt) acc = mma_w<BF16>(acc, L.W2, 64, mt, kt, h1[kt]);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) h2[mt][r] = tanhf(acc[r] + L.b2[16 * mt + 4 * g + r]);
+        for (int r = 0; r < 4; ++r) h2[mt][r] = act_tanh(acc[r] + L.b2[16 * mt + 4 * g + r]);
     }
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -154,6 +159,72 @@ __device__ __forceinline__ void stage_input(const NetLds& L, const float* __rest
         if (valid && f < SUR_IN) v = (X[row * SUR_IN + f] - L.imu[f]) / L.isd[f];
         xin[s * 16 + f] = v;
     }
+}
+
+// Inference copy of the network for P2G: weights already rounded to BF16
+// (so an A fragment is one 8-byte LDS read), biases and normalisation FP32.
+struct NetLds16 {
+    short W1[64 * 16], W2[64 * 64], W3[16 * 64];
+    float b1[64], b2[64], b3[16];
+    float imu[16], isd[16], omu[16], osd[16];
+};
+
+__device__ inline void load_net16(NetLds16& L, const float* __restrict__ th, const float* __restrict__ norm) {
+    for (int t = threadIdx.x; t < 64 * 16; t += blockDim.x) {
+        const int o = t >> 4, i = t & 15;
+        L.W1[t] = to_bf16(i < SUR_IN ? th[SUR_W1 + o * SUR_IN + i] : 0.0f);
+        const int o3 = t >> 6, i3 = t & 63;
+        L.W3[t] = to_bf16(o3 < SUR_OUT ? th[SUR_W3 + o3 * SUR_H + i3] : 0.0f);
+    }
+    for (int t = threadIdx.x; t < 64 * 64; t += blockDim.x) L.W2[t] = to_bf16(th[SUR_W2 + t]);
+    for (int t = threadIdx.x; t < 64; t += blockDim.x) {
+        L.b1[t] = th[SUR_B1 + t];
+        L.b2[t] = th[SUR_B2 + t];
+    }
+    for (int t = threadIdx.x; t < 16; t += blockDim.x) {
+        L.b3[t] = t < SUR_OUT ? th[SUR_B3 + t] : 0.0f;
+        L.imu[t] = t < SUR_IN ? norm[t] : 0.0f;
+        L.isd[t] = t < SUR_IN ? norm[SUR_IN + t] : 1.0f;
+        L.omu[t] = t < SUR_OUT ? norm[2 * SUR_IN + t] : 0.0f;
+        L.osd[t] = t < SUR_OUT ? norm[2 * SUR_IN + SUR_OUT + t] : 1.0f;
+    }
+}
+
+__device__ __forceinline__ f32x4 mma16(f32x4 acc, const short* W, int ld, int mt, int kt, const float b[4]) {
+    const int lane = threadIdx.x & 63, i = lane & 15, g = lane >> 4;
+    const bf16x4 a = *reinterpret_cast<const bf16x4*>(W + (16 * mt + i) * ld + 16 * kt + 4 * g);
+    bf16x4 bb;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bb[j] = to_bf16(b[j]);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc, 0, 0, 0);
+}
+
+// The forward pass of forward_tile with the BF16 inference copy (y: normalised outputs).
+__device__ __forceinline__ void forward_tile16(const NetLds16& L, const float* xin, float y[4]) {
+    const int lane = threadIdx.x & 63, g = lane >> 4, s = lane & 15;
+    float xb[4], h1[4][4], h2[4][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) xb[j] = xin[s * 16 + 4 * g + j];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mma16(acc, L.W1, 16, mt, 0, xb);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) h1[mt][r] = act_tanh(acc[r] + L.b1[16 * mt + 4 * g + r]);
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt) acc = mma16(acc, L.W2, 64, mt, kt, h1[kt]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) h2[mt][r] = act_tanh(acc[r] + L.b2[16 * mt + 4 * g + r]);
+    }
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt) acc = mma16(acc, L.W3, 64, 0, kt, h2[kt]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) y[r] = acc[r] + L.b3[4 * g + r];
 }
 
 }  // namespace mlp

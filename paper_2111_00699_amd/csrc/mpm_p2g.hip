@@ -22,9 +22,11 @@
 //     transfer of in-zone particles is deterministic.  Each workgroup owns an
 //     equal slice of the staging buffer and packs its chunks' tiles there
 //     (offset recorded per chunk), so no allocation is shared.
-// The rebuild stores each chunk with its sorted order spread by a stride
-// coprime to the count, so the 64 lanes of a wave sit in different cells
-// and rarely hit one LDS address (same-address atomics serialize).
+// The rebuild stores each chunk by cell rounds (first particle of every
+// cell, then the second, ...), so the 64 lanes of a wave sit in different
+// cells and rarely hit one LDS address (same-address atomics serialize),
+// and the tile's padded pitches put the 16 lanes of one LDS access on
+// different banks.
 // Particles outside their free zone (before a late rebuild) scatter straight
 // to global atomics and activate the blocks they touch.
 #include <type_traits>
@@ -36,7 +38,19 @@ namespace mpm {
 
 namespace {
 
-constexpr int CT = 512;  // compact tile capacity in nodes
+constexpr int CT = 1024;  // LDS tile capacity in nodes (padded layout, below)
+
+// LDS tile layout of a box of ext0 x ext1 x ext2 nodes: node (x, y, z) at
+// x + R y + Q z with the row pitch R in {4, 12} (so R = 4 or 12 mod 16) and
+// the plane pitch Q = 8 (mod 16).  With the round-ordered chunks, the 16
+// lanes an LDS access serves together hold cells x in 0..3, y in {y, y+1},
+// z in {z, z+1}; their FP64 addresses x + R y' + Q z' then fall on 16
+// different bank pairs for every stencil offset.
+__device__ __forceinline__ int pitch_row(int e0) { return e0 <= 4 ? 4 : 12; }
+__device__ __forceinline__ int pitch_plane(int R, int e1) {
+    const int q = R * e1;
+    return q + ((8 - (q & 15)) & 15);
+}
 
 // ------------------------------------------------ snow return map without SVD
 // Eigenvalues of the symmetric b = [b0 b1 b2; . b3 b4; . . b5] as
@@ -87,7 +101,7 @@ __device__ __forceinline__ void lagrange(const float mu[3], const float c[3], fl
 // particle is inverted, or (network) the prediction leaves the yield
 // surface or changes the total volume by more than the tolerance.
 template <bool NET>
-__device__ void snow_without_svd(const mlp::NetLds& net, float* stage, const Scenes& T, const Scene& sc, float dt,
+__device__ void snow_without_svd(const mlp::NetLds16* net, float* stage, const Scenes& T, const Scene& sc, float dt,
                                  int pending, bool have, const float C[9], float F[9], float& s, float tau[6],
                                  bool& fell_back) {
     const Mat& M = sc.M;
@@ -112,7 +126,7 @@ __device__ void snow_without_svd(const mlp::NetLds& net, float* stage, const Sce
 #pragma unroll
     for (int k = 0; k < 3; ++k) sh[k] = use ? sqrtf(fmaxf(q + p * mu[k], 1e-30f)) : 1.0f;
     const float Jp = use ? s : 1.0f;
-    if (NET && pending) {
+    if (NET && pending && __ballot(use) != 0ull) {  // a wave with no eligible lane skips the network
         // features [s, ln s, J_P, ln J_P, h, dt/dt_ref, s1 s2 s3, 1], one 16-sample tile at a time
         float xf[SUR_IN] = {sh[0], sh[1], sh[2], logf(sh[0]), logf(sh[1]), logf(sh[2]), Jp, logf(Jp),
                             expf(M.xi * (1.0f - Jp)), dt / T.sur_dt_ref, sh[0] * sh[1] * sh[2], 1.0f};
@@ -123,33 +137,42 @@ __device__ void snow_without_svd(const mlp::NetLds& net, float* stage, const Sce
         for (int t = 0; t < 4; ++t) {
             if ((lane >> 4) == t) {
 #pragma unroll
-                for (int f = 0; f < 16; ++f) xs[sl * 16 + f] = f < SUR_IN ? (xf[f] - net.imu[f]) / net.isd[f] : 0.0f;
+                for (int f = 0; f < 16; ++f) xs[sl * 16 + f] = f < SUR_IN ? (xf[f] - net->imu[f]) / net->isd[f] : 0.0f;
             }
             __builtin_amdgcn_wave_barrier();
-            float h1[4][4], h2[4][4], y[4];
-            mlp::forward_tile<true>(net, xs, h1, h2, y);
+            float y[4];
+            mlp::forward_tile16(*net, xs, y);
 #pragma unroll
             for (int r = 0; r < 4; ++r) ys[sl * 16 + 4 * g + r] = y[r];
             __builtin_amdgcn_wave_barrier();
             if ((lane >> 4) == t) {
 #pragma unroll
-                for (int o = 0; o < SUR_OUT; ++o) yv[o] = ys[sl * 16 + o] * net.osd[o] + net.omu[o];
+                for (int o = 0; o < SUR_OUT; ++o) yv[o] = ys[sl * 16 + o] * net->osd[o] + net->omu[o];
             }
             __builtin_amdgcn_wave_barrier();
         }
-        // outputs [s', ln(s'/s), tau/E, J_P'/J_P, h', s1's2's3']
+        // outputs [s', ln(s'/s), tau/E, J_P'/J_P, h', s1's2's3']: the projected state comes from
+        // ln(s'/s) and J_P'/J_P; the stress is evaluated from that state, and the network's own
+        // stress outputs serve as a consistency check
+        float res_t = 0.0f;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            sn[k] = sh[k] * expf(yv[3 + k]);
-            tk[k] = yv[6 + k] * sc.E;
-        }
+        for (int k = 0; k < 3; ++k) sn[k] = sh[k] * expf(yv[3 + k]);
         Jpn = Jp * yv[9];
+        {
+            const float h = expf(M.xi * (1.0f - Jpn));
+            const float Jn = sn[0] * sn[1] * sn[2];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                tk[k] = 2.0f * M.mu * h * (sn[k] - 1.0f) * sn[k] + M.la * h * (Jn - 1.0f) * Jn;
+                res_t = fmaxf(res_t, fabsf(yv[6 + k] - tk[k] / sc.E));
+            }
+        }
         float res_y = 0.0f;
 #pragma unroll
         for (int k = 0; k < 3; ++k) res_y = fmaxf(res_y, fmaxf(M.lo - sn[k], sn[k] - M.hi));
         const float res_v = fabsf(logf(sn[0] * sn[1] * sn[2] * Jpn) - logf(sh[0] * sh[1] * sh[2] * Jp));
         const bool fin = isfinite(tk[0] + tk[1] + tk[2] + Jpn + sn[0] + sn[1] + sn[2]);
-        use = use && fin && res_y <= T.sur_tol && res_v <= T.sur_tol;
+        use = use && fin && res_y <= T.sur_tol && res_v <= T.sur_tol && res_t <= T.sur_tol;
     } else {
         // exact clamp; with nothing pending the stored state is already projected
         // (as in the exact path), so only the stress is evaluated
@@ -206,9 +229,9 @@ __device__ void snow_without_svd(const mlp::NetLds& net, float* stage, const Sce
 }
 
 // NT threads per workgroup = the largest chunk it takes (128, 256 or 512).
-// SUR: some scene maps its snow without SVD (closed form or network), so the
-// network is staged in LDS.
-template <bool GLOBAL_ONLY, int NT, bool SUR>
+// SURM: 0 every snow scene takes the exact map; 1 some scene takes the
+// closed form without SVD; 2 some scene takes the network (staged in LDS).
+template <bool GLOBAL_ONLY, int NT, int SURM>
 __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, const Chunk* __restrict__ chunks,
                                             int* __restrict__ ctl, float* __restrict__ acc,
                                             float4* __restrict__ stage, int stage_nodes, int4* __restrict__ box,
@@ -217,10 +240,10 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
     __shared__ double tq[GLOBAL_ONLY ? 1 : 4 * CT];
     __shared__ int red_i[6][NT / 64];
     struct Empty {};
-    __shared__ typename std::conditional<SUR, mlp::NetLds, Empty>::type net;
-    __shared__ float sur_stage[SUR ? NT / 64 * 512 : 1];
-    if constexpr (SUR) {
-        if (T.sur_theta) mlp::load_net(net, T.sur_theta, T.sur_norm);
+    __shared__ typename std::conditional<SURM == 2, mlp::NetLds16, Empty>::type net;
+    __shared__ float sur_stage[SURM == 2 ? NT / 64 * 512 : 1];
+    if constexpr (SURM == 2) {
+        if (T.sur_theta) mlp::load_net16(net, T.sur_theta, T.sur_norm);
         __syncthreads();
     }
     unsigned err = 0;
@@ -268,14 +291,18 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
             }
         }
         bool sur_chunk = false;
-        if constexpr (SUR) {
+        if constexpr (SURM != 0) {
             sur_chunk = sc.ret != 0 && M.kind == MPM_SNOW;  // uniform over the workgroup
             if (sur_chunk) {
                 bool fb = false;
-                if (sc.ret == 1)
-                    snow_without_svd<true>(net, sur_stage + wv * 512, T, sc, dt, pending, have, C, F, s, tau, fb);
-                else
-                    snow_without_svd<false>(net, sur_stage + wv * 512, T, sc, dt, pending, have, C, F, s, tau, fb);
+                if constexpr (SURM == 2) {
+                    if (sc.ret == 1)
+                        snow_without_svd<true>(&net, sur_stage + wv * 512, T, sc, dt, pending, have, C, F, s, tau, fb);
+                    else
+                        snow_without_svd<false>(&net, sur_stage, T, sc, dt, pending, have, C, F, s, tau, fb);
+                } else {  // no network in this variant
+                    snow_without_svd<false>(nullptr, nullptr, T, sc, dt, pending, have, C, F, s, tau, fb);
+                }
                 n_sur += __popcll(__ballot(have && !fb));
                 n_fb += __popcll(__ballot(fb));
             }
@@ -311,7 +338,7 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
 
         // ---- the box of the in-zone stencils of the chunk
         int lo[3] = {0, 0, 0}, ext[3] = {0, 0, 0};
-        int nt = 0, off = 0;
+        int nt = 0, off = 0, R = 4, Q = 8;  // tight node count, staging offset, LDS pitches
         if (GLOBAL_ONLY && tid == 0) box[c] = make_int4(0, 0, 0, 0);
         if (!GLOBAL_ONLY) {
             const bool tiled = have && in_zone;
@@ -347,13 +374,18 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
 #pragma unroll
                 for (int a = 0; a < 3; ++a) ext[a] = hi[a] - lo[a] + 1;
                 nt = ext[0] * ext[1] * ext[2];
+                R = pitch_row(ext[0]);
+                Q = pitch_plane(R, ext[1]);
             }
             // no room in the tile or in this workgroup's staging slice: the chunk goes to global atomics
-            if (nt > CT || used + nt > slice) nt = -1;
+            if (Q * ext[2] > CT || used + nt > slice) nt = -1;
             if (nt < 0 && tid == 0) atomicAdd(&ctl64(ctl)[CTL64_FALLBACK_CHUNKS], 1ull);
             off = slice0 + used;
             if (nt > 0) used += nt;
-            for (int t = tid; t < nt; t += NT) {
+            const int e01 = ext[0] * ext[1];
+            for (int u = tid; u < nt; u += NT) {  // clear the box's nodes at their padded addresses
+                const int z = u / e01, y = (u - z * e01) / ext[0], x = u - z * e01 - y * ext[0];
+                const int t = x + R * y + Q * z;
 #pragma unroll
                 for (int ch4 = 0; ch4 < 4; ++ch4) tq[ch4 * CT + t] = 0.0;
             }
@@ -374,7 +406,7 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
         }
         if (have && ok) {
             if (!GLOBAL_ONLY && in_zone && nt > 0) {
-                const int tb = (st.base[0] - lo[0]) + ext[0] * ((st.base[1] - lo[1]) + ext[1] * (st.base[2] - lo[2]));
+                const int tb = (st.base[0] - lo[0]) + R * (st.base[1] - lo[1]) + Q * (st.base[2] - lo[2]);
 #pragma unroll
                 for (int o2 = 0; o2 < 3; ++o2)
 #pragma unroll
@@ -383,7 +415,7 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
                         float m0 = q[0] + o1 * Ad[1] + o2 * Ad[2];
                         float m1 = q[1] + o1 * Ad[4] + o2 * Ad[5];
                         float m2 = q[2] + o1 * Ad[7] + o2 * Ad[8];
-                        const int row = tb + ext[0] * (o1 + ext[1] * o2);
+                        const int row = tb + R * o1 + Q * o2;
 #pragma unroll
                         for (int o0 = 0; o0 < 3; ++o0) {
                             const float w = wyz * st.w[0][o0];
@@ -433,14 +465,18 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
         if (!GLOBAL_ONLY) {
             __syncthreads();
             float4* slot = stage + off;
-            for (int t = tid; t < nt; t += NT)
-                slot[t] = make_float4((float)(tq[t] * (double)M.mp), (float)tq[CT + t], (float)tq[2 * CT + t],
+            const int e01 = ext[0] * ext[1];
+            for (int u = tid; u < nt; u += NT) {  // staged in the tight box layout
+                const int z = u / e01, y = (u - z * e01) / ext[0], x = u - z * e01 - y * ext[0];
+                const int t = x + R * y + Q * z;
+                slot[u] = make_float4((float)(tq[t] * (double)M.mp), (float)tq[CT + t], (float)tq[2 * CT + t],
                                       (float)tq[3 * CT + t]);
+            }
             __syncthreads();
         }
     }
     if (err) atomicOr(&ctl[CTL_ERROR], (int)err);
-    if (SUR && (threadIdx.x & 63) == 0) {
+    if (SURM != 0 && (threadIdx.x & 63) == 0) {
         if (n_sur) atomicAdd(&ctl64(ctl)[CTL64_SUR_PARTICLES], (unsigned long long)n_sur);
         if (n_fb) atomicAdd(&ctl64(ctl)[CTL64_SUR_FALLBACKS], (unsigned long long)n_fb);
     }
@@ -450,9 +486,9 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
 
 int p2g_grid_size(int cus, int chunk) {
     const int nt = chunk_threads(chunk);
-    const void* fn = nt == 128   ? reinterpret_cast<const void*>(k_p2g<false, 128, false>)
-                     : nt == 256 ? reinterpret_cast<const void*>(k_p2g<false, 256, false>)
-                                 : reinterpret_cast<const void*>(k_p2g<false, 512, false>);
+    const void* fn = nt == 128   ? reinterpret_cast<const void*>(k_p2g<false, 128, 0>)
+                     : nt == 256 ? reinterpret_cast<const void*>(k_p2g<false, 256, 0>)
+                                 : reinterpret_cast<const void*>(k_p2g<false, 512, 0>);
     // Twice the resident workgroups: chunks differ in size, and a second wave
     // of workgroups evens out the per-XCD work split.
     int occ = 2 * wgs_per_cu(fn, nt);
@@ -477,11 +513,11 @@ void enqueue_p2g(hipStream_t st, const Launch& L, const Scenes& T, float* S, int
             MPM_LAUNCH_P2G(GO, 512, SU);                 \
     } while (0)
     const int nt = chunk_threads(chunk);
-    const bool sur = T.sur_any != 0;
+    const int surm = T.sur_any;  // 0, 1 (closed form) or 2 (network)
     if (global_atomics) {
-        if (sur) MPM_LAUNCH_P2G_NT(true, true); else MPM_LAUNCH_P2G_NT(true, false);
+        if (surm == 2) MPM_LAUNCH_P2G_NT(true, 2); else if (surm == 1) MPM_LAUNCH_P2G_NT(true, 1); else MPM_LAUNCH_P2G_NT(true, 0);
     } else {
-        if (sur) MPM_LAUNCH_P2G_NT(false, true); else MPM_LAUNCH_P2G_NT(false, false);
+        if (surm == 2) MPM_LAUNCH_P2G_NT(false, 2); else if (surm == 1) MPM_LAUNCH_P2G_NT(false, 1); else MPM_LAUNCH_P2G_NT(false, 0);
     }
 #undef MPM_LAUNCH_P2G_NT
 #undef MPM_LAUNCH_P2G

@@ -54,7 +54,8 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, float4* __
         const int NB = P.NB, base = sc.brick_base;
         const int lb = b - base;
         const int bx = lb % NB, by = (lb / NB) % NB, bz = lb / (NB * NB);
-        const int g[3] = {4 * (bx - 1) + lx, 4 * (by - 1) + ly, 4 * (bz - 1) + lz};
+        const int n0 = 4 * (bx - 1), n1 = 4 * (by - 1), n2 = 4 * (bz - 1);  // first node of the block
+        const int g[3] = {n0 + lx, n1 + ly, n2 + lz};
         float4 a = acc4[b * 64 + lane];
         // Lane k < 27 looks up the chunk range of candidate particle block k
         // (padded offsets -1..1 per axis); the ranges are laid out in LDS as
@@ -88,9 +89,18 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, float4* __
             __builtin_amdgcn_wave_barrier();
             const int m = min(64, total_c - base);
             int4 bb = make_int4(0, 0, 0, 0);
-            if (lane < m) bb = box[list[lane]];
+            bool ov = false;  // does candidate `lane`'s tile box reach into this block?
+            if (lane < m) {
+                bb = box[list[lane]];
+                const int e0 = bb.y & 255, e1 = (bb.y >> 8) & 255, e2 = bb.y >> 16;
+                const int l0 = bb.x & 1023, l1 = (bb.x >> 10) & 1023, l2 = bb.x >> 20;
+                ov = e0 > 0 && l0 <= n0 + 3 && l0 + e0 > n0 && l1 <= n1 + 3 && l1 + e1 > n1 && l2 <= n2 + 3 &&
+                     l2 + e2 > n2;
+            }
             __builtin_amdgcn_wave_barrier();
-            for (int i = 0; i < m; ++i) {
+            // only the overlapping candidates are visited (the mask is the same in every lane)
+            for (uint64_t mask = __ballot(ov); mask; mask &= mask - 1) {
+                const int i = __builtin_ctzll(mask);
                 const int bx_ = __shfl(bb.x, i, 64), by_ = __shfl(bb.y, i, 64), s_ = __shfl(bb.z, i, 64);
                 const int e0 = by_ & 255, e1 = (by_ >> 8) & 255, e2 = by_ >> 16;
                 const int r0 = g[0] - (bx_ & 1023), r1 = g[1] - ((bx_ >> 10) & 1023), r2 = g[2] - (bx_ >> 20);

@@ -2,6 +2,8 @@
 header declares, and the Python binding's structs match the C layout.
 No device work is done here."""
 import ctypes as ct
+
+import numpy as np
 import os
 import re
 import subprocess
@@ -120,11 +122,17 @@ def test_binding_refuses_to_run_without_the_library(monkeypatch, tmp_path):
 
 
 def test_documented_chunk_layout_rule_is_a_permutation():
-    """The storage layout include/mpm.h documents (slot t of a chunk of c
-    particles holds sorted position (t*K) mod c, K the smallest of 9, 11, 13,
-    17 coprime to c) must be a permutation for every chunk size up to 512."""
-    import math
+    """The cell-round storage order include/mpm.h documents is a permutation
+    of the chunk, every wave-sized run of it holds each cell at most once
+    while the cells are full, and a round lists its cells in code order."""
+    from tests.test_gpu_parity import round_order
 
-    for c in range(1, 513):
-        K = next(q for q in (9, 11, 13, 17) if math.gcd(q, c) == 1)
-        assert sorted((t * K) % c for t in range(c)) == list(range(c))
+    cells = np.repeat(np.arange(64), 8)  # a full block: 8 particles in each of 64 cells
+    order = round_order(cells)
+    assert sorted(order.tolist()) == list(range(cells.size))
+    for w in range(0, cells.size, 64):
+        wave = cells[order[w:w + 64]]
+        assert len(set(wave.tolist())) == 64
+        assert np.all(np.diff(wave) > 0)
+    ragged = np.array([0, 0, 0, 3, 5, 5, 9])
+    assert ragged[round_order(ragged)].tolist() == [0, 3, 5, 9, 0, 5, 0]

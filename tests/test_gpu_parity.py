@@ -96,18 +96,25 @@ def test_binning_is_bit_exact(torch_cuda, oracle, n, which):
     sim.close()
 
 
-def storage_order(perm, gstart, gcount, chunk=256):
+def round_order(cells):
+    """Slots of a chunk in cell-round order: positions sorted by (rank of the
+    particle inside its cell, cell), for a chunk whose particles are grouped by
+    cell in ascending cell order (the layout include/mpm.h documents)."""
+    cells = np.asarray(cells)
+    rank = np.zeros(cells.size, dtype=np.int64)
+    for k in range(1, cells.size):
+        rank[k] = rank[k - 1] + 1 if cells[k] == cells[k - 1] else 0
+    return np.lexsort((cells, rank))
+
+
+def storage_order(perm, keys, gstart, gcount, chunk=256):
     """Insertion ids in storage order after a rebuild: geometric blocks are cut
-    into chunks of `chunk`, and inside a chunk of `cnt` particles storage slot
-    t holds sorted position (t * K) mod cnt, K the smallest of 9, 11, 13, 17
-    coprime to cnt (the layout include/mpm.h documents)."""
+    into chunks of `chunk`, and each chunk is stored by cell rounds."""
     order = np.empty_like(perm)
     for s0, cnt in zip(gstart.tolist(), gcount.tolist()):
         for k in range(0, cnt, chunk):
             c0, cc = s0 + k, min(chunk, cnt - k)
-            K = next(q for q in (9, 11, 13, 17) if np.gcd(q, cc) == 1)
-            t = np.arange(cc)
-            order[c0 + t] = perm[c0 + (t * K) % cc]
+            order[c0:c0 + cc] = perm[c0 + round_order(keys[c0:c0 + cc] & 63)]
     return order
 
 
@@ -120,14 +127,14 @@ def test_binning_after_motion_composes(torch_cuda, oracle):
     sim = make_sim(torch_cuda, cfg, flags=0x4)
     sim.add_particles(dict(scenes.JELLY, E=0.0), st["x"], v=st["v"])
     sim.substep(10)
-    _, perm0 = sim.read_binning()
+    keys0, perm0 = sim.read_binning()
     b0 = sim.read_blocks()
     x_now = gpu_state(sim)["x"].astype(np.float32)
     sim.rebuild()
     sim.substep(1)
     keys1, perm1 = sim.read_binning()
     # oracle: positions in the storage order left by the first rebuild, then a stable sort
-    order0 = storage_order(perm0, b0["gstart"], b0["gcount"])
+    order0 = storage_order(perm0, keys0, b0["gstart"], b0["gcount"])
     assert np.array_equal(np.sort(order0), np.arange(order0.size))
     xs = x_now[:, order0]
     k, _, _ = oracle.keys(xs, 64)
