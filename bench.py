@@ -195,7 +195,7 @@ def bench_surrogate(args):
     sur.set(scenes.mlp_init(4))
     sur.fit_norm(X, T)
     t0 = time.perf_counter()
-    losses = sur.train(X, T, steps=args.train_steps, batch=16384, lr=2e-3, seed=7)
+    losses = sur.train(X, T, steps=args.train_steps, batch=16384, lr=1e-3, seed=7)
     t_train = time.perf_counter() - t0
     log(f"[bench] surrogate: {X.shape[0]} pairs in {t_sample:.1f} s, {args.train_steps} Adam steps in {t_train:.1f} s, "
         f"loss {losses[:10].mean():.3e} -> {losses[-10:].mean():.3e}")
@@ -263,8 +263,8 @@ def main():
     ap.add_argument("--flags", type=int, default=0)
     ap.add_argument("--workload", choices=("snow", "batched", "surrogate"), default="snow")
     ap.add_argument("--train-snapshots", type=int, default=4, help="surrogate: training snapshots per scene")
-    ap.add_argument("--train-steps", type=int, default=2000, help="surrogate: Adam steps")
-    ap.add_argument("--sur-tol", type=float, default=1e-2, help="surrogate: residual tolerance")
+    ap.add_argument("--train-steps", type=int, default=20000, help="surrogate: Adam steps")
+    ap.add_argument("--sur-tol", type=float, default=2e-3, help="surrogate: residual tolerance")
     ap.add_argument("--sur-start-frame", type=int, default=24, help="surrogate: frame the comparison starts at")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 4 times (HBM counter calibration)")

@@ -212,12 +212,14 @@ int mpm_read_grid(mpm_ctx* ctx, int32_t scene, float* m_dev, float* v_dev);
  * perm_dev[count] the scene-local insertion index of the particle at each
  * sorted position (a stable sort: ties keep their storage order before the
  * rebuild).  Storage layout after a rebuild: scenes in order of increasing dt
- * (ties by scene index), inside a scene geometric blocks in code order,
- * each cut into chunks of config.chunk particles; inside a chunk the
- * particles are stored by cell rounds: the first particle (in sorted order)
- * of every cell of the chunk in cell-code order, then the second particle of
- * every cell that has two, and so on (plain sorted order with
- * MPM_FLAG_P2G_SORTED_LANES).
+ * (ties by scene index), inside a scene geometric blocks in code order;
+ * chunks of at most config.chunk particles: consecutive blocks of one
+ * 2x2x1 slab of blocks (equal block code >> 2) share a chunk while they fit,
+ * a larger block is cut into runs of config.chunk; inside a chunk each
+ * block's particles are stored by cell rounds: the first particle (in
+ * sorted order) of every cell of the block in cell-code order, then the
+ * second particle of every cell that has two, and so on (plain sorted order
+ * with MPM_FLAG_P2G_SORTED_LANES).
  * count must equal the scene's particle count at the last rebuild.
  * Synchronizes.                                                             */
 int mpm_read_binning(mpm_ctx* ctx, int32_t scene, int64_t count, uint32_t* keys_dev, int32_t* perm_dev);

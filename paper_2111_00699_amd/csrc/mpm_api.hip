@@ -218,11 +218,11 @@ void free_particle_buffers(mpm_ctx* c) {
     (void)hipFree(c->B.gstart);
     (void)hipFree(c->B.gcode);
     (void)hipFree(c->B.chunks);
-    (void)hipFree(c->B.gchunk);
+    (void)hipFree(c->B.group_start);
     (void)hipFree(c->B.sorted_ids);
     (void)hipFree(c->G.stage);
     (void)hipFree(c->G.box);
-    c->B.gchunk = c->B.sorted_ids = nullptr;
+    c->B.group_start = c->B.sorted_ids = nullptr;
     c->G.stage = nullptr;
     c->G.box = nullptr;
     c->B.hist = c->B.scan_tiles = c->B.gstart = nullptr;
@@ -238,7 +238,7 @@ int grow(mpm_ctx* c, int64_t newcap) {
     int *hist = nullptr, *tiles = nullptr, *gstart = nullptr;
     uint32_t* gcode = nullptr;
     Chunk* chunks = nullptr;
-    int *gchunk = nullptr, *sorted_ids = nullptr;
+    int *group_start = nullptr, *sorted_ids = nullptr;
     float4* stage = nullptr;
     int4* box = nullptr;
     const int64_t rs_tiles = (newcap + 4095) / 4096;
@@ -258,7 +258,7 @@ int grow(mpm_ctx* c, int64_t newcap) {
     ok = ok && hipMalloc(&gstart, sizeof(int) * (newcap + 1)) == hipSuccess;
     ok = ok && hipMalloc(&gcode, sizeof(uint32_t) * (newcap + 1)) == hipSuccess;
     ok = ok && hipMalloc(&chunks, sizeof(Chunk) * (newcap + 1)) == hipSuccess;
-    ok = ok && hipMalloc(&gchunk, sizeof(int) * (newcap + 2)) == hipSuccess;
+    ok = ok && hipMalloc(&group_start, sizeof(int) * (newcap + 2)) == hipSuccess;
     ok = ok && hipMalloc(&sorted_ids, sizeof(int) * newcap) == hipSuccess;
     ok = ok && hipMalloc(&stage, sizeof(float4) * stage_nodes) == hipSuccess;
     ok = ok && hipMalloc(&box, sizeof(int4) * (newcap + 1)) == hipSuccess;
@@ -274,7 +274,7 @@ int grow(mpm_ctx* c, int64_t newcap) {
         (void)hipFree(gstart);
         (void)hipFree(gcode);
         (void)hipFree(chunks);
-        (void)hipFree(gchunk);
+        (void)hipFree(group_start);
         (void)hipFree(sorted_ids);
         (void)hipFree(stage);
         (void)hipFree(box);
@@ -300,7 +300,7 @@ int grow(mpm_ctx* c, int64_t newcap) {
     c->B.gstart = gstart;
     c->B.gcode = gcode;
     c->B.chunks = chunks;
-    c->B.gchunk = gchunk;
+    c->B.group_start = group_start;
     c->B.sorted_ids = sorted_ids;
     c->G.stage = stage;
     c->G.stage_nodes = (int)stage_nodes;
@@ -639,7 +639,8 @@ int mpm_create(const mpm_config* cfg, mpm_ctx** out) {
               hipMalloc(&c->G.ovf[1], sizeof(int) * nb) == hipSuccess &&
               hipMalloc(&c->B.brick_state, sizeof(int) * nb) == hipSuccess &&
               hipMalloc(&c->B.active, sizeof(int) * nb) == hipSuccess &&
-              hipMalloc(&c->B.gindex, sizeof(int) * nb) == hipSuccess &&
+              hipMalloc(&c->G.reg_n, sizeof(int) * nb) == hipSuccess &&
+              hipMalloc(&c->G.reg, sizeof(int) * REG_MAX * nb) == hipSuccess &&
               hipMalloc(&c->ctl, sizeof(int) * CTL_ALLOC_WORDS) == hipSuccess &&
               hipMalloc(&c->scene_dev, sizeof(Scene) * S) == hipSuccess &&
               hipMalloc(&c->rank_scene_dev, sizeof(int) * S) == hipSuccess &&
@@ -654,6 +655,7 @@ int mpm_create(const mpm_config* cfg, mpm_ctx** out) {
         hipMemsetAsync(c->G.vel, 0, sizeof(float4) * 64 * nb, c->stream) != hipSuccess ||
         hipMemsetAsync(c->G.stamp, 0xff, sizeof(int) * nb, c->stream) != hipSuccess ||
         hipMemsetAsync(c->B.brick_state, 0, sizeof(int) * nb, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->G.reg_n, 0, sizeof(int) * nb, c->stream) != hipSuccess ||
         hipMemsetAsync(c->ctl, 0, sizeof(int) * CTL_ALLOC_WORDS, c->stream) != hipSuccess ||
         hipMemsetAsync(c->rank_end_dev, 0, sizeof(int) * 4 * S, c->stream) != hipSuccess ||
         hipMemcpyAsync(c->scene_dev, c->table.data(), sizeof(Scene) * S, hipMemcpyHostToDevice, c->stream) !=
@@ -698,7 +700,8 @@ int mpm_destroy(mpm_ctx* c) {
     (void)hipFree(c->G.ovf[1]);
     (void)hipFree(c->B.brick_state);
     (void)hipFree(c->B.active);
-    (void)hipFree(c->B.gindex);
+    (void)hipFree(c->G.reg_n);
+    (void)hipFree(c->G.reg);
     (void)hipFree(c->ctl);
     (void)hipFree(c->scene_dev);
     (void)hipFree(c->rank_scene_dev);

@@ -69,7 +69,7 @@ __global__ __launch_bounds__(WG) void k_keys(const float* __restrict__ S, int64_
                                              int* __restrict__ ctl) {
     const int j = blockIdx.x * WG + threadIdx.x;
     if (j >= N) return;
-    const Scene& sc = T.scene[__float_as_int(S[FSID * cap + j])];
+    const Scene& sc = T.scene[fsid_scene(S[FSID * cap + j])];
     const float fn = sc.P.fn;
     const int n = sc.P.n;
     uint32_t code = (uint32_t)sc.rank << T.shift;
@@ -232,39 +232,77 @@ struct OpGBlocks {
     }
 };
 
-// Work chunks: each geometric block split into runs of at most `chunk`.
+// Merge groups: runs of geometric blocks of one 2x2x1 slab of blocks (equal
+// code >> 2; the rank bits make groups never cross scenes).
+struct OpGroups {
+    const uint32_t* gcode;
+    int* group_start;
+    const int* ctl;
+    __device__ int count(int g) const {
+        if (g >= ctl[CTL_NGB]) return 0;
+        return (g == 0 || (gcode[g] >> 2) != (gcode[g - 1] >> 2)) ? 1 : 0;
+    }
+    __device__ void emit(int g, int off, int) const { group_start[off] = g; }
+};
+
+// Work chunks, per merge group: consecutive blocks are packed into one chunk
+// while the total stays within `chunk` particles; a block larger than that
+// is cut into runs of `chunk`.  (Sparse regions then still fill the
+// workgroups; a chunk's tile box stays within a 2x2x1 slab of blocks.)
 struct OpChunks {
     const int* gstart;
     const uint32_t* gcode;
+    const int* group_start;
     const int* ctl;
     int N, chunk;
     Chunk* out;
-    int* gchunk;
     Scenes T;
     __device__ int len(int g) const {
         const int ng = ctl[CTL_NGB];
         const int end = (g + 1 < ng) ? gstart[g + 1] : N;
         return end - gstart[g];
     }
-    __device__ int count(int g) const {
-        if (g >= ctl[CTL_NGB]) return 0;
-        return (len(g) + chunk - 1) / chunk;
-    }
-    __device__ void emit(int g, int off, int k) const {
-        const int bshift = T.shift - 6;
-        const uint32_t code = gcode[g] & ((1u << bshift) - 1u);
-        const int scene = T.rank_scene[gcode[g] >> bshift];
-        const int packed = (int)(compact3(code) | (compact3(code >> 1) << 10) | (compact3(code >> 2) << 20));
-        const int s0 = gstart[g], l = len(g);
-        gchunk[g] = off;
-        for (int i = 0; i < k; ++i) {
-            Chunk c;
-            c.start = s0 + i * chunk;
-            c.count = min(chunk, l - i * chunk);
-            c.block = packed;
-            c.scene = scene;
-            out[off + i] = c;
+    __device__ int group_end(int s) const { return s + 1 < ctl[CTL_NGROUP] ? group_start[s + 1] : ctl[CTL_NGB]; }
+    // walk the group's blocks, calling put(start, count, first block) for each chunk
+    template <class Put>
+    __device__ int walk(int s, Put put) const {
+        int k = 0, run0 = -1, runn = 0, runb = 0;
+        for (int g = group_start[s]; g < group_end(s); ++g) {
+            const int l = len(g);
+            if (l > chunk) {
+                if (runn) put(k++, run0, runn, runb);
+                runn = 0;
+                for (int i = 0; i < l; i += chunk) put(k++, gstart[g] + i, min(chunk, l - i), g);
+            } else {
+                if (runn && runn + l > chunk) {
+                    put(k++, run0, runn, runb);
+                    runn = 0;
+                }
+                if (!runn) {
+                    run0 = gstart[g];
+                    runb = g;
+                }
+                runn += l;
+            }
         }
+        if (runn) put(k++, run0, runn, runb);
+        return k;
+    }
+    __device__ int count(int s) const {
+        if (s >= ctl[CTL_NGROUP]) return 0;
+        return walk(s, [](int, int, int, int) {});
+    }
+    __device__ void emit(int s, int off, int) const {
+        const int bshift = T.shift - 6;
+        walk(s, [&](int k, int start, int n, int g) {
+            const uint32_t code = gcode[g] & ((1u << bshift) - 1u);
+            Chunk c;
+            c.start = start;
+            c.count = n;
+            c.block = (int)(compact3(code) | (compact3(code >> 1) << 10) | (compact3(code >> 2) << 20));
+            c.scene = T.rank_scene[gcode[g] >> bshift];
+            out[off + k] = c;
+        });
     }
 };
 
@@ -277,54 +315,66 @@ struct OpActive {
 
 // ------------------------------------------------------------ data movement
 // Gather the whole particle state into sorted order, one chunk per
-// workgroup.  Inside a chunk (a sorted run of one block, so its particles are
-// grouped by cell in cell-code order) the storage order is by rounds: the
-// first particle of every cell in cell order, then the second particle of
-// every cell that has two, and so on (unless `spread` is 0: plain sorted
-// order).  A wave then holds about one particle per cell, and the 16 lanes
-// an LDS access serves together hold a 4x2x2 patch of cells.  Also records
-// the insertion ids in plain sorted order for the binning view.
+// workgroup.  A chunk holds one to four blocks (segments of its sorted run;
+// inside a segment particles are grouped by cell in cell-code order), and
+// each segment is stored by rounds: the first particle of every cell in cell
+// order, then the second particle of every cell that has two, and so on
+// (unless `spread` is 0: plain sorted order).  A wave then holds about one
+// particle per cell, and the 16 lanes an LDS access serves together hold a
+// 4x2x2 patch of cells.  Each particle's field FSID gets its block (its free
+// zone).  Also records the insertion ids in plain sorted order for the
+// binning view.
 __global__ __launch_bounds__(WG) void k_permute_chunks(const float* __restrict__ Sin, float* __restrict__ Sout,
                                                        const int* __restrict__ idin, int* __restrict__ idout,
                                                        int* __restrict__ sorted_ids, const uint32_t* __restrict__ src,
                                                        const uint32_t* __restrict__ keys,
                                                        const Chunk* __restrict__ chunks, const int* __restrict__ ctl,
-                                                       int64_t cap, int spread) {
-    __shared__ int cnt[64], first[64];
+                                                       int64_t cap, int spread, int shift) {
+    __shared__ int cnt[4][64], first[4][64], segfirst[4];
     const int nch = ctl[CTL_NCHUNK];
+    const uint32_t mmask = (1u << shift) - 1u;
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
         const Chunk ch = chunks[c];
         if (spread) {
-            if (threadIdx.x < 64) {
-                cnt[threadIdx.x] = 0;
-                first[threadIdx.x] = INT32_MAX;
+            for (int t = threadIdx.x; t < 4 * 64; t += WG) {
+                cnt[t >> 6][t & 63] = 0;
+                first[t >> 6][t & 63] = INT32_MAX;
             }
+            if (threadIdx.x < 4) segfirst[threadIdx.x] = INT32_MAX;
             __syncthreads();
             for (int t = threadIdx.x; t < ch.count; t += WG) {
-                const int cell = (int)(keys[ch.start + t] & 63u);
-                atomicAdd(&cnt[cell], 1);
-                atomicMin(&first[cell], t);
+                const uint32_t key = keys[ch.start + t];
+                const int seg = (int)((key >> 6) & 3u), cell = (int)(key & 63u);
+                atomicAdd(&cnt[seg][cell], 1);
+                atomicMin(&first[seg][cell], t);
+                atomicMin(&segfirst[seg], t);
             }
             __syncthreads();
         }
         for (int t = threadIdx.x; t < ch.count; t += WG) {
             const int j = ch.start + t;  // sorted position
+            const uint32_t key = keys[j];
             int slot = t;
             if (spread) {
-                const int cell = (int)(keys[j] & 63u);
-                const int r = t - first[cell];  // rank inside its cell
+                const int seg = (int)((key >> 6) & 3u), cell = (int)(key & 63u);
+                const int r = t - first[seg][cell];  // rank inside its cell
                 int before = 0, pos = 0;
                 for (int q = 0; q < 64; ++q) {
-                    const int n_q = cnt[q];
-                    before += min(n_q, r);               // particles of the earlier rounds
+                    const int n_q = cnt[seg][q];
+                    before += min(n_q, r);                 // the segment's particles of earlier rounds
                     pos += (q < cell && n_q > r) ? 1 : 0;  // cells ahead in this round
                 }
-                slot = before + pos;
+                slot = segfirst[seg] + before + pos;
             }
             const int k = (int)src[j];  // its position before the sort
             const int dst = ch.start + slot;
 #pragma unroll
-            for (int f = 0; f < NF; ++f) Sout[f * cap + dst] = Sin[f * cap + k];
+            for (int f = 0; f < FSID; ++f) Sout[f * cap + dst] = Sin[f * cap + k];
+            const uint32_t bcode = (key & mmask) >> 6;
+            const int scene = fsid_scene(Sin[FSID * cap + k]);
+            Sout[FSID * cap + dst] = __int_as_float(scene | (int)(compact3(bcode) << 8) |
+                                                    (int)(compact3(bcode >> 1) << 16) |
+                                                    (int)(compact3(bcode >> 2) << 24));
             const int id = idin[k];
             idout[dst] = id;
             sorted_ids[j] = id;
@@ -344,11 +394,10 @@ __global__ __launch_bounds__(WG) void k_fill(int* __restrict__ p, int v, int n) 
     if (i < n) p[i] = v;
 }
 
-// Mark the 3x3x3 neighbourhood of every geometric block as physical and
-// record each geometric block's index at its own (padded) position, in the
-// block grid of the block's scene.
+// Mark the 3x3x3 neighbourhood of every geometric block as physical, in
+// the block grid of the block's scene.
 __global__ __launch_bounds__(WG) void k_dilate(const uint32_t* __restrict__ gcode, const int* __restrict__ ctl,
-                                               Scenes T, int* __restrict__ state, int* __restrict__ gindex) {
+                                               Scenes T, int* __restrict__ state) {
     const int total = ctl[CTL_NGB] * 27;
     const int bshift = T.shift - 6;
     for (int t = blockIdx.x * WG + threadIdx.x; t < total; t += gridDim.x * WG) {
@@ -360,10 +409,16 @@ __global__ __launch_bounds__(WG) void k_dilate(const uint32_t* __restrict__ gcod
         const int bx = B0 + (o % 3);  // (B - 1) + o + 1 in padded coordinates
         const int by = B1 + (o / 3) % 3;
         const int bz = B2 + o / 9;
-        const int b = sc.brick_base + (bz * NB + by) * NB + bx;
-        state[b] = 1;
-        if (o == 13) gindex[b] = g;  // o = (1,1,1): the block itself
+        state[sc.brick_base + (bz * NB + by) * NB + bx] = 1;
     }
+}
+
+// After compaction a physical block's state names its position in the active
+// list (3 + i), where P2G registers the tiles that reach it.
+__global__ __launch_bounds__(WG) void k_mark_active(const int* __restrict__ active, const int* __restrict__ ctl,
+                                                    int* __restrict__ state) {
+    const int n = ctl[CTL_NACTIVE];
+    for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) state[active[i]] = 3 + i;
 }
 
 // Per-rank ends of the sorted particles, geometric blocks, chunks and
@@ -394,11 +449,10 @@ __global__ __launch_bounds__(WG) void k_rank_ends(const uint32_t* __restrict__ k
 }
 
 // The rebuild also starts the overflow lists and fallback counts afresh.
-__global__ void k_finish_rebuild(int* ctl, int* gchunk) {
+__global__ void k_finish_rebuild(int* ctl) {
     ctl[CTL_REBUILD] = 0;
     ctl[CTL_OVF] = ctl[CTL_OVF + 1] = 0;
     ctl[CTL_FB] = ctl[CTL_FB + 1] = 0;
-    gchunk[ctl[CTL_NGB]] = ctl[CTL_NCHUNK];
 }
 
 }  // namespace
@@ -427,17 +481,18 @@ void enqueue_rebuild(hipStream_t st, const Scenes& T, float* S_cur, float* S_alt
     B.sorted = cur;  // slot holding the sorted codes and their source positions
     // 3. geometric blocks and work chunks
     device_scan(st, OpGBlocks{B.keys[cur], N, B.gstart, B.gcode}, N, B.scan_tiles, ctl + CTL_NGB);
-    device_scan(st, OpChunks{B.gstart, B.gcode, ctl, N, chunk, B.chunks, B.gchunk, T}, N, B.scan_tiles,
+    device_scan(st, OpGroups{B.gcode, B.group_start, ctl}, N, B.scan_tiles, ctl + CTL_NGROUP);
+    device_scan(st, OpChunks{B.gstart, B.gcode, B.group_start, ctl, N, chunk, B.chunks, T}, N, B.scan_tiles,
                 ctl + CTL_NCHUNK);
     // 4. gather the whole particle state into (chunk-spread) sorted order
     hipLaunchKernelGGL(k_permute_chunks, dim3(2048), dim3(WG), 0, st, S_cur, S_alt, id_cur, id_alt, B.sorted_ids,
-                       B.vals[cur], B.keys[cur], B.chunks, ctl, cap, spread);
+                       B.vals[cur], B.keys[cur], B.chunks, ctl, cap, spread, T.shift);
     // 5. physical blocks: 3x3x3 dilation, compacted in padded linear order
     hipLaunchKernelGGL(k_fill, dim3(cdiv(nbricks, WG)), dim3(WG), 0, st, B.brick_state, 0, nbricks);
-    hipLaunchKernelGGL(k_fill, dim3(cdiv(nbricks, WG)), dim3(WG), 0, st, B.gindex, -1, nbricks);
-    hipLaunchKernelGGL(k_dilate, dim3(512), dim3(WG), 0, st, B.gcode, ctl, T, B.brick_state, B.gindex);
+    hipLaunchKernelGGL(k_dilate, dim3(512), dim3(WG), 0, st, B.gcode, ctl, T, B.brick_state);
     device_scan(st, OpActive{B.brick_state, B.active}, nbricks, B.scan_tiles, ctl + CTL_NACTIVE);
-    hipLaunchKernelGGL(k_finish_rebuild, dim3(1), dim3(1), 0, st, ctl, B.gchunk);
+    hipLaunchKernelGGL(k_mark_active, dim3(512), dim3(WG), 0, st, B.active, ctl, B.brick_state);
+    hipLaunchKernelGGL(k_finish_rebuild, dim3(1), dim3(1), 0, st, ctl);
     hipLaunchKernelGGL(k_rank_ends, dim3(1), dim3(WG), 0, st, B.keys[cur], N, B.gcode, B.chunks, B.active, ctl, T);
 }
 

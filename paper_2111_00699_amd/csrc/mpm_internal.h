@@ -11,9 +11,19 @@ namespace mpm {
 
 // ----------------------------------------------------------------- layout
 // Particle state: one FP32 array per scalar field, field f at S + f * cap.
-// FSID holds the particle's scene index as integer bits; it moves with the
-// particle through the rebuild permutation.
+// FSID holds integer bits: the particle's scene (bits 0-7) and the block it
+// was binned to at the last rebuild (x, y, z in bits 8-15, 16-23, 24-31),
+// which fixes its free zone; it moves with the particle through the rebuild
+// permutation.
 enum Field : int { FX = 0, FV = 3, FC = 6, FF = 15, FS = 24, FSID = 25, NF = 26 };
+
+__device__ __forceinline__ int fsid_scene(float f) { return __float_as_int(f) & 255; }
+__device__ __forceinline__ void fsid_block(float f, int B[3]) {
+    const uint32_t u = (uint32_t)__float_as_int(f);
+    B[0] = (int)((u >> 8) & 255u);
+    B[1] = (int)((u >> 16) & 255u);
+    B[2] = (int)(u >> 24);
+}
 
 constexpr int WG = 256;       // threads per workgroup (four wave64s)
 constexpr int TILE = 12;      // nodes per axis reachable from one particle block (3 blocks)
@@ -31,6 +41,7 @@ enum Ctl : int {
     CTL_SCAN = 8,      // scratch total of a device scan
     CTL_FB = 9,        // in-zone particles of chunks whose tile did not fit, two slots by substep parity
     CTL_STEP = 11,     // substeps completed (advanced by G2P; stamps the blocks the grid update touched)
+    CTL_NGROUP = 12,   // merge groups (2x2x1 block slabs) of the last rebuild
     CTL_WORDS = 16,
     // 64-bit running counters follow the 16 words (byte offset 64):
     CTL64_FALLBACK_CHUNKS = 0,     // P2G chunks whose node box did not fit the LDS tile
@@ -65,12 +76,17 @@ struct Step {
     int bc, bc_cells;
 };
 
-// A run of at most `chunk` sorted particles that share one particle block.
+// A run of at most `chunk` sorted particles: a piece of one particle block,
+// or several whole blocks of one 2x2x1 slab of blocks (sparse regions).
 struct Chunk {
     int start, count;
-    int block;  // packed block coordinates Bx | By << 10 | Bz << 20
+    int block;  // packed coordinates Bx | By << 10 | Bz << 20 of its first block
     int scene;
 };
+
+// Tile registrations per physical block: P2G lists each chunk whose tile
+// box reaches a block under that block's position in the active list.
+constexpr int REG_MAX = 256;
 
 // One scene of a context: its grid and time step, its material, where its
 // dense block grid starts in the shared brick space, and its rank (position
@@ -133,10 +149,9 @@ struct BinBuffers {
     int* gstart;       // [cap + 1]
     uint32_t* gcode;   // [cap]
     Chunk* chunks;     // [cap]
-    int* brick_state;  // [bricks] 0 idle, 1 physical block of the rebuild, 2 overflow this substep
+    int* brick_state;  // [bricks] 0 idle, 2 overflow this substep, 3 + i physical block at active[i]
     int* active;       // [bricks]
-    int* gindex;       // [bricks] geometric-block index of each particle block (padded coords), -1 if none
-    int* gchunk;       // [cap + 1] first chunk of each geometric block
+    int* group_start;  // [cap + 1] first geometric block of each merge group
     int* sorted_ids;   // [cap] insertion id of each particle in particle-code order
     int sorted;        // which keys/vals slot holds the last sorted codes (host side)
 };
@@ -159,6 +174,8 @@ struct GridBuffers {
     int4* box;      // [cap] per chunk: x = tile origin packed 10 bits/axis, y = extent packed 8 bits/axis
                     // (0 = no tile), z = offset of the tile in `stage` (nodes)
     int stage_nodes;
+    int* reg_n;     // [bricks] tiles registered with physical block i this substep (reset by the grid update)
+    int* reg;       // [bricks * REG_MAX] their chunk indices
 };
 
 struct Launch {

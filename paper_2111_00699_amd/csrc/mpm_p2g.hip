@@ -17,8 +17,9 @@
 //     (weight sum and three momentum components) accumulated with
 //     ds_add_f64;
 //   * the tile is then STORED (plain, coalesced float4 stores) to the
-//     staging buffer, and the grid update gathers each node from the tiles
-//     of the particle blocks around it -- no global atomics, and the
+//     staging buffer and registered with every physical block its box
+//     reaches; the grid update gathers each node from the tiles registered
+//     with its block -- no global atomics, and the
 //     transfer of in-zone particles is deterministic.  Each workgroup owns an
 //     equal slice of the staging buffer and packs its chunks' tiles there
 //     (offset recorded per chunk), so no allocation is shared.
@@ -41,12 +42,14 @@ namespace {
 constexpr int CT = 1024;  // LDS tile capacity in nodes (padded layout, below)
 
 // LDS tile layout of a box of ext0 x ext1 x ext2 nodes: node (x, y, z) at
-// x + R y + Q z with the row pitch R in {4, 12} (so R = 4 or 12 mod 16) and
-// the plane pitch Q = 8 (mod 16).  With the round-ordered chunks, the 16
-// lanes an LDS access serves together hold cells x in 0..3, y in {y, y+1},
-// z in {z, z+1}; their FP64 addresses x + R y' + Q z' then fall on 16
-// different bank pairs for every stencil offset.
-__device__ __forceinline__ int pitch_row(int e0) { return e0 <= 4 ? 4 : 12; }
+// x + R y + Q z with the row pitch R the smallest of 4, 12, 20, 28, ... that
+// holds a row (so R >= ext0 and R = 4 or 12 mod 16) and the plane pitch
+// Q = 8 (mod 16).  With the round-ordered chunks, the 16 lanes an LDS access
+// serves together hold cells x in 0..3, y in {y, y+1}, z in {z, z+1}; their
+// FP64 addresses x + R y' + Q z' then fall on 16 different bank pairs for
+// every stencil offset.  (A chunk of several blocks has a box up to 16 nodes
+// wide.)
+__device__ __forceinline__ int pitch_row(int e0) { return e0 <= 4 ? 4 : ((e0 + 3) & ~7) + 4; }
 __device__ __forceinline__ int pitch_plane(int R, int e1) {
     const int q = R * e1;
     return q + ((8 - (q & 15)) & 15);
@@ -235,10 +238,12 @@ template <bool GLOBAL_ONLY, int NT, int SURM>
 __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, const Chunk* __restrict__ chunks,
                                             int* __restrict__ ctl, float* __restrict__ acc,
                                             float4* __restrict__ stage, int stage_nodes, int4* __restrict__ box,
-                                            int* __restrict__ brick_state, int* __restrict__ ovf, int parity,
+                                            int* __restrict__ brick_state, int* __restrict__ reg_n,
+                                            int* __restrict__ reg, int* __restrict__ ovf, int parity,
                                             Scenes T, int pending, int nbricks, int act) {
     __shared__ double tq[GLOBAL_ONLY ? 1 : 4 * CT];
     __shared__ int red_i[6][NT / 64];
+    __shared__ int reg_fail;
     struct Empty {};
     __shared__ typename std::conditional<SURM == 2, mlp::NetLds16, Empty>::type net;
     __shared__ float sur_stage[SURM == 2 ? NT / 64 * 512 : 1];
@@ -262,7 +267,6 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
         const Mat M = sc.M;
         const float dx = P.dx, dt = P.dt;
         const int count = ch.count;
-        const int B[3] = {ch.block & 1023, (ch.block >> 10) & 1023, ch.block >> 20};
         const bool have = tid < count;
         const int p = ch.start + (have ? tid : 0);
 
@@ -290,6 +294,8 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
                 for (int k = 0; k < 9; ++k) F[k] = S[(FF + k) * cap + p];
             }
         }
+        int B[3] = {0, 0, 0};  // the particle's block at the last rebuild (its free zone)
+        if (have) fsid_block(S[FSID * cap + p], B);
         bool sur_chunk = false;
         if constexpr (SURM != 0) {
             sur_chunk = sc.ret != 0 && M.kind == MPM_SNOW;  // uniform over the workgroup
@@ -379,13 +385,41 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
             }
             // no room in the tile or in this workgroup's staging slice: the chunk goes to global atomics
             if (Q * ext[2] > CT || used + nt > slice) nt = -1;
+            // register the tile with every physical block its box reaches (the grid update's
+            // gather list); a full list sends the chunk to global atomics instead.  Blocks of
+            // the box that are not physical are skipped: every in-zone stencil lies in the
+            // 3x3x3 neighbourhood of its particle's block, all physical, so the tile holds
+            // zeros there (a bounding box of several blocks' stencils can reach past them).
+            if (tid == 0) reg_fail = 0;
+            __syncthreads();
+            if (nt > 0) {
+                int b0[3], nb[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    b0[a] = (lo[a] >> 2) + 1;  // padded block coordinates
+                    nb[a] = ((lo[a] + ext[a] - 1) >> 2) + 1 - b0[a] + 1;
+                }
+                for (int k = tid; k < nb[0] * nb[1] * nb[2]; k += NT) {
+                    const int bx = b0[0] + k % nb[0], by = b0[1] + (k / nb[0]) % nb[1], bz = b0[2] + k / (nb[0] * nb[1]);
+                    const int state = brick_state[sc.brick_base + (bz * P.NB + by) * P.NB + bx];
+                    if (state >= 3) {
+                        const int slot = atomicAdd(&reg_n[state - 3], 1);
+                        if (slot < REG_MAX)
+                            reg[(int64_t)(state - 3) * REG_MAX + slot] = c;
+                        else
+                            reg_fail = 1;
+                    }
+                }
+            }
+            __syncthreads();
+            if (reg_fail) nt = -1;
             if (nt < 0 && tid == 0) atomicAdd(&ctl64(ctl)[CTL64_FALLBACK_CHUNKS], 1ull);
             off = slice0 + used;
             if (nt > 0) used += nt;
             const int e01 = ext[0] * ext[1];
             for (int u = tid; u < nt; u += NT) {  // clear the box's nodes at their padded addresses
-                const int z = u / e01, y = (u - z * e01) / ext[0], x = u - z * e01 - y * ext[0];
-                const int t = x + R * y + Q * z;
+                const int z = u / e01, y = (u - z * e01) / ext[0], xx = u - z * e01 - y * ext[0];
+                const int t = xx + R * y + Q * z;
 #pragma unroll
                 for (int ch4 = 0; ch4 < 4; ++ch4) tq[ch4 * CT + t] = 0.0;
             }
@@ -467,8 +501,8 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
             float4* slot = stage + off;
             const int e01 = ext[0] * ext[1];
             for (int u = tid; u < nt; u += NT) {  // staged in the tight box layout
-                const int z = u / e01, y = (u - z * e01) / ext[0], x = u - z * e01 - y * ext[0];
-                const int t = x + R * y + Q * z;
+                const int z = u / e01, y = (u - z * e01) / ext[0], xx = u - z * e01 - y * ext[0];
+                const int t = xx + R * y + Q * z;
                 slot[u] = make_float4((float)(tq[t] * (double)M.mp), (float)tq[CT + t], (float)tq[2 * CT + t],
                                       (float)tq[3 * CT + t]);
             }
@@ -502,7 +536,8 @@ void enqueue_p2g(hipStream_t st, const Launch& L, const Scenes& T, float* S, int
                  int nbricks, int chunk, int act) {
 #define MPM_LAUNCH_P2G(GO, NT, SU)                                                                              \
     hipLaunchKernelGGL((k_p2g<GO, NT, SU>), dim3(L.p2g_grid), dim3(NT), 0, st, S, cap, chunks, ctl, G.acc,        \
-                       G.stage, G.stage_nodes, G.box, brick_state, G.ovf[parity], parity, T, pending, nbricks, act)
+                       G.stage, G.stage_nodes, G.box, brick_state, G.reg_n, G.reg, G.ovf[parity], parity, T, pending,   \
+                       nbricks, act)
 #define MPM_LAUNCH_P2G_NT(GO, SU)                        \
     do {                                                 \
         if (nt == 128)                                   \

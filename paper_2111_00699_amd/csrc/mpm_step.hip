@@ -28,15 +28,15 @@ namespace {
 
 // ----------------------------------------------------------- grid update
 // One wave64 per 4^3 block.  Each node sums the global-path accumulator and
-// the staged P2G tiles of the particle blocks whose 3x3x3 neighbourhood
-// holds it (padded block coordinates b-1..b+1 per axis), then
+// the staged P2G tiles registered with its block this substep (P2G lists
+// every chunk whose tile box reaches a physical block), then
 // v = p/m + dt g where m > 0 (else 0) and the wall condition; writes (v, m),
-// clears the accumulator, and stamps the block.
+// clears the accumulator and the registrations, and stamps the block.
 __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, float4* __restrict__ vel,
                                              const int* __restrict__ active, int* __restrict__ ctl,
                                              const int* __restrict__ ovf, int* __restrict__ brick_state,
-                                             int* __restrict__ stamp, const int* __restrict__ gindex,
-                                             const int* __restrict__ gchunk, const float4* __restrict__ stage,
+                                             int* __restrict__ stamp, int* __restrict__ reg_n,
+                                             const int* __restrict__ reg, const float4* __restrict__ stage,
                                              const int4* __restrict__ box, int parity, int nbricks, Scenes T,
                                              int act) {
     const int nact = rank_limit(T, ctl, act, RE_ACTIVE, CTL_NACTIVE);
@@ -46,7 +46,6 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, float4* __
     const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
     const int nwaves = gridDim.x * (WG / 64);
     float4* acc4 = reinterpret_cast<float4*>(acc);
-    __shared__ int cand[WG / 64][64];
     for (int it = blockIdx.x * (WG / 64) + (threadIdx.x >> 6); it < total; it += nwaves) {
         const int b = __builtin_amdgcn_readfirstlane(it < nact ? active[it] : ovf[it - nact]);
         const Scene& sc = T.scene[T.rank_scene[rank_of_brick(T, b)]];
@@ -56,62 +55,34 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, float4* __
         const int bx = lb % NB, by = (lb / NB) % NB, bz = lb / (NB * NB);
         const int n0 = 4 * (bx - 1), n1 = 4 * (by - 1), n2 = 4 * (bz - 1);  // first node of the block
         const int g[3] = {n0 + lx, n1 + ly, n2 + lz};
-        float4 a = acc4[b * 64 + lane];
-        // Lane k < 27 looks up the chunk range of candidate particle block k
-        // (padded offsets -1..1 per axis); the ranges are laid out in LDS as
-        // this wave's candidate list, then every lane sums the staged tile
-        // values that cover its node.
-        int n_k = 0, c0_k = 0;
-        if (lane < 27) {
-            const int px = bx + lane % 3 - 1, py = by + (lane / 3) % 3 - 1, pz = bz + lane / 9 - 1;
-            if (px >= 0 && px < NB && py >= 0 && py < NB && pz >= 0 && pz < NB) {
-                const int gb = gindex[base + (pz * NB + py) * NB + px];
-                if (gb >= 0) {
-                    c0_k = gchunk[gb];
-                    n_k = gchunk[gb + 1] - c0_k;
+        float4 a = acc4[(int64_t)b * 64 + lane];
+        if (it < nact) {  // a physical block: gather the tiles registered with it (at most REG_MAX)
+            const int m = min(__builtin_amdgcn_readfirstlane(reg_n[it]), REG_MAX);
+            for (int rb = 0; rb < m; rb += 64) {  // 64 registrations a round, one per lane
+                int4 bb = make_int4(0, 0, 0, 0);
+                bool ov = false;  // does tile `lane` still exist and reach into this block?
+                if (rb + lane < m) {
+                    bb = box[reg[(int64_t)it * REG_MAX + rb + lane]];
+                    const int e0 = bb.y & 255, e1 = (bb.y >> 8) & 255, e2 = bb.y >> 16;
+                    const int l0 = bb.x & 1023, l1 = (bb.x >> 10) & 1023, l2 = bb.x >> 20;
+                    ov = e0 > 0 && l0 <= n0 + 3 && l0 + e0 > n0 && l1 <= n1 + 3 && l1 + e1 > n1 &&
+                         l2 <= n2 + 3 && l2 + e2 > n2;
+                }
+                for (uint64_t mask = __ballot(ov); mask; mask &= mask - 1) {
+                    const int i = __builtin_ctzll(mask);
+                    const int bx_ = __shfl(bb.x, i, 64), by_ = __shfl(bb.y, i, 64), s_ = __shfl(bb.z, i, 64);
+                    const int e0 = by_ & 255, e1 = (by_ >> 8) & 255, e2 = by_ >> 16;
+                    const int r0 = g[0] - (bx_ & 1023), r1 = g[1] - ((bx_ >> 10) & 1023), r2 = g[2] - (bx_ >> 20);
+                    if (r0 >= 0 && r0 < e0 && r1 >= 0 && r1 < e1 && r2 >= 0 && r2 < e2) {
+                        const float4 sv = stage[s_ + r0 + e0 * (r1 + e1 * r2)];
+                        a.x += sv.x;
+                        a.y += sv.y;
+                        a.z += sv.z;
+                        a.w += sv.w;
+                    }
                 }
             }
-        }
-        int incl = n_k;
-#pragma unroll
-        for (int d = 1; d < 32; d <<= 1) {
-            const int t = __shfl_up(incl, d, 64);
-            if (lane >= d) incl += t;
-        }
-        const int total_c = __shfl(incl, 26, 64);
-        int* list = cand[threadIdx.x >> 6];
-        for (int base = 0; base < total_c; base += 64) {
-            // lanes k < 27 write the part of their range that falls in [base, base + 64)
-            for (int i = 0; i < n_k; ++i) {
-                const int slot = incl - n_k + i - base;
-                if (slot >= 0 && slot < 64) list[slot] = c0_k + i;
-            }
-            __builtin_amdgcn_wave_barrier();
-            const int m = min(64, total_c - base);
-            int4 bb = make_int4(0, 0, 0, 0);
-            bool ov = false;  // does candidate `lane`'s tile box reach into this block?
-            if (lane < m) {
-                bb = box[list[lane]];
-                const int e0 = bb.y & 255, e1 = (bb.y >> 8) & 255, e2 = bb.y >> 16;
-                const int l0 = bb.x & 1023, l1 = (bb.x >> 10) & 1023, l2 = bb.x >> 20;
-                ov = e0 > 0 && l0 <= n0 + 3 && l0 + e0 > n0 && l1 <= n1 + 3 && l1 + e1 > n1 && l2 <= n2 + 3 &&
-                     l2 + e2 > n2;
-            }
-            __builtin_amdgcn_wave_barrier();
-            // only the overlapping candidates are visited (the mask is the same in every lane)
-            for (uint64_t mask = __ballot(ov); mask; mask &= mask - 1) {
-                const int i = __builtin_ctzll(mask);
-                const int bx_ = __shfl(bb.x, i, 64), by_ = __shfl(bb.y, i, 64), s_ = __shfl(bb.z, i, 64);
-                const int e0 = by_ & 255, e1 = (by_ >> 8) & 255, e2 = by_ >> 16;
-                const int r0 = g[0] - (bx_ & 1023), r1 = g[1] - ((bx_ >> 10) & 1023), r2 = g[2] - (bx_ >> 20);
-                if (r0 >= 0 && r0 < e0 && r1 >= 0 && r1 < e1 && r2 >= 0 && r2 < e2) {
-                    const float4 sv = stage[s_ + r0 + e0 * (r1 + e1 * r2)];
-                    a.x += sv.x;
-                    a.y += sv.y;
-                    a.z += sv.z;
-                    a.w += sv.w;
-                }
-            }
+            if (lane == 0) reg_n[it] = 0;  // ready for the next substep
         }
         float v[3] = {0.0f, 0.0f, 0.0f};
         if (a.x > 0.0f) {
@@ -143,8 +114,8 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, float4* __
                 }
             }
         }
-        vel[b * 64 + lane] = make_float4(v[0], v[1], v[2], a.x);
-        acc4[b * 64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+        vel[(int64_t)b * 64 + lane] = make_float4(v[0], v[1], v[2], a.x);
+        acc4[(int64_t)b * 64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (lane == 0) {
             stamp[b] = step;
             if (it >= nact) brick_state[b] = 0;
@@ -183,7 +154,6 @@ __global__ __launch_bounds__(NT) void k_g2p(float* __restrict__ S, int64_t cap, 
         const float c4 = 4.0f * P.fn;  // (4/dx^2) * dx
         const int NB = P.NB;
         const float4* vels = vel + (int64_t)sc.brick_base * BLOCK_NODES;
-        const int B[3] = {ch.block & 1023, (ch.block >> 10) & 1023, ch.block >> 20};
         int lo[3] = {0, 0, 0}, e[3] = {0, 0, 0}, nt = 0;
         if (LDS_BOX) {
             const int4 bb = box[c];
@@ -207,6 +177,8 @@ __global__ __launch_bounds__(NT) void k_g2p(float* __restrict__ S, int64_t cap, 
             float x[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) x[a] = S[(FX + a) * cap + p];
+            int B[3];  // the particle's block at the last rebuild (its free zone)
+            fsid_block(S[FSID * cap + p], B);
             Stencil st;
             if (!make_stencil(x, P, st, err)) continue;
             int r[3];
@@ -303,7 +275,7 @@ __global__ __launch_bounds__(NT) void k_g2p(float* __restrict__ S, int64_t cap, 
 __global__ __launch_bounds__(WG) void k_materialize(float* __restrict__ S, int64_t cap, int N, Scenes T) {
     const int p = blockIdx.x * WG + threadIdx.x;
     if (p >= N) return;
-    const Scene& sc = T.scene[__float_as_int(S[FSID * cap + p])];
+    const Scene& sc = T.scene[fsid_scene(S[FSID * cap + p])];
     float C[9], F[9], s, tau[6];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
@@ -353,7 +325,7 @@ __global__ __launch_bounds__(WG) void k_read(const float* __restrict__ S, const 
                                              float* __restrict__ v, float* __restrict__ C, float* __restrict__ F,
                                              float* __restrict__ s) {
     const int j = blockIdx.x * WG + threadIdx.x;
-    if (j >= N || __float_as_int(S[FSID * cap + j]) != scene) return;
+    if (j >= N || fsid_scene(S[FSID * cap + j]) != scene) return;
     const Scene& sc = T.scene[scene];
     const int64_t id = ids[j];
 #pragma unroll
@@ -448,7 +420,7 @@ void query_launch(Launch& L, int chunk) {
 void enqueue_grid(hipStream_t st, const Launch& L, const Scenes& T, const BinBuffers& B, int* ctl, GridBuffers& G,
                   int parity, int nbricks, int act) {
     hipLaunchKernelGGL(k_grid, dim3(L.grid_grid), dim3(WG), 0, st, G.acc, G.vel, B.active, ctl, G.ovf[parity],
-                       B.brick_state, G.stamp, B.gindex, B.gchunk, G.stage, G.box, parity, nbricks, T, act);
+                       B.brick_state, G.stamp, G.reg_n, G.reg, G.stage, G.box, parity, nbricks, T, act);
 }
 
 void enqueue_g2p(hipStream_t st, const Launch& L, const Scenes& T, float* S, int64_t cap, const Chunk* chunks,

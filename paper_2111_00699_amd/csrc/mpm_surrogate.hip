@@ -301,7 +301,7 @@ __global__ __launch_bounds__(SW) void k_sur_sample(const float* __restrict__ S, 
                                                    float* __restrict__ X, float* __restrict__ Y,
                                                    unsigned long long* __restrict__ counter) {
     const int j = blockIdx.x * SW + threadIdx.x;
-    if (j >= N || __float_as_int(S[FSID * cap + j]) != scene) return;
+    if (j >= N || fsid_scene(S[FSID * cap + j]) != scene) return;
     const Scene& sc = T.scene[scene];
     const Mat& M = sc.M;
     float C[9], F[9], Fh[9];

@@ -107,14 +107,49 @@ def round_order(cells):
     return np.lexsort((cells, rank))
 
 
-def storage_order(perm, keys, gstart, gcount, chunk=256):
-    """Insertion ids in storage order after a rebuild: geometric blocks are cut
-    into chunks of `chunk`, and each chunk is stored by cell rounds."""
+def chunk_runs(gcode, gstart, gcount, chunk=256):
+    """Chunks as (start, count): consecutive blocks of one 2x2x1 slab of blocks
+    (equal code >> 2) are packed while they fit in `chunk` particles, larger
+    blocks are cut into runs of `chunk` (the layout include/mpm.h documents)."""
+    runs, g = [], 0
+    gcode, gstart, gcount = list(map(int, gcode)), list(map(int, gstart)), list(map(int, gcount))
+    while g < len(gcode):
+        h = g
+        while h < len(gcode) and gcode[h] >> 2 == gcode[g] >> 2:
+            h += 1
+        run0, runn = None, 0
+        for b in range(g, h):
+            n = gcount[b]
+            if n > chunk:
+                if runn:
+                    runs.append((run0, runn))
+                runn = 0
+                runs += [(gstart[b] + i, min(chunk, n - i)) for i in range(0, n, chunk)]
+            else:
+                if runn and runn + n > chunk:
+                    runs.append((run0, runn))
+                    runn = 0
+                if not runn:
+                    run0 = gstart[b]
+                runn += n
+        if runn:
+            runs.append((run0, runn))
+        g = h
+    return runs
+
+
+def storage_order(perm, keys, gcode, gstart, gcount, chunk=256):
+    """Insertion ids in storage order after a rebuild: each chunk's blocks are
+    stored one after another, each by cell rounds."""
     order = np.empty_like(perm)
-    for s0, cnt in zip(gstart.tolist(), gcount.tolist()):
-        for k in range(0, cnt, chunk):
-            c0, cc = s0 + k, min(chunk, cnt - k)
-            order[c0:c0 + cc] = perm[c0 + round_order(keys[c0:c0 + cc] & 63)]
+    for c0, cc in chunk_runs(gcode, gstart, gcount, chunk):
+        blocks = (keys[c0:c0 + cc] >> 6).astype(np.int64)
+        seg0 = 0
+        for blk in np.unique(blocks):
+            n = int(np.sum(blocks == blk))
+            s = c0 + seg0
+            order[s:s + n] = perm[s + round_order(keys[s:s + n] & 63)]
+            seg0 += n
     return order
 
 
@@ -134,7 +169,7 @@ def test_binning_after_motion_composes(torch_cuda, oracle):
     sim.substep(1)
     keys1, perm1 = sim.read_binning()
     # oracle: positions in the storage order left by the first rebuild, then a stable sort
-    order0 = storage_order(perm0, keys0, b0["gstart"], b0["gcount"])
+    order0 = storage_order(perm0, keys0, b0["gcode"], b0["gstart"], b0["gcount"])
     assert np.array_equal(np.sort(order0), np.arange(order0.size))
     xs = x_now[:, order0]
     k, _, _ = oracle.keys(xs, 64)
@@ -267,7 +302,8 @@ def test_out_of_free_zone_without_rebuild(torch_cuda, oracle):
     gs = gpu_state(sim)
     os_, _, _, bad = oracle.substep(cfg, mat, st, steps=40)
     assert bad == 0
-    compare_state(gs, os_, "jelly", tol=2e-4)
+    # a translating cube: C is small against n |v|, the scale of its FP32 cancellation noise
+    compare_state(gs, os_, "jelly", tol=2e-4, n=cfg["n"])
     sim.close()
 
 
@@ -292,7 +328,7 @@ def test_expanding_cloud_overflows_tiles(torch_cuda, oracle):
     gs = gpu_state(sim)
     os_, _, _, bad = oracle.substep(cfg, mat, st, steps=30)
     assert bad == 0
-    compare_state(gs, os_, "jelly", tol=2e-4)
+    compare_state(gs, os_, "jelly", tol=2e-4, n=cfg["n"])
     sim.close()
 
 
