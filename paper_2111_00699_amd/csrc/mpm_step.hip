@@ -68,17 +68,30 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, float4* __
                     ov = e0 > 0 && l0 <= n0 + 3 && l0 + e0 > n0 && l1 <= n1 + 3 && l1 + e1 > n1 &&
                          l2 <= n2 + 3 && l2 + e2 > n2;
                 }
-                for (uint64_t mask = __ballot(ov); mask; mask &= mask - 1) {
-                    const int i = __builtin_ctzll(mask);
-                    const int bx_ = __shfl(bb.x, i, 64), by_ = __shfl(bb.y, i, 64), s_ = __shfl(bb.z, i, 64);
-                    const int e0 = by_ & 255, e1 = (by_ >> 8) & 255, e2 = by_ >> 16;
-                    const int r0 = g[0] - (bx_ & 1023), r1 = g[1] - ((bx_ >> 10) & 1023), r2 = g[2] - (bx_ >> 20);
-                    if (r0 >= 0 && r0 < e0 && r1 >= 0 && r1 < e1 && r2 >= 0 && r2 < e2) {
-                        const float4 sv = stage[s_ + r0 + e0 * (r1 + e1 * r2)];
-                        a.x += sv.x;
-                        a.y += sv.y;
-                        a.z += sv.z;
-                        a.w += sv.w;
+                // the overlapping tiles in registration order, eight loads in flight at a time
+                // (summed in the same order as one at a time)
+                for (uint64_t mask = __ballot(ov); mask;) {
+                    float4 sv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        sv[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+                        if (mask) {  // wave-uniform
+                            const int i = __builtin_ctzll(mask);
+                            mask &= mask - 1;
+                            const int bx_ = __shfl(bb.x, i, 64), by_ = __shfl(bb.y, i, 64), s_ = __shfl(bb.z, i, 64);
+                            const int e0 = by_ & 255, e1 = (by_ >> 8) & 255, e2 = by_ >> 16;
+                            const int r0 = g[0] - (bx_ & 1023), r1 = g[1] - ((bx_ >> 10) & 1023),
+                                      r2 = g[2] - (bx_ >> 20);
+                            if (r0 >= 0 && r0 < e0 && r1 >= 0 && r1 < e1 && r2 >= 0 && r2 < e2)
+                                sv[u] = stage[s_ + r0 + e0 * (r1 + e1 * r2)];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        a.x += sv[u].x;
+                        a.y += sv[u].y;
+                        a.z += sv[u].z;
+                        a.w += sv[u].w;
                     }
                 }
             }
