@@ -411,7 +411,7 @@ int fb_limit(const mpm_ctx* c) { return (int)(c->N >> 8); }
 void enqueue_rebuild_into_alt(mpm_ctx* c) {
     enqueue_rebuild(c->stream, tables(c), c->S[c->cur], c->S[c->cur ^ 1], c->ids[c->cur], c->ids[c->cur ^ 1], c->cap,
                     (int)c->N, c->cfg.chunk, (c->cfg.flags & MPM_FLAG_P2G_SORTED_LANES) ? 0 : 1, c->B, c->ctl,
-                    c->nbricks, c->key_bits);
+                    c->nbricks, c->key_bits, c->G.reg_n, c->G.reg);
 }
 
 void note_rebuild(mpm_ctx* c) {

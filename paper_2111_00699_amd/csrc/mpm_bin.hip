@@ -295,11 +295,10 @@ struct OpChunks {
     __device__ void emit(int s, int off, int) const {
         const int bshift = T.shift - 6;
         walk(s, [&](int k, int start, int n, int g) {
-            const uint32_t code = gcode[g] & ((1u << bshift) - 1u);
             Chunk c;
             c.start = start;
             c.count = n;
-            c.block = (int)(compact3(code) | (compact3(code >> 1) << 10) | (compact3(code >> 2) << 20));
+            c.tile = 1;
             c.scene = T.rank_scene[gcode[g] >> bshift];
             out[off + k] = c;
         });
@@ -449,6 +448,82 @@ __global__ __launch_bounds__(WG) void k_rank_ends(const uint32_t* __restrict__ k
 }
 
 // The rebuild also starts the overflow lists and fallback counts afresh.
+// Tile registrations, one wave per chunk: the chunk's particle blocks (the
+// blocks of its sorted range, at most the four of one 2x2x1 slab) reach
+// padded blocks B .. B+2 per axis with in-zone stencils; the chunk is listed
+// with each physical block of that region.  A full list clears the chunk's
+// `tile` flag.
+__global__ __launch_bounds__(WG) void k_register(Chunk* __restrict__ chunks, const uint32_t* __restrict__ keys,
+                                                 const int* __restrict__ ctl, const int* __restrict__ state,
+                                                 int* __restrict__ reg_n, int* __restrict__ reg, Scenes T) {
+    const int nch = ctl[CTL_NCHUNK];
+    const int lane = threadIdx.x & 63;
+    const uint32_t mmask = (1u << T.shift) - 1u;
+    for (int c = blockIdx.x * (WG / 64) + (threadIdx.x >> 6); c < nch; c += gridDim.x * (WG / 64)) {
+        const Chunk ch = chunks[c];
+        const Scene& sc = T.scene[ch.scene];
+        const int NB = sc.P.NB;
+        const uint32_t b0 = (keys[ch.start] & mmask) >> 6, b1 = (keys[ch.start + ch.count - 1] & mmask) >> 6;
+        int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+        for (uint32_t b = b0; b <= b1; ++b) {  // Morton codes of one slab: at most four
+            const int q[3] = {(int)compact3(b), (int)compact3(b >> 1), (int)compact3(b >> 2)};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = min(lo[a], q[a]);
+                hi[a] = max(hi[a], q[a] + 2);
+            }
+        }
+        const int n0 = hi[0] - lo[0] + 1, n1 = hi[1] - lo[1] + 1, n2 = hi[2] - lo[2] + 1;
+        bool fail = false;
+        for (int k = lane; k < n0 * n1 * n2; k += 64) {
+            const int bx = lo[0] + k % n0, by = lo[1] + (k / n0) % n1, bz = lo[2] + k / (n0 * n1);
+            const int s = state[sc.brick_base + (bz * NB + by) * NB + bx];
+            if (s >= 3) {
+                const int slot = atomicAdd(&reg_n[s - 3], 1);
+                if (slot < REG_MAX)
+                    reg[(int64_t)(s - 3) * REG_MAX + slot] = c;
+                else
+                    fail = true;
+            }
+        }
+        if (__ballot(fail) != 0ull && lane == 0) chunks[c].tile = 0;
+    }
+}
+
+// Each physical block's registration list in ascending chunk order (one wave
+// per block; a lane's rank is the count of smaller entries), so the grid
+// update sums the tiles in a fixed order.
+__global__ __launch_bounds__(WG) void k_sort_registrations(const int* __restrict__ ctl, const int* __restrict__ reg_n,
+                                                           int* __restrict__ reg) {
+    __shared__ int buf[WG / 64][REG_MAX];
+    const int nact = ctl[CTL_NACTIVE];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int i = blockIdx.x * (WG / 64) + wv; i < nact; i += gridDim.x * (WG / 64)) {
+        const int m = min(__builtin_amdgcn_readfirstlane(reg_n[i]), REG_MAX);
+        int* list = reg + (int64_t)i * REG_MAX;
+        for (int k = lane; k < m; k += 64) buf[wv][k] = list[k];
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        int v[REG_MAX / 64], r[REG_MAX / 64];
+#pragma unroll
+        for (int u = 0; u < REG_MAX / 64; ++u) {
+            const int k = lane + 64 * u;
+            v[u] = k < m ? buf[wv][k] : 0;
+            r[u] = 0;
+        }
+        for (int j = 0; j < m; ++j) {  // entries are distinct chunk indices
+            const int e = buf[wv][j];
+#pragma unroll
+            for (int u = 0; u < REG_MAX / 64; ++u) r[u] += e < v[u] ? 1 : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < REG_MAX / 64; ++u)
+            if (lane + 64 * u < m) list[r[u]] = v[u];
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
+}
+
 __global__ void k_finish_rebuild(int* ctl) {
     ctl[CTL_REBUILD] = 0;
     ctl[CTL_OVF] = ctl[CTL_OVF + 1] = 0;
@@ -463,7 +538,8 @@ void enqueue_copy_codes(hipStream_t st, uint32_t* dst, const uint32_t* src, int 
 }
 
 void enqueue_rebuild(hipStream_t st, const Scenes& T, float* S_cur, float* S_alt, int* id_cur, int* id_alt,
-                     int64_t cap, int N, int chunk, int spread, BinBuffers& B, int* ctl, int nbricks, int key_bits) {
+                     int64_t cap, int N, int chunk, int spread, BinBuffers& B, int* ctl, int nbricks, int key_bits,
+                     int* reg_n, int* reg) {
     const int nb = cdiv(N > 0 ? N : 1, WG);
     // 1. particle codes
     hipLaunchKernelGGL(k_keys, dim3(nb), dim3(WG), 0, st, S_cur, cap, N, T, B.keys[0], B.vals[0], ctl);
@@ -492,6 +568,11 @@ void enqueue_rebuild(hipStream_t st, const Scenes& T, float* S_cur, float* S_alt
     hipLaunchKernelGGL(k_dilate, dim3(512), dim3(WG), 0, st, B.gcode, ctl, T, B.brick_state);
     device_scan(st, OpActive{B.brick_state, B.active}, nbricks, B.scan_tiles, ctl + CTL_NACTIVE);
     hipLaunchKernelGGL(k_mark_active, dim3(512), dim3(WG), 0, st, B.active, ctl, B.brick_state);
+    // 6. tile registrations of the chunks with the physical blocks
+    hipLaunchKernelGGL(k_fill, dim3(cdiv(nbricks, WG)), dim3(WG), 0, st, reg_n, 0, nbricks);
+    hipLaunchKernelGGL(k_register, dim3(1024), dim3(WG), 0, st, B.chunks, B.keys[cur], ctl, B.brick_state, reg_n, reg,
+                       T);
+    hipLaunchKernelGGL(k_sort_registrations, dim3(1024), dim3(WG), 0, st, ctl, reg_n, reg);
     hipLaunchKernelGGL(k_finish_rebuild, dim3(1), dim3(1), 0, st, ctl);
     hipLaunchKernelGGL(k_rank_ends, dim3(1), dim3(WG), 0, st, B.keys[cur], N, B.gcode, B.chunks, B.active, ctl, T);
 }

@@ -80,12 +80,15 @@ struct Step {
 // or several whole blocks of one 2x2x1 slab of blocks (sparse regions).
 struct Chunk {
     int start, count;
-    int block;  // packed coordinates Bx | By << 10 | Bz << 20 of its first block
+    int tile;  // 1: registered with every physical block its in-zone stencils can reach (P2G may stage
+               // a tile); 0: a registration list was full, the chunk scatters to global atomics
     int scene;
 };
 
-// Tile registrations per physical block: P2G lists each chunk whose tile
-// box reaches a block under that block's position in the active list.
+// Tile registrations per physical block, made by the rebuild: every chunk
+// whose in-zone stencils can reach a block (the 3x3x3 neighbourhoods of the
+// chunk's particle blocks) is listed under that block's position in the
+// active list, in ascending chunk order.
 constexpr int REG_MAX = 256;
 
 // One scene of a context: its grid and time step, its material, where its
@@ -159,7 +162,8 @@ struct BinBuffers {
 // Codes, stable radix sort, blocks, chunks and the gather into sorted order
 // for all scenes at once; `key_bits` is the width of the particle codes.
 void enqueue_rebuild(hipStream_t st, const Scenes& T, float* S_cur, float* S_alt, int* id_cur, int* id_alt,
-                     int64_t cap, int N, int chunk, int spread, BinBuffers& B, int* ctl, int nbricks, int key_bits);
+                     int64_t cap, int N, int chunk, int spread, BinBuffers& B, int* ctl, int nbricks, int key_bits,
+                     int* reg_n, int* reg);
 // dst[i] = src[i] & mask (particle codes without the rank bits).
 void enqueue_copy_codes(hipStream_t st, uint32_t* dst, const uint32_t* src, int count, uint32_t mask);
 
@@ -174,8 +178,9 @@ struct GridBuffers {
     int4* box;      // [cap] per chunk: x = tile origin packed 10 bits/axis, y = extent packed 8 bits/axis
                     // (0 = no tile), z = offset of the tile in `stage` (nodes)
     int stage_nodes;
-    int* reg_n;     // [bricks] tiles registered with physical block i this substep (reset by the grid update)
-    int* reg;       // [bricks * REG_MAX] their chunk indices
+    int* reg_n;     // [bricks] chunks registered with physical block i at the last rebuild (may exceed
+                    // REG_MAX: those chunks have no tile)
+    int* reg;       // [bricks * REG_MAX] their chunk indices, ascending
 };
 
 struct Launch {

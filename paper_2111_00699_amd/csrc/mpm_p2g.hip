@@ -17,10 +17,11 @@
 //     (weight sum and three momentum components) accumulated with
 //     ds_add_f64;
 //   * the tile is then STORED (plain, coalesced float4 stores) to the
-//     staging buffer and registered with every physical block its box
-//     reaches; the grid update gathers each node from the tiles registered
-//     with its block -- no global atomics, and the
-//     transfer of in-zone particles is deterministic.  Each workgroup owns an
+//     staging buffer; the rebuild registered each chunk with every physical
+//     block its in-zone stencils can reach, and the grid update gathers each
+//     node from the registered tiles whose box holds it, in chunk order --
+//     no global atomics, and the transfer of in-zone particles is
+//     deterministic.  Each workgroup owns an
 //     equal slice of the staging buffer and packs its chunks' tiles there
 //     (offset recorded per chunk), so no allocation is shared.
 // The rebuild stores each chunk by cell rounds (first particle of every
@@ -238,12 +239,10 @@ template <bool GLOBAL_ONLY, int NT, int SURM>
 __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, const Chunk* __restrict__ chunks,
                                             int* __restrict__ ctl, float* __restrict__ acc,
                                             float4* __restrict__ stage, int stage_nodes, int4* __restrict__ box,
-                                            int* __restrict__ brick_state, int* __restrict__ reg_n,
-                                            int* __restrict__ reg, int* __restrict__ ovf, int parity,
+                                            int* __restrict__ brick_state, int* __restrict__ ovf, int parity,
                                             Scenes T, int pending, int nbricks, int act) {
     __shared__ double tq[GLOBAL_ONLY ? 1 : 4 * CT];
     __shared__ int red_i[6][NT / 64];
-    __shared__ int reg_fail;
     struct Empty {};
     __shared__ typename std::conditional<SURM == 2, mlp::NetLds16, Empty>::type net;
     __shared__ float sur_stage[SURM == 2 ? NT / 64 * 512 : 1];
@@ -385,34 +384,7 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
             }
             // no room in the tile or in this workgroup's staging slice: the chunk goes to global atomics
             if (Q * ext[2] > CT || used + nt > slice) nt = -1;
-            // register the tile with every physical block its box reaches (the grid update's
-            // gather list); a full list sends the chunk to global atomics instead.  Blocks of
-            // the box that are not physical are skipped: every in-zone stencil lies in the
-            // 3x3x3 neighbourhood of its particle's block, all physical, so the tile holds
-            // zeros there (a bounding box of several blocks' stencils can reach past them).
-            if (tid == 0) reg_fail = 0;
-            __syncthreads();
-            if (nt > 0) {
-                int b0[3], nb[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    b0[a] = (lo[a] >> 2) + 1;  // padded block coordinates
-                    nb[a] = ((lo[a] + ext[a] - 1) >> 2) + 1 - b0[a] + 1;
-                }
-                for (int k = tid; k < nb[0] * nb[1] * nb[2]; k += NT) {
-                    const int bx = b0[0] + k % nb[0], by = b0[1] + (k / nb[0]) % nb[1], bz = b0[2] + k / (nb[0] * nb[1]);
-                    const int state = brick_state[sc.brick_base + (bz * P.NB + by) * P.NB + bx];
-                    if (state >= 3) {
-                        const int slot = atomicAdd(&reg_n[state - 3], 1);
-                        if (slot < REG_MAX)
-                            reg[(int64_t)(state - 3) * REG_MAX + slot] = c;
-                        else
-                            reg_fail = 1;
-                    }
-                }
-            }
-            __syncthreads();
-            if (reg_fail) nt = -1;
+            if (!ch.tile) nt = -1;  // a registration list was full at the rebuild
             if (nt < 0 && tid == 0) atomicAdd(&ctl64(ctl)[CTL64_FALLBACK_CHUNKS], 1ull);
             off = slice0 + used;
             if (nt > 0) used += nt;
@@ -536,7 +508,7 @@ void enqueue_p2g(hipStream_t st, const Launch& L, const Scenes& T, float* S, int
                  int nbricks, int chunk, int act) {
 #define MPM_LAUNCH_P2G(GO, NT, SU)                                                                              \
     hipLaunchKernelGGL((k_p2g<GO, NT, SU>), dim3(L.p2g_grid), dim3(NT), 0, st, S, cap, chunks, ctl, G.acc,        \
-                       G.stage, G.stage_nodes, G.box, brick_state, G.reg_n, G.reg, G.ovf[parity], parity, T, pending,   \
+                       G.stage, G.stage_nodes, G.box, brick_state, G.ovf[parity], parity, T, pending,                 \
                        nbricks, act)
 #define MPM_LAUNCH_P2G_NT(GO, SU)                        \
     do {                                                 \

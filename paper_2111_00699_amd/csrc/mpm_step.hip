@@ -28,14 +28,14 @@ namespace {
 
 // ----------------------------------------------------------- grid update
 // One wave64 per 4^3 block.  Each node sums the global-path accumulator and
-// the staged P2G tiles registered with its block this substep (P2G lists
-// every chunk whose tile box reaches a physical block), then
+// the staged P2G tiles of the chunks registered with its block at the
+// rebuild whose box (this substep's) holds the node, in chunk order, then
 // v = p/m + dt g where m > 0 (else 0) and the wall condition; writes (v, m),
-// clears the accumulator and the registrations, and stamps the block.
+// clears the accumulator, and stamps the block.
 __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, float4* __restrict__ vel,
                                              const int* __restrict__ active, int* __restrict__ ctl,
                                              const int* __restrict__ ovf, int* __restrict__ brick_state,
-                                             int* __restrict__ stamp, int* __restrict__ reg_n,
+                                             int* __restrict__ stamp, const int* __restrict__ reg_n,
                                              const int* __restrict__ reg, const float4* __restrict__ stage,
                                              const int4* __restrict__ box, int parity, int nbricks, Scenes T,
                                              int act) {
@@ -95,7 +95,6 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, float4* __
                     }
                 }
             }
-            if (lane == 0) reg_n[it] = 0;  // ready for the next substep
         }
         float v[3] = {0.0f, 0.0f, 0.0f};
         if (a.x > 0.0f) {
