@@ -250,6 +250,10 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
         if (T.sur_theta) mlp::load_net16(net, T.sur_theta, T.sur_norm);
         __syncthreads();
     }
+    if constexpr (!GLOBAL_ONLY) {
+        for (int t = threadIdx.x; t < 4 * CT; t += NT) tq[t] = 0.0;
+        __syncthreads();
+    }
     unsigned err = 0;
     unsigned n_sur = 0, n_fb = 0;
     int begin, end, stride;
@@ -388,18 +392,12 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
             if (nt < 0 && tid == 0) atomicAdd(&ctl64(ctl)[CTL64_FALLBACK_CHUNKS], 1ull);
             off = slice0 + used;
             if (nt > 0) used += nt;
-            const int e01 = ext[0] * ext[1];
-            for (int u = tid; u < nt; u += NT) {  // clear the box's nodes at their padded addresses
-                const int z = u / e01, y = (u - z * e01) / ext[0], xx = u - z * e01 - y * ext[0];
-                const int t = xx + R * y + Q * z;
-#pragma unroll
-                for (int ch4 = 0; ch4 < 4; ++ch4) tq[ch4 * CT + t] = 0.0;
-            }
+            // (the tile is all zero here: cleared at the start, and every node a chunk touched is
+            // zeroed again as it is stored)
             if (tid == 0)
                 box[c] = nt > 0 ? make_int4(lo[0] | (lo[1] << 10) | (lo[2] << 20), ext[0] | (ext[1] << 8) | (ext[2] << 16),
                                             off, 0)
                                 : make_int4(0, 0, 0, 0);
-            __syncthreads();
         }
 
         // ---- phase 2: scatter
@@ -477,6 +475,8 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
                 const int t = xx + R * y + Q * z;
                 slot[u] = make_float4((float)(tq[t] * (double)M.mp), (float)tq[CT + t], (float)tq[2 * CT + t],
                                       (float)tq[3 * CT + t]);
+#pragma unroll
+                for (int ch4 = 0; ch4 < 4; ++ch4) tq[ch4 * CT + t] = 0.0;  // ready for the next chunk
             }
             __syncthreads();
         }
