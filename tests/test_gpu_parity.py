@@ -332,6 +332,28 @@ def test_expanding_cloud_overflows_tiles(torch_cuda, oracle):
     sim.close()
 
 
+def test_full_registration_lists_fall_back_to_global_atomics(torch_cuda, oracle):
+    """About 16 particles per cell and chunks of 64: a block's registration
+    list (chunks whose stencils can reach it, at most 256) overflows for the
+    central blocks, those chunks scatter with global atomics, and the substep
+    still matches the oracle."""
+    x = scenes.uniform(23, 3 * 32000, 0, 0.4, 0.6).reshape(3, -1).astype(np.float32)
+    st = scenes.nontrivial_state(x, seed=19)
+    cfg = dict(n=64, dt=1e-4)
+    print_case("dense_registrations", N=x.shape[1])
+    sim = make_sim(torch_cuda, cfg, chunk=64)
+    sim.add_particles(scenes.JELLY, st["x"], v=st["v"], C=st["C"], F=st["F"])
+    sim.substep(2)
+    stats = sim.stats()
+    assert stats["p2g_fallback_chunks"] > 0, stats
+    assert stats["p2g_global_particles"] > 0, stats
+    gs = gpu_state(sim)
+    os_, _, _, bad = oracle.substep(cfg, scenes.JELLY, st, steps=2)
+    assert bad == 0
+    compare_state(gs, os_, "jelly", n=cfg["n"])
+    sim.close()
+
+
 def test_free_zone_triggers_rebuild(torch_cuda):
     sc = scenes.jelly_cube(0)
     v = np.zeros_like(sc["x"])
