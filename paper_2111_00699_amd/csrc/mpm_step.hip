@@ -78,7 +78,8 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, float4* __
                         if (mask) {  // wave-uniform
                             const int i = __builtin_ctzll(mask);
                             mask &= mask - 1;
-                            const int bx_ = __shfl(bb.x, i, 64), by_ = __shfl(bb.y, i, 64), s_ = __shfl(bb.z, i, 64);
+                            const int bx_ = __builtin_amdgcn_readlane(bb.x, i), by_ = __builtin_amdgcn_readlane(bb.y, i),
+                                      s_ = __builtin_amdgcn_readlane(bb.z, i);
                             const int e0 = by_ & 255, e1 = (by_ >> 8) & 255, e2 = by_ >> 16;
                             const int r0 = g[0] - (bx_ & 1023), r1 = g[1] - ((bx_ >> 10) & 1023),
                                       r2 = g[2] - (bx_ >> 20);
