@@ -413,7 +413,8 @@ __global__ __launch_bounds__(WG) void k_dilate(const uint32_t* __restrict__ gcod
 }
 
 // After compaction a physical block's state names its position in the active
-// list (3 + i), where P2G registers the tiles that reach it.
+// list (3 + i), under which the rebuild lists the chunks whose tiles can reach
+// it.
 __global__ __launch_bounds__(WG) void k_mark_active(const int* __restrict__ active, const int* __restrict__ ctl,
                                                     int* __restrict__ state) {
     const int n = ctl[CTL_NACTIVE];
