@@ -24,6 +24,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# LDS FP64 atomic throughput of gfx950, measured with a probe of ds_add_f64 on
+# distinct addresses: 6.61 lane-operations per clock per compute unit, i.e.
+# 6.61 x 256 CUs x 2.4 GHz.  P2G's scatter issues 27 nodes x 4 channels of
+# them per in-zone particle.
+LDS_F64_ATOMIC_PEAK = 6.61 * 256 * 2.4e9
+P2G_LDS_ATOMICS_PER_PARTICLE = 108
 # Algorithmic bytes per particle and launch (FP32 state, deferred deformation
 # update): P2G reads x, v, C, F_E, J_P (100 B) and writes F_E, J_P (40 B);
 # G2P reads x (12 B) and writes x, v, C (60 B).
@@ -356,6 +362,11 @@ def main():
                      "traffic": p2g_traffic_bytes(), "traffic_unit": "HBM bytes per launch",
                      "avg_launch_us": p2g_avg_ms * 1e3, "launches": p2g["launches"],
                      "bytes_per_particle": P2G_BYTES["snow"]},
+        # the bound P2G actually meets: its LDS FP64 atomics against their measured peak rate
+        "roofline_lds": {"kernel": "p2g", "bound": "lds_fp64_atomics",
+                         "achieved": P2G_LDS_ATOMICS_PER_PARTICLE * N / (p2g_avg_ms * 1e-3),
+                         "peak": LDS_F64_ATOMIC_PEAK, "unit": "lane-ops/s",
+                         "frac": P2G_LDS_ATOMICS_PER_PARTICLE * N / (p2g_avg_ms * 1e-3) / LDS_F64_ATOMIC_PEAK},
         "wall_ms": wall * 1e3,
         "gpu_event_ms": gpu_ms,
     }
