@@ -9,8 +9,10 @@ with boundary conditions, G2P with the free-zone test).  Prints ONE JSON line.
 
 `value` is particle-substeps per second over the K timed frames (inputs
 resident in HBM before timing starts).  `roofline` covers the P2G kernel,
-timed with HIP events on the library's stream during the timed frames;
-`cpu_baseline` times the FP64 oracle on the host on a bounded sample.
+timed with HIP events on the library's stream during the timed frames,
+against the HBM peak; `roofline_lds` puts the same launches against the LDS
+FP64 atomic rate that bounds them; `cpu_baseline` times the FP64 oracle on
+the host on a bounded sample.
 """
 import argparse
 import json
