@@ -32,6 +32,13 @@ HBM_PEAK_GBS = 8000.0
 # them per in-zone particle.
 LDS_F64_ATOMIC_PEAK = 6.61 * 256 * 2.4e9
 P2G_LDS_ATOMICS_PER_PARTICLE = 108
+# The surrogate MLP 12-64-64-12 as executed on MFMA (inputs and outputs padded
+# to 16): 16x64 + 64x64 + 64x16 = 6,144 multiply-adds per forward pass; a
+# training sample adds the weight gradients (6,144) and the activation
+# deltas of layers 2 and 3 (4,096 + 1,024).
+MLP_FWD_FLOPS = 2 * 6144
+MLP_TRAIN_FLOPS = 2 * (6144 + 6144 + 5120)
+MFMA_BF16_PEAK_TFLOPS = 2500.0
 # Algorithmic bytes per particle and launch (FP32 state, deferred deformation
 # update): P2G reads x, v, C, F_E, J_P (100 B) and writes F_E, J_P (40 B);
 # G2P reads x (12 B) and writes x, v, C (60 B).
@@ -204,6 +211,7 @@ def bench_surrogate(args):
     sur.fit_norm(X, T)
     t0 = time.perf_counter()
     losses = sur.train(X, T, steps=args.train_steps, batch=16384, lr=1e-3, seed=7)
+    torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     log(f"[bench] surrogate: {X.shape[0]} pairs in {t_sample:.1f} s, {args.train_steps} Adam steps in {t_train:.1f} s, "
         f"loss {losses[:10].mean():.3e} -> {losses[-10:].mean():.3e}")
@@ -224,6 +232,7 @@ def bench_surrogate(args):
             sim.use_surrogate(mode, sur if mode == 1 else None, tol=args.sur_tol, dt_ref=cfg["dt"])
         sim.substep(nsub // 3)  # warm-up
         sim.synchronize()
+        sim.profile(mpm.PHASE_P2G)
         st0 = sim.stats()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -232,11 +241,17 @@ def bench_surrogate(args):
         e1.record()
         torch.cuda.synchronize()
         st1 = sim.stats()
+        p2g = sim.profile_read()["p2g"]
+        p2g_us = 1e3 * p2g["ms"] / max(p2g["launches"], 1)
         finals[name] = sim.read_particles()["x"]
         done = st1["surrogate_particles"] - st0["surrogate_particles"]
         fb = st1["surrogate_fallbacks"] - st0["surrogate_fallbacks"]
-        results[name] = {"ms_per_frame": e0.elapsed_time(e1) / args.steps,
+        results[name] = {"ms_per_frame": e0.elapsed_time(e1) / args.steps, "p2g_avg_launch_us": p2g_us,
                          "fallback_rate": (fb / max(done + fb, 1)) if mode else None}
+        if mode == 1:  # network evaluations per P2G launch (both kept and fallen-back particles)
+            tflops = MLP_FWD_FLOPS * (done + fb) / max(p2g["launches"], 1) / (p2g_us * 1e-6) / 1e12
+            results[name]["p2g_mfma"] = {"achieved": tflops, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                         "frac": tflops / MFMA_BF16_PEAK_TFLOPS}
         sim.close()
         log(f"[bench] {name}: {results[name]}")
     dx = 1.0 / cfg["n"]
@@ -244,6 +259,7 @@ def bench_surrogate(args):
         d = (finals[name] - finals["exact"]).norm(dim=0) / dx
         results[name]["position_error_dx"] = {"mean": float(d.mean()), "max": float(d.max())}
     ex = results["exact"]["ms_per_frame"]
+    train_tflops = MLP_TRAIN_FLOPS * 16384 * args.train_steps / t_train / 1e12
     out = {
         "metric": "particle-substeps/s", "value": N * nsub / (results["surrogate"]["ms_per_frame"] * 1e-3),
         "unit": "particle-substeps/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
@@ -254,6 +270,8 @@ def bench_surrogate(args):
                    "frames_timed": args.steps, "start_frame": args.sur_start_frame,
                    "train_pairs": int(X.shape[0]), "train_steps": args.train_steps,
                    "final_loss": float(losses[-10:].mean()), "tol": args.sur_tol},
+        "train_mfma": {"seconds": t_train, "achieved": train_tflops, "peak": MFMA_BF16_PEAK_TFLOPS,
+                       "unit": "TFLOP/s", "frac": train_tflops / MFMA_BF16_PEAK_TFLOPS},
         "modes": results,
         "speedup_vs_exact": {k: ex / v["ms_per_frame"] for k, v in results.items()},
     }
