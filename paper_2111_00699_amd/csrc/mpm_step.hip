@@ -167,6 +167,16 @@ __global__ __launch_bounds__(NT) void k_g2p(float* __restrict__ S, int64_t cap, 
         const float c4 = 4.0f * P.fn;  // (4/dx^2) * dx
         const int NB = P.NB;
         const float4* vels = vel + (int64_t)sc.brick_base * BLOCK_NODES;
+        // this thread's particle (a chunk holds at most NT): its position and
+        // block word are loaded before the node box, so the two loads overlap
+        const bool mine = (int)threadIdx.x < ch.count;
+        const int p = ch.start + (mine ? (int)threadIdx.x : 0);
+        float x[3] = {0.f, 0.f, 0.f}, fsid = 0.f;
+        if (mine) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) x[a] = S[(FX + a) * cap + p];
+            fsid = S[FSID * cap + p];
+        }
         int lo[3] = {0, 0, 0}, e[3] = {0, 0, 0}, nt = 0;
         if (LDS_BOX) {
             const int4 bb = box[c];
@@ -185,13 +195,10 @@ __global__ __launch_bounds__(NT) void k_g2p(float* __restrict__ S, int64_t cap, 
             }
             __syncthreads();
         }
-        for (int i = threadIdx.x; i < ch.count; i += NT) {
-            const int p = ch.start + i;
-            float x[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) x[a] = S[(FX + a) * cap + p];
+        do {  // once, for this thread's particle
+            if (!mine) break;
             int B[3];  // the particle's block at the last rebuild (its free zone)
-            fsid_block(S[FSID * cap + p], B);
+            fsid_block(fsid, B);
             Stencil st;
             if (!make_stencil(x, P, st, err)) continue;
             int r[3];
@@ -268,7 +275,7 @@ __global__ __launch_bounds__(NT) void k_g2p(float* __restrict__ S, int64_t cap, 
                 left = left || !(cc >= (float)(4 * B[a] - 3) && cc <= (float)(4 * B[a] + 6));
             }
             if (!fin) err |= MPM_ERR_NONFINITE;
-        }
+        } while (false);
         if (LDS_BOX) __syncthreads();
     }
     if (__ballot(left) != 0ull && (threadIdx.x & 63) == 0) {
