@@ -177,9 +177,14 @@ int mpm_add_particles(mpm_ctx* ctx, int32_t scene, const mpm_material* mat, int6
 
 /* Enqueue `nsteps` substeps of every scene.  Each is: [rebuild-mapping + sort
  * when a particle left its free zone] -> P2G -> grid update -> G2P, one launch
- * per phase for all scenes.  The host waits for the device only to keep at
- * most `lag` substeps in flight, so that it can read the device's rebuild
- * flag; it never drains the stream.                                         */
+ * per phase for all scenes.  Unless MPM_FLAG_P2G_GLOBAL_ATOMICS,
+ * MPM_FLAG_REBUILD_EVERY_STEP, MPM_FLAG_G2P_GLOBAL_GATHER,
+ * MPM_FLAG_FRAME_GRAPHS or a learned / closed-form return map is in use, a
+ * substep's G2P runs inside the next substep's P2G launch (paper, "Merge
+ * Kernels": G2P2G); calls that read, extend, sample or rebuild the state run
+ * the outstanding G2P first, so what they see does not change.  The host
+ * waits for the device only to keep at most `lag` substeps in flight, so
+ * that it can read the device's rebuild flag; it never drains the stream.  */
 int mpm_substep(mpm_ctx* ctx, int32_t nsteps);
 
 /* Advance one frame (frame_dt > 0): scene s runs ceil(frame_dt/dt_s)

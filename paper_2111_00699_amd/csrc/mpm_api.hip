@@ -94,6 +94,10 @@ struct mpm_ctx {
     int64_t n_at_rebuild = 0;
     bool need_rebuild = true;
     int pending = 0;
+    // The G2P of the last substep of ranks [0, g2p_due_act) has not run yet:
+    // the next substep's P2G runs it first (fused), or bring_up_to_date()
+    // does before the state is read, extended, sampled or rebuilt.
+    int g2p_due_act = 0;
     FrameGraph graphs[2];
     // snow return map without SVD (see mpm_use_surrogate)
     const float* sur_theta = nullptr;
@@ -446,13 +450,42 @@ int check_error_word(mpm_ctx* c) {
     return MPM_OK;
 }
 
+// Whether a substep may leave its G2P to the next substep's P2G (the fused
+// kernel needs the LDS tile path, the exact return map and the node-box
+// gather).
+bool fusion_allowed(const mpm_ctx* c) {
+    return !c->sur_any && !(c->cfg.flags & (MPM_FLAG_P2G_GLOBAL_ATOMICS | MPM_FLAG_REBUILD_EVERY_STEP |
+                                            MPM_FLAG_G2P_GLOBAL_GATHER | MPM_FLAG_FRAME_GRAPHS));
+}
+
+// Run the G2P that the last substep left to its successor (see g2p_due_act).
+int bring_up_to_date(mpm_ctx* c) {
+    if (!c->g2p_due_act) return MPM_OK;
+    int slot;
+    if (int r = prof_begin(c, 3, &slot)) return r;
+    enqueue_g2p(c->stream, c->L, tables(c), c->S[c->cur], c->cap, c->B.chunks, c->ctl, c->G, nullptr,
+                (c->cfg.flags & MPM_FLAG_G2P_GLOBAL_GATHER) ? 0 : 1, 0, fb_limit(c), c->cfg.chunk, c->g2p_due_act, 0);
+    if (int r = prof_end(c, slot)) return r;
+    HIP_OK(c, hipGetLastError());
+    c->g2p_due_act = 0;
+    return MPM_OK;
+}
+
 // One substep of the first `act` ranks, enqueued directly (host-lagged
-// rebuild decision, optional phase events).
+// rebuild decision, optional phase events).  When fusion is allowed the
+// substep ends after its grid update and its G2P runs at the start of the
+// next substep's P2G.
 int substep_one(mpm_ctx* c, int act) {
     int r = poll_flags(c, c->step - c->cfg.lag);
     if (r) return r;
     int slot;
-    if (c->need_rebuild || (c->cfg.flags & MPM_FLAG_REBUILD_EVERY_STEP)) {
+    const bool rebuild = c->need_rebuild || (c->cfg.flags & MPM_FLAG_REBUILD_EVERY_STEP);
+    const bool fusable = fusion_allowed(c);
+    if (c->g2p_due_act && (rebuild || !fusable || act > c->g2p_due_act)) {
+        if ((r = bring_up_to_date(c))) return r;
+    }
+    const bool fused = fusable && c->g2p_due_act >= act;
+    if (rebuild) {
         if ((r = prof_begin(c, 0, &slot))) return r;
         enqueue_rebuild_into_alt(c);
         if ((r = prof_end(c, slot))) return r;
@@ -463,16 +496,21 @@ int substep_one(mpm_ctx* c, int act) {
     const int parity = (int)(c->parity_ctr & 1);
     const Scenes T = tables(c);
     if ((r = prof_begin(c, 1, &slot))) return r;
-    enqueue_p2g(c->stream, c->L, T, c->S[c->cur], c->cap, c->B.chunks, c->ctl, c->G, c->B.brick_state, c->pending,
-                parity, (c->cfg.flags & MPM_FLAG_P2G_GLOBAL_ATOMICS) ? 1 : 0, c->nbricks, c->cfg.chunk, act);
+    enqueue_p2g(c->stream, c->L, T, c->S[c->cur], c->cap, c->B.chunks, c->ctl, c->G, c->B.brick_state,
+                fused ? 1 : c->pending, parity, (c->cfg.flags & MPM_FLAG_P2G_GLOBAL_ATOMICS) ? 1 : 0, c->nbricks,
+                c->cfg.chunk, act, fused ? 1 : 0, c->ring_dev + rs, fb_limit(c));
     if ((r = prof_end(c, slot))) return r;
     if ((r = prof_begin(c, 2, &slot))) return r;
     enqueue_grid(c->stream, c->L, T, c->B, c->ctl, c->G, parity, c->nbricks, act);
     if ((r = prof_end(c, slot))) return r;
-    if ((r = prof_begin(c, 3, &slot))) return r;
-    enqueue_g2p(c->stream, c->L, T, c->S[c->cur], c->cap, c->B.chunks, c->ctl, c->G, c->ring_dev + rs,
-                (c->cfg.flags & MPM_FLAG_G2P_GLOBAL_GATHER) ? 0 : 1, parity, fb_limit(c), c->cfg.chunk, act);
-    if ((r = prof_end(c, slot))) return r;
+    if (fusable) {
+        c->g2p_due_act = std::max(c->g2p_due_act, act);
+    } else {
+        if ((r = prof_begin(c, 3, &slot))) return r;
+        enqueue_g2p(c->stream, c->L, T, c->S[c->cur], c->cap, c->B.chunks, c->ctl, c->G, c->ring_dev + rs,
+                    (c->cfg.flags & MPM_FLAG_G2P_GLOBAL_GATHER) ? 0 : 1, parity, fb_limit(c), c->cfg.chunk, act, 1);
+        if ((r = prof_end(c, slot))) return r;
+    }
     HIP_OK(c, hipGetLastError());
     HIP_OK(c, hipEventRecord(c->ev[rs], c->stream));
     note_substep(c, act);
@@ -497,11 +535,11 @@ int graph_frame(mpm_ctx* c, float frame_dt, const std::vector<int>& ns) {
             const int parity = k & 1;  // the rebuild cleared both overflow slots
             enqueue_p2g(c->stream, c->L, T, c->S[other], c->cap, c->B.chunks, c->ctl, c->G, c->B.brick_state, 1,
                         parity, (c->cfg.flags & MPM_FLAG_P2G_GLOBAL_ATOMICS) ? 1 : 0, c->nbricks, c->cfg.chunk,
-                        act);
+                        act, 0, nullptr, 0);
             enqueue_grid(c->stream, c->L, T, c->B, c->ctl, c->G, parity, c->nbricks, act);
             enqueue_g2p(c->stream, c->L, T, c->S[other], c->cap, c->B.chunks, c->ctl, c->G, nullptr,
                         (c->cfg.flags & MPM_FLAG_G2P_GLOBAL_GATHER) ? 0 : 1, parity, fb_limit(c), c->cfg.chunk,
-                        act);
+                        act, 1);
         }
         hipGraph_t graph = nullptr;
         const hipError_t e1 = hipGetLastError();
@@ -531,6 +569,7 @@ int run_frame(mpm_ctx* c, float frame_dt) {
     if ((c->cfg.flags & MPM_FLAG_FRAME_GRAPHS) && c->pending && !(c->cfg.flags & MPM_FLAG_REBUILD_EVERY_STEP)) {
         int r = poll_flags(c, c->step);  // the ring is idle across a graph frame
         if (r) return r;
+        if ((r = bring_up_to_date(c))) return r;
         return graph_frame(c, frame_dt, ns);
     }
     for (int k = 0; k < ns[0]; ++k) {
@@ -742,6 +781,8 @@ int mpm_add_particles(mpm_ctx* c, int32_t scene, const mpm_material* mat, int64_
         return fail(c, MPM_EINVAL, "the first call for a scene must pass a material");
     }
     if (count == 0) return MPM_OK;
+    // the pending G2P walks the current chunk list, which growing the buffers replaces
+    if (int r = bring_up_to_date(c)) return r;
     if (c->N + count > c->cap / 2) {
         int64_t newcap = c->cap;
         while (c->N + count > newcap / 2) newcap *= 4;
@@ -794,6 +835,7 @@ int mpm_read_particles(mpm_ctx* c, int32_t scene, int64_t count, float* x, float
     if (!c) return MPM_EINVAL;
     if (int r = scene_arg(c, scene)) return r;
     if (count != c->sh[scene].N) return fail(c, MPM_EINVAL, "count must equal the scene's particle count");
+    if (int r = bring_up_to_date(c)) return r;
     enqueue_read(c->stream, tables(c), c->S[c->cur], c->ids[c->cur], c->cap, (int)c->N, scene, (int)count, c->pending,
                  x, v, C, F, s);
     HIP_OK(c, hipGetLastError());
@@ -921,6 +963,7 @@ int mpm_autotune(mpm_ctx* c, float frame_dt, int32_t frames, int32_t* chunk_out)
         if (chunk_out) *chunk_out = orig_chunk;
         return MPM_OK;
     }
+    if (int r = bring_up_to_date(c)) return r;
     HIP_OK(c, hipStreamSynchronize(c->stream));
     if (int r = poll_flags(c, c->step)) return r;
     // snapshot of the device state and of the host counters
@@ -942,6 +985,7 @@ int mpm_autotune(mpm_ctx* c, float frame_dt, int32_t frames, int32_t* chunk_out)
         dst->parity_ctr = s.parity_ctr;
         dst->n_at_rebuild = s.n_at_rebuild;
         dst->pending = s.pending;
+        dst->g2p_due_act = 0;  // the snapshot holds the state brought up to date
         dst->sh = s.sh;
     };
     mpm_ctx saved;  // host counters only
@@ -1241,6 +1285,7 @@ int mpm_surrogate_sample(mpm_ctx* c, int32_t scene, float dt_ref, int64_t max_co
     if (int r = scene_arg(c, scene)) return r;
     if (!X || !T || max_count < 0 || !(dt_ref > 0.0f)) return fail(c, MPM_EINVAL, "bad sampling arguments");
     if (!c->sh[scene].has_mat || c->sh[scene].mat.kind != MPM_SNOW) return fail(c, MPM_EINVAL, "the scene is not snow");
+    if (int r = bring_up_to_date(c)) return r;
     unsigned long long* counter = nullptr;
     HIP_OK(c, hipMalloc(&counter, sizeof(unsigned long long)));
     sur_zero(c->stream, reinterpret_cast<float*>(counter), 2);

@@ -191,9 +191,12 @@ struct Launch {
 inline int chunk_threads(int chunk) { return chunk <= 128 ? 128 : chunk <= 256 ? 256 : 512; }
 
 // `act`: the substep advances the scenes of the first `act` ranks only.
+// fused: the previous substep's G2P runs inside P2G (see k_p2g); host_flag
+// and fb_limit serve its free-zone request.  Only with the tile path and the
+// exact return map (T.sur_any == 0, global_atomics == 0).
 void enqueue_p2g(hipStream_t st, const Launch& L, const Scenes& T, float* S, int64_t cap, const Chunk* chunks,
                  int* ctl, GridBuffers& G, int* brick_state, int pending, int parity, int global_atomics,
-                 int nbricks, int chunk, int act);
+                 int nbricks, int chunk, int act, int fused, int* host_flag, int fb_limit);
 int p2g_grid_size(int cus, int chunk);
 // Workgroups of `threads` threads that fit on one compute unit at once, from
 // the kernel's register and LDS use (gfx950: 512 VGPRs per lane and SIMD,
@@ -201,10 +204,12 @@ int p2g_grid_size(int cus, int chunk);
 int wgs_per_cu(const void* fn, int threads);
 void enqueue_grid(hipStream_t st, const Launch& L, const Scenes& T, const BinBuffers& B, int* ctl, GridBuffers& G,
                   int parity, int nbricks, int act);
-// host_flag may be NULL (graph-recorded frames read no flag).
+// host_flag may be NULL (graph-recorded frames read no flag); report_zone 0
+// leaves the free-zone request alone (a G2P that only brings the state up to
+// date before it is read; the next substep's G2P reports the same exits).
 void enqueue_g2p(hipStream_t st, const Launch& L, const Scenes& T, float* S, int64_t cap, const Chunk* chunks,
                  int* ctl, const GridBuffers& G, int* host_flag, int lds_box, int parity, int fb_limit, int chunk,
-                 int act);
+                 int act, int report_zone);
 void enqueue_materialize(hipStream_t st, const Scenes& T, float* S, int64_t cap, int N);
 void enqueue_insert(hipStream_t st, float* S, int* ids, int64_t cap, int N0, int count, int scene, int id0,
                     const float* x, const float* v, const float* C, const float* F, const float* s, int* ctl);

@@ -66,6 +66,102 @@ __device__ __forceinline__ void axis_offsets(int base, int blockstride, int loca
     }
 }
 
+// ------------------------------------------------------------ G2P pieces
+// A chunk's node box (origin lo, extent e per axis, from its P2G tile) as a
+// tight float4 array tv[x + e0 (y + e1 z)] of grid velocities, loaded by the
+// workgroup's threads (vels: the scene's node velocities).
+__device__ __forceinline__ void load_node_box(float4* tv, const float4* vels, int NB, const int lo[3],
+                                              const int e[3], int nt, int tid, int nthreads) {
+    for (int t = tid; t < nt; t += nthreads) {
+        const int gx = lo[0] + t % e[0], gy = lo[1] + (t / e[0]) % e[1], gz = lo[2] + t / (e[0] * e[1]);
+        tv[t] = vels[((((gz >> 2) + 1) * NB + ((gy >> 2) + 1)) * NB + ((gx >> 2) + 1)) * 64 + (gx & 3) +
+                     ((gy & 3) << 2) + ((gz & 3) << 4)];
+    }
+}
+
+// G2P of one particle with stencil st: v' = sum w v_i and
+// C' = 4/dx^2 sum w v_i (x_i - x_p)^T, gathered from the node box tv
+// (nt > 0 nodes, origin lo, extent e) when the stencil lies inside it, else
+// from the dense node velocities.  c4 = 4/dx.
+__device__ __forceinline__ void g2p_gather(const Stencil& st, const float4* tv, const float4* vels, int NB,
+                                           const int lo[3], const int e[3], int nt, float c4, float vp[3],
+                                           float Cn[9]) {
+    int r[3];
+    bool inbox = nt > 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        r[a] = st.base[a] - lo[a];
+        inbox = inbox && r[a] >= 0 && r[a] + 2 < e[a];
+    }
+    float Mo[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // sum w v_a o_b
+#pragma unroll
+    for (int a = 0; a < 3; ++a) vp[a] = 0.0f;
+    if (inbox) {
+        const int tb = r[0] + e[0] * (r[1] + e[1] * r[2]);
+#pragma unroll
+        for (int o2 = 0; o2 < 3; ++o2)
+#pragma unroll
+            for (int o1 = 0; o1 < 3; ++o1) {
+                const float wyz = st.w[1][o1] * st.w[2][o2];
+                const int row = tb + e[0] * (o1 + e[1] * o2);
+#pragma unroll
+                for (int o0 = 0; o0 < 3; ++o0) {
+                    const float w = wyz * st.w[0][o0];
+                    const float4 g = tv[row + o0];
+                    const float wv[3] = {w * g.x, w * g.y, w * g.z};
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        vp[a] += wv[a];
+                        Mo[a * 3 + 0] += o0 * wv[a];
+                        Mo[a * 3 + 1] += o1 * wv[a];
+                        Mo[a * 3 + 2] += o2 * wv[a];
+                    }
+                }
+            }
+    } else {
+        int xo[3], yo[3], zo[3];
+        axis_offsets(st.base[0], 1, 0, xo);
+        axis_offsets(st.base[1], NB, 2, yo);
+        axis_offsets(st.base[2], NB * NB, 4, zo);
+#pragma unroll
+        for (int o2 = 0; o2 < 3; ++o2)
+#pragma unroll
+            for (int o1 = 0; o1 < 3; ++o1) {
+                const float wyz = st.w[1][o1] * st.w[2][o2];
+#pragma unroll
+                for (int o0 = 0; o0 < 3; ++o0) {
+                    const float w = wyz * st.w[0][o0];
+                    const float4 g = vels[xo[o0] + yo[o1] + zo[o2]];
+                    const float wv[3] = {w * g.x, w * g.y, w * g.z};
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        vp[a] += wv[a];
+                        Mo[a * 3 + 0] += o0 * wv[a];
+                        Mo[a * 3 + 1] += o1 * wv[a];
+                        Mo[a * 3 + 2] += o2 * wv[a];
+                    }
+                }
+            }
+    }
+    // C' = 4/dx^2 sum w v (x_i - x_p)^T = (4/dx) (Mo - v' f^T)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b2 = 0; b2 < 3; ++b2) Cn[a * 3 + b2] = c4 * (Mo[a * 3 + b2] - vp[a] * st.f[b2]);
+}
+
+// The particle's cell code after the move must stay within [4B-3, 4B+6] per
+// axis (its free zone, B its block at the last rebuild).
+__device__ __forceinline__ bool left_free_zone(const float xn[3], float fn, const int B[3]) {
+    bool left = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float cc = floorf(xn[a] * fn - 0.5f) + 1.0f;
+        left = left || !(cc >= (float)(4 * B[a] - 3) && cc <= (float)(4 * B[a] + 6));
+    }
+    return left;
+}
+
 // Mark the (at most 2x2x2) blocks of a stencil in the block grid of its
 // scene (NB padded blocks per axis, first brick `base`); blocks outside the
 // physical set of the last rebuild are appended once to the overflow list.

@@ -235,13 +235,21 @@ __device__ void snow_without_svd(const mlp::NetLds16* net, float* stage, const S
 // NT threads per workgroup = the largest chunk it takes (128, 256 or 512).
 // SURM: 0 every snow scene takes the exact map; 1 some scene takes the
 // closed form without SVD; 2 some scene takes the network (staged in LDS).
-template <bool GLOBAL_ONLY, int NT, int SURM>
-__global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, const Chunk* __restrict__ chunks,
-                                            int* __restrict__ ctl, float* __restrict__ acc,
-                                            float4* __restrict__ stage, int stage_nodes, int4* __restrict__ box,
-                                            int* __restrict__ brick_state, int* __restrict__ ovf, int parity,
-                                            Scenes T, int pending, int nbricks, int act) {
-    __shared__ double tq[GLOBAL_ONLY ? 1 : 4 * CT];
+// FUSED (with the tile path and the exact map only): each chunk first does
+// the previous substep's G2P -- gathered from the node box of that
+// substep's tile, staged in the tile's LDS -- and scatters with the fresh
+// v, C and x; the particle's v and C are not stored (the G2P that brings the
+// state up to date before a read recomputes them).  vel, host_flag and
+// fb_limit serve that G2P.
+template <bool GLOBAL_ONLY, int NT, int SURM, bool FUSED>
+__device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, const Chunk* __restrict__ chunks,
+                                         int* __restrict__ ctl, float* __restrict__ acc, float4* __restrict__ stage,
+                                         int stage_nodes, int4* __restrict__ box, int* __restrict__ brick_state,
+                                         int* __restrict__ ovf, int parity, const Scenes& T, int pending,
+                                         int nbricks, int act, const float4* __restrict__ vel,
+                                         int* __restrict__ host_flag, int fb_limit) {
+    static_assert(!FUSED || (!GLOBAL_ONLY && SURM == 0), "the fused G2P needs the LDS tile and the exact map");
+    __shared__ __align__(16) double tq[GLOBAL_ONLY ? 1 : 4 * CT];
     __shared__ int red_i[6][NT / 64];
     struct Empty {};
     __shared__ typename std::conditional<SURM == 2, mlp::NetLds16, Empty>::type net;
@@ -256,6 +264,9 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
     }
     unsigned err = 0;
     unsigned n_sur = 0, n_fb = 0;
+    // fused G2P: the free-zone request, as the G2P kernel makes it (the
+    // previous substep's P2G counted its tile fallbacks in the other slot)
+    bool left = FUSED && blockIdx.x == 0 && threadIdx.x == 0 && ctl[CTL_FB + (parity ^ 1)] > fb_limit;
     int begin, end, stride;
     xcd_split(rank_limit(T, ctl, act, RE_CHUNK, CTL_NCHUNK), begin, end, stride);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -285,12 +296,13 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
         }
         if (have) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                x[a] = S[(FX + a) * cap + p];
-                v[a] = S[(FV + a) * cap + p];
-            }
+            for (int a = 0; a < 3; ++a) x[a] = S[(FX + a) * cap + p];
+            if (!FUSED) {
 #pragma unroll
-            for (int k = 0; k < 9; ++k) C[k] = S[(FC + k) * cap + p];
+                for (int a = 0; a < 3; ++a) v[a] = S[(FV + a) * cap + p];
+#pragma unroll
+                for (int k = 0; k < 9; ++k) C[k] = S[(FC + k) * cap + p];
+            }
             s = S[FS * cap + p];
             if (M.kind != MPM_WATER) {
 #pragma unroll
@@ -299,6 +311,31 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
         }
         int B[3] = {0, 0, 0};  // the particle's block at the last rebuild (its free zone)
         if (have) fsid_block(S[FSID * cap + p], B);
+        int ng = 0;  // fused G2P: nodes of the previous box staged in the tile's LDS
+        if constexpr (FUSED) {
+            const int4 bb = box[c];  // this chunk's tile box of the previous substep
+            const int lg[3] = {bb.x & 1023, (bb.x >> 10) & 1023, bb.x >> 20};
+            const int eg[3] = {bb.y & 255, (bb.y >> 8) & 255, bb.y >> 16};
+            ng = eg[0] * eg[1] * eg[2];
+            if (ng > 2 * CT) ng = 0;  // the tile holds 2 CT float4
+            float4* tv = reinterpret_cast<float4*>(tq);
+            const float4* vels = vel + (int64_t)sc.brick_base * BLOCK_NODES;
+            load_node_box(tv, vels, P.NB, lg, eg, ng, tid, NT);
+            __syncthreads();
+            Stencil sg;
+            if (have && make_stencil(x, P, sg, err)) {
+                g2p_gather(sg, tv, vels, P.NB, lg, eg, ng, 4.0f * P.fn, v, C);
+                bool fin = true;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    x[a] += dt * v[a];
+                    S[(FX + a) * cap + p] = x[a];
+                    fin = fin && (fabsf(x[a]) < 1e30f) && (fabsf(v[a]) < 1e30f);
+                }
+                left = left || left_free_zone(x, P.fn, B);
+                if (!fin) err |= MPM_ERR_NONFINITE;
+            }
+        }
         bool sur_chunk = false;
         if constexpr (SURM != 0) {
             sur_chunk = sc.ret != 0 && M.kind == MPM_SNOW;  // uniform over the workgroup
@@ -365,6 +402,10 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
                 }
             }
             __syncthreads();
+            if constexpr (FUSED) {  // every gather is done: clear the staged node box, keeping the tile zero
+                for (int t = tid; t < 2 * ng; t += NT) tq[t] = 0.0;
+                __syncthreads();
+            }
             int hi[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
@@ -481,12 +522,44 @@ __global__ __launch_bounds__(NT) void k_p2g(float* __restrict__ S, int64_t cap, 
             __syncthreads();
         }
     }
+    if constexpr (FUSED) {
+        if (__ballot(left) != 0ull && (threadIdx.x & 63) == 0) {
+            if (__hip_atomic_load(&ctl[CTL_REBUILD], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
+                atomicExch(&ctl[CTL_REBUILD], 1) == 0 && host_flag)
+                __hip_atomic_store(host_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) ctl[CTL_STEP] += 1;  // the G2P part completed a substep
+    }
     if (err) atomicOr(&ctl[CTL_ERROR], (int)err);
     if (SURM != 0 && (threadIdx.x & 63) == 0) {
         if (n_sur) atomicAdd(&ctl64(ctl)[CTL64_SUR_PARTICLES], (unsigned long long)n_sur);
         if (n_fb) atomicAdd(&ctl64(ctl)[CTL64_SUR_FALLBACKS], (unsigned long long)n_fb);
     }
 }
+
+
+#define MPM_P2G_PARAMS                                                                                          \
+    float *__restrict__ S, int64_t cap, const Chunk *__restrict__ chunks, int *__restrict__ ctl,               \
+        float *__restrict__ acc, float4 *__restrict__ stage, int stage_nodes, int4 *__restrict__ box,          \
+        int *__restrict__ brick_state, int *__restrict__ ovf, int parity, Scenes T, int pending, int nbricks, \
+        int act, const float4 *__restrict__ vel, int *__restrict__ host_flag, int fb_limit
+#define MPM_P2G_ARGS \
+    S, cap, chunks, ctl, acc, stage, stage_nodes, box, brick_state, ovf, parity, T, pending, nbricks, act, vel, host_flag, fb_limit
+
+template <bool GLOBAL_ONLY, int NT, int SURM>
+__global__ __launch_bounds__(NT) void k_p2g(MPM_P2G_PARAMS) {
+    p2g_body<GLOBAL_ONLY, NT, SURM, false>(MPM_P2G_ARGS);
+}
+
+// The fused form holds the gathered v and C beside the P2G state; four
+// waves per SIMD (at most 128 VGPRs) keep it as resident as the plain form.
+template <int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_p2g_fused(MPM_P2G_PARAMS) {
+    p2g_body<false, NT, 0, true>(MPM_P2G_ARGS);
+}
+
+#undef MPM_P2G_PARAMS
+#undef MPM_P2G_ARGS
 
 }  // namespace
 
@@ -505,29 +578,28 @@ int p2g_grid_size(int cus, int chunk) {
 
 void enqueue_p2g(hipStream_t st, const Launch& L, const Scenes& T, float* S, int64_t cap, const Chunk* chunks,
                  int* ctl, GridBuffers& G, int* brick_state, int pending, int parity, int global_atomics,
-                 int nbricks, int chunk, int act) {
-#define MPM_LAUNCH_P2G(GO, NT, SU)                                                                              \
-    hipLaunchKernelGGL((k_p2g<GO, NT, SU>), dim3(L.p2g_grid), dim3(NT), 0, st, S, cap, chunks, ctl, G.acc,        \
-                       G.stage, G.stage_nodes, G.box, brick_state, G.ovf[parity], parity, T, pending,                 \
-                       nbricks, act)
-#define MPM_LAUNCH_P2G_NT(GO, SU)                        \
-    do {                                                 \
-        if (nt == 128)                                   \
-            MPM_LAUNCH_P2G(GO, 128, SU);                 \
-        else if (nt == 256)                              \
-            MPM_LAUNCH_P2G(GO, 256, SU);                 \
-        else                                             \
-            MPM_LAUNCH_P2G(GO, 512, SU);                 \
-    } while (0)
+                 int nbricks, int chunk, int act, int fused, int* host_flag, int fb_limit) {
     const int nt = chunk_threads(chunk);
     const int surm = T.sur_any;  // 0, 1 (closed form) or 2 (network)
-    if (global_atomics) {
+    auto launch = [&](auto kernel, int threads) {
+        hipLaunchKernelGGL(kernel, dim3(L.p2g_grid), dim3(threads), 0, st, S, cap, chunks, ctl, G.acc, G.stage,
+                           G.stage_nodes, G.box, brick_state, G.ovf[parity], parity, T, pending, nbricks, act, G.vel,
+                           host_flag, fb_limit);
+    };
+#define MPM_LAUNCH_P2G_NT(GO, SU)                                                              \
+    do {                                                                                       \
+        if (nt == 128) launch(k_p2g<GO, 128, SU>, 128);                                        \
+        else if (nt == 256) launch(k_p2g<GO, 256, SU>, 256);                                   \
+        else launch(k_p2g<GO, 512, SU>, 512);                                                  \
+    } while (0)
+    if (fused) {  // callers check: tile path, exact map
+        if (nt == 128) launch(k_p2g_fused<128>, 128); else if (nt == 256) launch(k_p2g_fused<256>, 256); else launch(k_p2g_fused<512>, 512);
+    } else if (global_atomics) {
         if (surm == 2) MPM_LAUNCH_P2G_NT(true, 2); else if (surm == 1) MPM_LAUNCH_P2G_NT(true, 1); else MPM_LAUNCH_P2G_NT(true, 0);
     } else {
         if (surm == 2) MPM_LAUNCH_P2G_NT(false, 2); else if (surm == 1) MPM_LAUNCH_P2G_NT(false, 1); else MPM_LAUNCH_P2G_NT(false, 0);
     }
 #undef MPM_LAUNCH_P2G_NT
-#undef MPM_LAUNCH_P2G
 }
 
 }  // namespace mpm

@@ -154,10 +154,10 @@ template <bool LDS_BOX, int NT>
 __global__ __launch_bounds__(NT) void k_g2p(float* __restrict__ S, int64_t cap, const Chunk* __restrict__ chunks,
                                             int* __restrict__ ctl, const float4* __restrict__ vel,
                                             const int4* __restrict__ box, int* __restrict__ host_flag, int parity,
-                                            int fb_limit, Scenes T, int act) {
+                                            int fb_limit, int report_zone, Scenes T, int act) {
     __shared__ float4 tv[LDS_BOX ? G2P_BOX : 1];
     unsigned err = 0;
-    bool left = blockIdx.x == 0 && threadIdx.x == 0 && ctl[CTL_FB + parity] > fb_limit;
+    bool left = report_zone && blockIdx.x == 0 && threadIdx.x == 0 && ctl[CTL_FB + parity] > fb_limit;
     int begin, end, stride;
     xcd_split(rank_limit(T, ctl, act, RE_CHUNK, CTL_NCHUNK), begin, end, stride);
     for (int c = begin; c < end; c += stride) {
@@ -188,94 +188,29 @@ __global__ __launch_bounds__(NT) void k_g2p(float* __restrict__ S, int64_t cap, 
             lo[2] = bb.x >> 20;
             nt = e[0] * e[1] * e[2];
             if (nt > G2P_BOX) nt = 0;
-            for (int t = threadIdx.x; t < nt; t += NT) {
-                const int gx = lo[0] + t % e[0], gy = lo[1] + (t / e[0]) % e[1], gz = lo[2] + t / (e[0] * e[1]);
-                tv[t] = vels[((((gz >> 2) + 1) * NB + ((gy >> 2) + 1)) * NB + ((gx >> 2) + 1)) * 64 + (gx & 3) +
-                             ((gy & 3) << 2) + ((gz & 3) << 4)];
-            }
+            load_node_box(tv, vels, NB, lo, e, nt, threadIdx.x, NT);
             __syncthreads();
         }
-        do {  // once, for this thread's particle
-            if (!mine) break;
+        Stencil st;
+        if (mine && make_stencil(x, P, st, err)) {
+            float vp[3], Cn[9];
+            g2p_gather(st, tv, vels, NB, lo, e, nt, c4, vp, Cn);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) S[(FC + k) * cap + p] = Cn[k];
+            bool fin = true;
+            float xn[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                xn[a] = x[a] + P.dt * vp[a];
+                S[(FV + a) * cap + p] = vp[a];
+                S[(FX + a) * cap + p] = xn[a];
+                fin = fin && (fabsf(xn[a]) < 1e30f) && (fabsf(vp[a]) < 1e30f);
+            }
             int B[3];  // the particle's block at the last rebuild (its free zone)
             fsid_block(fsid, B);
-            Stencil st;
-            if (!make_stencil(x, P, st, err)) continue;
-            int r[3];
-            bool inbox = nt > 0;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                r[a] = st.base[a] - lo[a];
-                inbox = inbox && r[a] >= 0 && r[a] + 2 < e[a];
-            }
-            float vp[3] = {0, 0, 0};
-            float Mo[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // sum w v_a o_b
-            if (inbox) {
-                const int tb = r[0] + e[0] * (r[1] + e[1] * r[2]);
-#pragma unroll
-                for (int o2 = 0; o2 < 3; ++o2)
-#pragma unroll
-                    for (int o1 = 0; o1 < 3; ++o1) {
-                        const float wyz = st.w[1][o1] * st.w[2][o2];
-                        const int row = tb + e[0] * (o1 + e[1] * o2);
-#pragma unroll
-                        for (int o0 = 0; o0 < 3; ++o0) {
-                            const float w = wyz * st.w[0][o0];
-                            const float4 g = tv[row + o0];
-                            const float wv[3] = {w * g.x, w * g.y, w * g.z};
-#pragma unroll
-                            for (int a = 0; a < 3; ++a) {
-                                vp[a] += wv[a];
-                                Mo[a * 3 + 0] += o0 * wv[a];
-                                Mo[a * 3 + 1] += o1 * wv[a];
-                                Mo[a * 3 + 2] += o2 * wv[a];
-                            }
-                        }
-                    }
-            } else {
-                int xo[3], yo[3], zo[3];
-                axis_offsets(st.base[0], 1, 0, xo);
-                axis_offsets(st.base[1], NB, 2, yo);
-                axis_offsets(st.base[2], NB * NB, 4, zo);
-#pragma unroll
-                for (int o2 = 0; o2 < 3; ++o2)
-#pragma unroll
-                    for (int o1 = 0; o1 < 3; ++o1) {
-                        const float wyz = st.w[1][o1] * st.w[2][o2];
-#pragma unroll
-                        for (int o0 = 0; o0 < 3; ++o0) {
-                            const float w = wyz * st.w[0][o0];
-                            const float4 g = vels[xo[o0] + yo[o1] + zo[o2]];
-                            const float wv[3] = {w * g.x, w * g.y, w * g.z};
-#pragma unroll
-                            for (int a = 0; a < 3; ++a) {
-                                vp[a] += wv[a];
-                                Mo[a * 3 + 0] += o0 * wv[a];
-                                Mo[a * 3 + 1] += o1 * wv[a];
-                                Mo[a * 3 + 2] += o2 * wv[a];
-                            }
-                        }
-                    }
-            }
-            // C' = 4/dx^2 sum w v (x_i - x_p)^T = (4/dx) (Mo - v' f^T)
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b2 = 0; b2 < 3; ++b2)
-                    S[(FC + a * 3 + b2) * cap + p] = c4 * (Mo[a * 3 + b2] - vp[a] * st.f[b2]);
-            bool fin = true;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const float xn = x[a] + P.dt * vp[a];
-                S[(FV + a) * cap + p] = vp[a];
-                S[(FX + a) * cap + p] = xn;
-                fin = fin && (fabsf(xn) < 1e30f) && (fabsf(vp[a]) < 1e30f);
-                // free zone: the cell code must stay within [4B-3, 4B+6]
-                const float cc = floorf(xn * P.fn - 0.5f) + 1.0f;
-                left = left || !(cc >= (float)(4 * B[a] - 3) && cc <= (float)(4 * B[a] + 6));
-            }
+            left = left || (report_zone && left_free_zone(xn, P.fn, B));
             if (!fin) err |= MPM_ERR_NONFINITE;
-        } while (false);
+        }
         if (LDS_BOX) __syncthreads();
     }
     if (__ballot(left) != 0ull && (threadIdx.x & 63) == 0) {
@@ -445,10 +380,10 @@ void enqueue_grid(hipStream_t st, const Launch& L, const Scenes& T, const BinBuf
 
 void enqueue_g2p(hipStream_t st, const Launch& L, const Scenes& T, float* S, int64_t cap, const Chunk* chunks,
                  int* ctl, const GridBuffers& G, int* host_flag, int lds_box, int parity, int fb_limit, int chunk,
-                 int act) {
+                 int act, int report_zone) {
 #define MPM_LAUNCH_G2P(LB, NT)                                                                                    \
     hipLaunchKernelGGL((k_g2p<LB, NT>), dim3(L.g2p_grid), dim3(NT), 0, st, S, cap, chunks, ctl, G.vel, G.box, \
-                       host_flag, parity, fb_limit, T, act)
+                       host_flag, parity, fb_limit, report_zone, T, act)
     const int nt = chunk_threads(chunk);
     if (lds_box) {
         if (nt == 128) MPM_LAUNCH_G2P(true, 128); else if (nt == 256) MPM_LAUNCH_G2P(true, 256); else MPM_LAUNCH_G2P(true, 512);

@@ -425,13 +425,22 @@ def test_binding_rejects_bad_arguments(torch_cuda):
 
 
 def test_profile_counts_launches(torch_cuda):
+    """Phases launched per substep: with the fused G2P, a substep's G2P runs
+    inside the next substep's P2G, and one G2P launch brings the state up to
+    date when it is read; without fusion (node-box gather off) every substep
+    launches its own G2P."""
     sc = scenes.jelly_cube(0)
-    sim = make_sim(torch_cuda, scenes.jelly_config())
-    sim.add_particles(scenes.JELLY, sc["x"])
-    sim.profile(0xF)
-    sim.substep(5)
-    prof = sim.profile_read()
-    assert prof["p2g"]["launches"] == 5 and prof["g2p"]["launches"] == 5 and prof["grid"]["launches"] == 5
-    assert prof["rebuild"]["launches"] == 1
-    assert all(prof[k]["ms"] > 0 for k in ("p2g", "grid", "g2p"))
-    sim.close()
+    for flags, g2p_before, g2p_after in ((0, 0, 1), (0x10, 5, 5)):
+        sim = make_sim(torch_cuda, scenes.jelly_config(), flags=flags)
+        sim.add_particles(scenes.JELLY, sc["x"])
+        sim.profile(0xF)
+        sim.substep(5)
+        prof = sim.profile_read()
+        assert prof["p2g"]["launches"] == 5 and prof["grid"]["launches"] == 5
+        assert prof["g2p"]["launches"] == g2p_before, flags
+        assert prof["rebuild"]["launches"] == 1
+        sim.read_particles()
+        prof = sim.profile_read()
+        assert prof["g2p"]["launches"] == g2p_after, flags
+        assert all(prof[k]["ms"] > 0 for k in ("p2g", "grid", "g2p"))
+        sim.close()
