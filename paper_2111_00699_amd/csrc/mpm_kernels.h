@@ -66,26 +66,44 @@ __device__ __forceinline__ void axis_offsets(int base, int blockstride, int loca
     }
 }
 
+// ------------------------------------------------------------ node boxes
+// Padded layout of a node box of ext0 x ext1 x ext2 nodes in LDS: node
+// (x, y, z) at x + R y + Q z with the row pitch R the smallest of 4, 12, 20,
+// 28, ... that holds a row (so R >= ext0 and R = 4 or 12 mod 16) and the
+// plane pitch Q = 8 (mod 16).  With the round-ordered chunks, the 16 lanes an
+// LDS access serves together hold cells x in 0..3, y in {y, y+1}, z in
+// {z, z+1}; their addresses x + R y' + Q z' are 16 different values mod 16
+// for every stencil offset, so 8-byte (FP64) and 16-byte (float4) accesses
+// meet no bank conflicts.  (A chunk of several blocks has a box up to 16
+// nodes wide.)
+__device__ __forceinline__ int pitch_row(int e0) { return e0 <= 4 ? 4 : ((e0 + 3) & ~7) + 4; }
+__device__ __forceinline__ int pitch_plane(int R, int e1) {
+    const int q = R * e1;
+    return q + ((8 - (q & 15)) & 15);
+}
+
 // ------------------------------------------------------------ G2P pieces
 // A chunk's node box (origin lo, extent e per axis, from its P2G tile) as a
-// tight float4 array tv[x + e0 (y + e1 z)] of grid velocities, loaded by the
-// workgroup's threads (vels: the scene's node velocities).
+// float4 array tv[x + R y + Q z] of grid velocities (R, Q: the row and plane
+// pitches), loaded by the workgroup's threads (vels: the scene's node
+// velocities; nt = e0 e1 e2 nodes).
 __device__ __forceinline__ void load_node_box(float4* tv, const float4* vels, int NB, const int lo[3],
-                                              const int e[3], int nt, int tid, int nthreads) {
+                                              const int e[3], int nt, int R, int Q, int tid, int nthreads) {
     for (int t = tid; t < nt; t += nthreads) {
-        const int gx = lo[0] + t % e[0], gy = lo[1] + (t / e[0]) % e[1], gz = lo[2] + t / (e[0] * e[1]);
-        tv[t] = vels[((((gz >> 2) + 1) * NB + ((gy >> 2) + 1)) * NB + ((gx >> 2) + 1)) * 64 + (gx & 3) +
-                     ((gy & 3) << 2) + ((gz & 3) << 4)];
+        const int x = t % e[0], y = (t / e[0]) % e[1], z = t / (e[0] * e[1]);
+        const int gx = lo[0] + x, gy = lo[1] + y, gz = lo[2] + z;
+        tv[x + R * y + Q * z] = vels[((((gz >> 2) + 1) * NB + ((gy >> 2) + 1)) * NB + ((gx >> 2) + 1)) * 64 +
+                                     (gx & 3) + ((gy & 3) << 2) + ((gz & 3) << 4)];
     }
 }
 
 // G2P of one particle with stencil st: v' = sum w v_i and
 // C' = 4/dx^2 sum w v_i (x_i - x_p)^T, gathered from the node box tv
-// (nt > 0 nodes, origin lo, extent e) when the stencil lies inside it, else
-// from the dense node velocities.  c4 = 4/dx.
+// (nt > 0 nodes, origin lo, extent e, pitches R, Q) when the stencil lies
+// inside it, else from the dense node velocities.  c4 = 4/dx.
 __device__ __forceinline__ void g2p_gather(const Stencil& st, const float4* tv, const float4* vels, int NB,
-                                           const int lo[3], const int e[3], int nt, float c4, float vp[3],
-                                           float Cn[9]) {
+                                           const int lo[3], const int e[3], int nt, int R, int Q, float c4,
+                                           float vp[3], float Cn[9]) {
     int r[3];
     bool inbox = nt > 0;
 #pragma unroll
@@ -97,13 +115,13 @@ __device__ __forceinline__ void g2p_gather(const Stencil& st, const float4* tv, 
 #pragma unroll
     for (int a = 0; a < 3; ++a) vp[a] = 0.0f;
     if (inbox) {
-        const int tb = r[0] + e[0] * (r[1] + e[1] * r[2]);
+        const int tb = r[0] + R * r[1] + Q * r[2];
 #pragma unroll
         for (int o2 = 0; o2 < 3; ++o2)
 #pragma unroll
             for (int o1 = 0; o1 < 3; ++o1) {
                 const float wyz = st.w[1][o1] * st.w[2][o2];
-                const int row = tb + e[0] * (o1 + e[1] * o2);
+                const int row = tb + R * o1 + Q * o2;
 #pragma unroll
                 for (int o0 = 0; o0 < 3; ++o0) {
                     const float w = wyz * st.w[0][o0];

@@ -42,19 +42,8 @@ namespace {
 
 constexpr int CT = 1024;  // LDS tile capacity in nodes (padded layout, below)
 
-// LDS tile layout of a box of ext0 x ext1 x ext2 nodes: node (x, y, z) at
-// x + R y + Q z with the row pitch R the smallest of 4, 12, 20, 28, ... that
-// holds a row (so R >= ext0 and R = 4 or 12 mod 16) and the plane pitch
-// Q = 8 (mod 16).  With the round-ordered chunks, the 16 lanes an LDS access
-// serves together hold cells x in 0..3, y in {y, y+1}, z in {z, z+1}; their
-// FP64 addresses x + R y' + Q z' then fall on 16 different bank pairs for
-// every stencil offset.  (A chunk of several blocks has a box up to 16 nodes
-// wide.)
-__device__ __forceinline__ int pitch_row(int e0) { return e0 <= 4 ? 4 : ((e0 + 3) & ~7) + 4; }
-__device__ __forceinline__ int pitch_plane(int R, int e1) {
-    const int q = R * e1;
-    return q + ((8 - (q & 15)) & 15);
-}
+// LDS tile layout: the padded node-box layout (pitch_row, pitch_plane in
+// mpm_kernels.h), FP64 channels.
 
 // ------------------------------------------------ snow return map without SVD
 // Eigenvalues of the symmetric b = [b0 b1 b2; . b3 b4; . . b5] as
@@ -311,20 +300,22 @@ __device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, con
         }
         int B[3] = {0, 0, 0};  // the particle's block at the last rebuild (its free zone)
         if (have) fsid_block(S[FSID * cap + p], B);
-        int ng = 0;  // fused G2P: nodes of the previous box staged in the tile's LDS
+        int ng = 0, ngs = 0;  // fused G2P: nodes of the previous box, and the LDS float4 they span
         if constexpr (FUSED) {
             const int4 bb = box[c];  // this chunk's tile box of the previous substep
             const int lg[3] = {bb.x & 1023, (bb.x >> 10) & 1023, bb.x >> 20};
             const int eg[3] = {bb.y & 255, (bb.y >> 8) & 255, bb.y >> 16};
             ng = eg[0] * eg[1] * eg[2];
-            if (ng > 2 * CT) ng = 0;  // the tile holds 2 CT float4
+            const int Rg = pitch_row(eg[0]), Qg = pitch_plane(Rg, eg[1]);  // padded: no bank conflicts
+            ngs = ng > 0 ? Qg * eg[2] : 0;
+            if (ngs > 2 * CT) ng = ngs = 0;  // the tile holds 2 CT float4
             float4* tv = reinterpret_cast<float4*>(tq);
             const float4* vels = vel + (int64_t)sc.brick_base * BLOCK_NODES;
-            load_node_box(tv, vels, P.NB, lg, eg, ng, tid, NT);
+            load_node_box(tv, vels, P.NB, lg, eg, ng, Rg, Qg, tid, NT);
             __syncthreads();
             Stencil sg;
             if (have && make_stencil(x, P, sg, err)) {
-                g2p_gather(sg, tv, vels, P.NB, lg, eg, ng, 4.0f * P.fn, v, C);
+                g2p_gather(sg, tv, vels, P.NB, lg, eg, ng, Rg, Qg, 4.0f * P.fn, v, C);
                 bool fin = true;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
@@ -403,7 +394,7 @@ __device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, con
             }
             __syncthreads();
             if constexpr (FUSED) {  // every gather is done: clear the staged node box, keeping the tile zero
-                for (int t = tid; t < 2 * ng; t += NT) tq[t] = 0.0;
+                for (int t = tid; t < 2 * ngs; t += NT) tq[t] = 0.0;
                 __syncthreads();
             }
             int hi[3];

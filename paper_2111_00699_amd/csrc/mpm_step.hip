@@ -188,13 +188,13 @@ __global__ __launch_bounds__(NT) void k_g2p(float* __restrict__ S, int64_t cap, 
             lo[2] = bb.x >> 20;
             nt = e[0] * e[1] * e[2];
             if (nt > G2P_BOX) nt = 0;
-            load_node_box(tv, vels, NB, lo, e, nt, threadIdx.x, NT);
+            load_node_box(tv, vels, NB, lo, e, nt, e[0], e[0] * e[1], threadIdx.x, NT);  // tight layout
             __syncthreads();
         }
         Stencil st;
         if (mine && make_stencil(x, P, st, err)) {
             float vp[3], Cn[9];
-            g2p_gather(st, tv, vels, NB, lo, e, nt, c4, vp, Cn);
+            g2p_gather(st, tv, vels, NB, lo, e, nt, e[0], e[0] * e[1], c4, vp, Cn);
 #pragma unroll
             for (int k = 0; k < 9; ++k) S[(FC + k) * cap + p] = Cn[k];
             bool fin = true;
