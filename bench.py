@@ -44,14 +44,11 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0
 # G2P reads x (12 B) and writes x, v, C (60 B).
 P2G_BYTES = {"jelly": 132, "snow": 140, "water": 68}
 G2P_BYTES = 72
-# The snow scene's substeps run P2G fused with the previous substep's G2P:
-# x, F_E, J_P and the block word in (56 B), x, F_E, J_P out (52 B).
-P2G_FUSED_BYTES = {"snow": 108}
 
-# HBM bytes per (fused) P2G launch measured with rocprofv3 counters (FETCH_SIZE
-# x 2.0 + WRITE_SIZE x 1.0, the factors a plain 1 GiB copy reads back,
-# averaged over the 334 launches of the first frame);
-# profiles/substep_snow256_counters.md.
+# HBM bytes per P2G launch measured with rocprofv3 counters (FETCH_SIZE x 2.0
+# + WRITE_SIZE x 1.0, the factors a plain 1 GiB copy reads back, averaged over
+# the 334 launches of the first frame); profiles/substep_snow256_counters.md.
+# (The snow scene's 1.28M particles keep G2P a launch of its own.)
 # The figure belongs to the P2G sources whose hash is stored beside it: after
 # any change to them the bench reports traffic as null until it is measured
 # again.
@@ -360,7 +357,7 @@ def main():
     value = N * substeps / (ms * 1e-3)
     p2g = prof["p2g"]
     p2g_avg_ms = p2g["ms"] / max(p2g["launches"], 1)
-    achieved = P2G_FUSED_BYTES["snow"] * N / (p2g_avg_ms * 1e-3) / 1e9
+    achieved = P2G_BYTES["snow"] * N / (p2g_avg_ms * 1e-3) / 1e9
     rebuilds = st1["rebuilds"] - st0["rebuilds"]
     out = {
         "metric": "particle-substeps/s",
@@ -381,12 +378,11 @@ def main():
                    "particles": N, "grid": cfg["n"], "substeps_per_frame": nsub, "frames_timed": args.steps,
                    "rebuilds_in_timed_frames": rebuilds,
                    "substeps_per_rebuild": substeps / max(rebuilds, 1), "chunk": args.chunk or 256},
-        "roofline": {"kernel": "p2g (with the previous substep's G2P fused in)", "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "roofline": {"kernel": "p2g", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": p2g_traffic_bytes(), "traffic_unit": "HBM bytes per launch",
                      "avg_launch_us": p2g_avg_ms * 1e3, "launches": p2g["launches"],
-                     "bytes_per_particle": P2G_FUSED_BYTES["snow"]},
+                     "bytes_per_particle": P2G_BYTES["snow"]},
         # the bound P2G actually meets: its LDS FP64 atomics against their measured peak rate
         "roofline_lds": {"kernel": "p2g", "bound": "lds_fp64_atomics",
                          "achieved": P2G_LDS_ATOMICS_PER_PARTICLE * N / (p2g_avg_ms * 1e-3),

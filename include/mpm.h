@@ -81,6 +81,9 @@ typedef enum { MPM_BC_STICKY = 0, MPM_BC_SLIP = 1, MPM_BC_SEPARATE = 2 } mpm_bc;
                                             read (particles that leave their zone transfer through global
                                             atomics).  Needs config.stream != 0.  A graph is recorded again
                                             after mpm_add_particles, a new frame_dt or a new chunk size. */
+#define MPM_FLAG_FUSED_G2P 0x40u        /* always run each substep's G2P inside the next substep's P2G
+                                            (see mpm_substep)                                          */
+#define MPM_FLAG_SEPARATE_G2P 0x80u     /* never: every substep launches its own G2P               */
 
 #define MPM_MAX_SCENES 256
 
@@ -177,14 +180,16 @@ int mpm_add_particles(mpm_ctx* ctx, int32_t scene, const mpm_material* mat, int6
 
 /* Enqueue `nsteps` substeps of every scene.  Each is: [rebuild-mapping + sort
  * when a particle left its free zone] -> P2G -> grid update -> G2P, one launch
- * per phase for all scenes.  Unless MPM_FLAG_P2G_GLOBAL_ATOMICS,
+ * per phase for all scenes.  A substep's G2P runs inside the next substep's
+ * P2G launch (paper, "Merge Kernels": G2P2G) when the context holds fewer
+ * than 100,000 particles (as in the paper) or MPM_FLAG_FUSED_G2P is set --
+ * unless MPM_FLAG_SEPARATE_G2P, MPM_FLAG_P2G_GLOBAL_ATOMICS,
  * MPM_FLAG_REBUILD_EVERY_STEP, MPM_FLAG_G2P_GLOBAL_GATHER,
- * MPM_FLAG_FRAME_GRAPHS or a learned / closed-form return map is in use, a
- * substep's G2P runs inside the next substep's P2G launch (paper, "Merge
- * Kernels": G2P2G); calls that read, extend, sample or rebuild the state run
- * the outstanding G2P first, so what they see does not change.  The host
- * waits for the device only to keep at most `lag` substeps in flight, so
- * that it can read the device's rebuild flag; it never drains the stream.  */
+ * MPM_FLAG_FRAME_GRAPHS or a learned / closed-form return map is in use.
+ * Calls that read, extend, sample or rebuild the state run the outstanding
+ * G2P first, so what they see does not change.  The host waits for the
+ * device only to keep at most `lag` substeps in flight, so that it can read
+ * the device's rebuild flag; it never drains the stream.                    */
 int mpm_substep(mpm_ctx* ctx, int32_t nsteps);
 
 /* Advance one frame (frame_dt > 0): scene s runs ceil(frame_dt/dt_s)

@@ -452,10 +452,16 @@ int check_error_word(mpm_ctx* c) {
 
 // Whether a substep may leave its G2P to the next substep's P2G (the fused
 // kernel needs the LDS tile path, the exact return map and the node-box
-// gather).
+// gather).  By default only small systems fuse: the paper keeps G2P2G below
+// 100K particles, and on gfx950 it saves 10% of a 32K-particle substep
+// (mostly a launch) but nothing at 1.28M particles.
+constexpr int64_t FUSE_BELOW = 100000;
 bool fusion_allowed(const mpm_ctx* c) {
-    return !c->sur_any && !(c->cfg.flags & (MPM_FLAG_P2G_GLOBAL_ATOMICS | MPM_FLAG_REBUILD_EVERY_STEP |
-                                            MPM_FLAG_G2P_GLOBAL_GATHER | MPM_FLAG_FRAME_GRAPHS));
+    const bool wanted = (c->cfg.flags & MPM_FLAG_FUSED_G2P) ||
+                        (!(c->cfg.flags & MPM_FLAG_SEPARATE_G2P) && c->N < FUSE_BELOW);
+    return wanted && !c->sur_any &&
+           !(c->cfg.flags & (MPM_FLAG_P2G_GLOBAL_ATOMICS | MPM_FLAG_REBUILD_EVERY_STEP |
+                             MPM_FLAG_G2P_GLOBAL_GATHER | MPM_FLAG_FRAME_GRAPHS));
 }
 
 // Run the G2P that the last substep left to its successor (see g2p_due_act).

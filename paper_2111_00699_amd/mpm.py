@@ -20,7 +20,7 @@ BC = {"sticky": 0, "slip": 1, "separate": 2}
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -1, -2, -3, -4
 ERR_NONFINITE, ERR_DOMAIN, ERR_CAPACITY = 0x1, 0x2, 0x4
 FLAG_REBUILD_EVERY_STEP, FLAG_P2G_GLOBAL_ATOMICS, FLAG_MANUAL_REBUILD, FLAG_P2G_SORTED_LANES = 0x1, 0x2, 0x4, 0x8
-FLAG_G2P_GLOBAL_GATHER, FLAG_FRAME_GRAPHS = 0x10, 0x20
+FLAG_G2P_GLOBAL_GATHER, FLAG_FRAME_GRAPHS, FLAG_FUSED_G2P, FLAG_SEPARATE_G2P = 0x10, 0x20, 0x40, 0x80
 MAX_SCENES = 256
 PHASE_REBUILD, PHASE_P2G, PHASE_GRID, PHASE_G2P = 0x1, 0x2, 0x4, 0x8
 PHASES = ("rebuild", "p2g", "grid", "g2p")
