@@ -47,12 +47,13 @@ G2P_BYTES = 72
 
 # HBM bytes per P2G launch measured with rocprofv3 counters (FETCH_SIZE x 2.0
 # + WRITE_SIZE x 1.0, the factors a plain 1 GiB copy reads back, averaged over
-# the 334 launches of the first frame); profiles/substep_snow256_counters.md.
+# the 10,020 launches of the 30 timed frames of the default run);
+# profiles/substep_snow256_counters.md.
 # (The snow scene's 1.28M particles keep G2P a launch of its own.)
 # The figure belongs to the P2G sources whose hash is stored beside it: after
 # any change to them the bench reports traffic as null until it is measured
 # again.
-P2G_TRAFFIC = {"sources_sha256_16": "57389da052bdf9f3", "bytes": 201.86e6}
+P2G_TRAFFIC = {"sources_sha256_16": "69ba62b18d40ac90", "bytes": 218.26e6}
 P2G_SOURCES = ("paper_2111_00699_amd/csrc/mpm_p2g.hip", "paper_2111_00699_amd/csrc/mpm_internal.h",
                "paper_2111_00699_amd/csrc/mpm_kernels.h", "paper_2111_00699_amd/csrc/mpm_api.hip")
 
