@@ -6,13 +6,20 @@ its free zone, P2G with the fused snow return map and stress, grid update
 with boundary conditions, G2P with the free-zone test).  Prints ONE JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--workload snow|fountain|batched|surrogate]
 
-`value` is particle-substeps per second over the K timed frames (inputs
-resident in HBM before timing starts).  `roofline` covers the P2G kernel,
-timed with HIP events on the library's stream during the timed frames,
-against the HBM peak; `roofline_lds` puts the same launches against the LDS
-FP64 atomic rate that bounds them; `cpu_baseline` times the FP64 oracle on
-the host on a bounded sample.
+By default K = 60 timed frames after W = 1 warmup frame, so `value` is the
+average over 60 frames of the falling, landing and settling snow, as the
+paper averages its frame costs.  `value` is particle-substeps per second over
+the K timed frames (inputs resident in HBM before timing starts).
+`roofline` covers the P2G kernel, timed with HIP events on the library's
+stream during the timed frames, against the HBM peak (`frac` from the
+algorithmic bytes, `traffic_frac` from the measured HBM bytes);
+`roofline_lds` puts the same launches against the LDS FP64 atomic rate that
+bounds them; `cpu_baseline` times the FP64 oracle on the host on a bounded
+sample.  The other workloads print their own line: the fountain (ms per
+frame against the growing particle count), 256 batched scenes, and the
+learned constitutive map.
 """
 import argparse
 import json
@@ -47,13 +54,13 @@ G2P_BYTES = 72
 
 # HBM bytes per P2G launch measured with rocprofv3 counters (FETCH_SIZE x 2.0
 # + WRITE_SIZE x 1.0, the factors a plain 1 GiB copy reads back, averaged over
-# the 10,020 launches of the 30 timed frames of the default run);
+# the 20,040 launches of the 60 timed frames of the default run);
 # profiles/substep_snow256_counters.md.
 # (The snow scene's 1.28M particles keep G2P a launch of its own.)
 # The figure belongs to the P2G sources whose hash is stored beside it: after
 # any change to them the bench reports traffic as null until it is measured
 # again.
-P2G_TRAFFIC = {"sources_sha256_16": "69ba62b18d40ac90", "bytes": 218.26e6}
+P2G_TRAFFIC = {"sources_sha256_16": "69ba62b18d40ac90", "bytes": 221.85e6}
 P2G_SOURCES = ("paper_2111_00699_amd/csrc/mpm_p2g.hip", "paper_2111_00699_amd/csrc/mpm_internal.h",
                "paper_2111_00699_amd/csrc/mpm_kernels.h", "paper_2111_00699_amd/csrc/mpm_api.hip")
 
@@ -172,6 +179,87 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+FOUNTAIN_MAX = 143500
+
+
+def bench_fountain(args):
+    """The fountain: water emitted from the inlet once per 1/60 s frame until
+    143,500 particles, on a 128^3 grid, frames of 167 substeps.  Reports ms per
+    frame against the particle count, once with G2P fused into the next P2G
+    below 100,000 particles (the default) and once with G2P kept separate."""
+    import torch
+
+    from paper_2111_00699_amd import mpm, scenes
+
+    torch.cuda.set_device(0)
+    cfg = scenes.fountain_config()
+    nsub = cfg["substeps_per_frame"]
+    frames = args.steps
+    emissions = []
+    total = 0
+    for f in range(frames):
+        if total >= FOUNTAIN_MAX:
+            break
+        e = scenes.fountain_emission(f)
+        keep = min(e["x"].shape[1], FOUNTAIN_MAX - total)
+        emissions.append({"x": np.ascontiguousarray(e["x"][:, :keep]), "v": np.ascontiguousarray(e["v"][:, :keep])})
+        total += keep
+    log(f"[bench] fountain: {len(emissions)} emitting frames, {total} particles, {frames} frames of {nsub} substeps")
+    stream = torch.cuda.current_stream()
+    runs = {}
+    for name, flags in (("fused_below_100k", 0), ("separate_g2p", mpm.FLAG_SEPARATE_G2P)):
+        sim = mpm.Sim(cfg["n"], cfg["dt"], bc=cfg["bc"], bc_cells=cfg["bc_cells"], gravity=cfg["gravity"],
+                      capacity=2 * total + 256, flags=flags | args.flags, chunk=args.chunk)
+        # warmup: one frame of a throwaway emission, then a fresh context
+        sim.add_particles(scenes.WATER, emissions[0]["x"], v=emissions[0]["v"])
+        sim.substep(nsub)
+        sim.synchronize()
+        sim.close()
+        sim = mpm.Sim(cfg["n"], cfg["dt"], bc=cfg["bc"], bc_cells=cfg["bc_cells"], gravity=cfg["gravity"],
+                      capacity=2 * total + 256, flags=flags | args.flags, chunk=args.chunk)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(frames + 1)]
+        counts = []
+        n = 0
+        w0 = time.perf_counter()
+        ev[0].record(stream)
+        for f in range(frames):
+            if f < len(emissions):
+                sim.add_particles(scenes.WATER if f == 0 else None, emissions[f]["x"], v=emissions[f]["v"])
+                n += emissions[f]["x"].shape[1]
+            sim.substep(nsub)
+            ev[f + 1].record(stream)
+            counts.append(n)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        ms = [ev[f].elapsed_time(ev[f + 1]) for f in range(frames)]
+        st = sim.stats()
+        sim.close()
+        gpu_ms = sum(ms)
+        work = nsub * sum(counts)
+        runs[name] = {"ms_total": max(gpu_ms, wall * 1e3), "gpu_event_ms": gpu_ms, "wall_ms": wall * 1e3,
+                      "value": work / (max(gpu_ms, wall * 1e3) * 1e-3), "rebuilds": st["rebuilds"],
+                      "frames": [[f + 1, counts[f], round(ms[f], 3)] for f in range(frames)]}
+        log(f"[bench] fountain {name}: {runs[name]['ms_total'] / frames:.2f} ms per frame on average")
+    r = runs["fused_below_100k"]
+    out = {
+        "metric": "particle-substeps/s",
+        "value": r["value"],
+        "unit": "particle-substeps/s",
+        "n_gpus": 1, "steps": frames, "warmup": 1,
+        "ms_per_step": r["ms_total"] / frames, "ms_per_frame": r["ms_total"] / frames,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "fountain: water (J-based EOS, bulk modulus 1e4) emitted once per frame at 3 m/s "
+                               "from a 0.05-radius inlet until 143,500 particles, 128^3 grid, separating walls, "
+                               f"{nsub} substeps per 1/60 s frame",
+                   "particles_final": total, "emitting_frames": len(emissions), "grid": cfg["n"],
+                   "substeps_per_frame": nsub, "fuse_below": 100000},
+        "runs": runs,
+        "fused_vs_separate": runs["separate_g2p"]["ms_total"] / r["ms_total"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_surrogate(args):
     """The learned snow return map on the snow scene: trained on the GPU from
     exact-path runs of snow scenes with other sphere seeds (4 and 40), then
@@ -284,12 +372,13 @@ def bench_surrogate(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30, help="timed frames")
-    ap.add_argument("--warmup", type=int, default=2, help="untimed frames")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed frames (snow and fountain 60, as the paper averages; batched 10; surrogate 5)")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed frames")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--flags", type=int, default=0)
-    ap.add_argument("--workload", choices=("snow", "batched", "surrogate"), default="snow")
+    ap.add_argument("--workload", choices=("snow", "batched", "surrogate", "fountain"), default="snow")
     ap.add_argument("--train-snapshots", type=int, default=4, help="surrogate: training snapshots per scene")
     ap.add_argument("--train-steps", type=int, default=20000, help="surrogate: Adam steps")
     ap.add_argument("--sur-tol", type=float, default=2e-3, help="surrogate: residual tolerance")
@@ -297,6 +386,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 4 times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = {"snow": 60, "fountain": 60, "batched": 10, "surrogate": 5}[args.workload]
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
@@ -318,6 +409,9 @@ def main():
         return
     if args.workload == "surrogate":
         bench_surrogate(args)
+        return
+    if args.workload == "fountain":
+        bench_fountain(args)
         return
 
     from paper_2111_00699_amd import mpm, scenes
@@ -360,6 +454,7 @@ def main():
     p2g_avg_ms = p2g["ms"] / max(p2g["launches"], 1)
     achieved = P2G_BYTES["snow"] * N / (p2g_avg_ms * 1e-3) / 1e9
     rebuilds = st1["rebuilds"] - st0["rebuilds"]
+    traffic = p2g_traffic_bytes()
     out = {
         "metric": "particle-substeps/s",
         "value": value,
@@ -375,13 +470,15 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "snow: 12 seeded spheres dropped in a 256^3 grid, snow plasticity with "
-                               "hardening, 334 substeps of 4.99e-5 s per 1/60 s frame",
+                               "hardening, 334 substeps of 4.99e-5 s per 1/60 s frame, "
+                               f"frames {args.warmup + 1}-{args.warmup + args.steps} timed",
                    "particles": N, "grid": cfg["n"], "substeps_per_frame": nsub, "frames_timed": args.steps,
                    "rebuilds_in_timed_frames": rebuilds,
                    "substeps_per_rebuild": substeps / max(rebuilds, 1), "chunk": args.chunk or 256},
         "roofline": {"kernel": "p2g", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": p2g_traffic_bytes(), "traffic_unit": "HBM bytes per launch",
+                     "traffic": traffic, "traffic_unit": "HBM bytes per launch",
+                     "traffic_frac": (traffic / (p2g_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None,
                      "avg_launch_us": p2g_avg_ms * 1e3, "launches": p2g["launches"],
                      "bytes_per_particle": P2G_BYTES["snow"]},
         # the bound P2G actually meets: its LDS FP64 atomics against their measured peak rate
