@@ -678,6 +678,7 @@ int mpm_create(const mpm_config* cfg, mpm_ctx** out) {
     };
     const size_t nb = (size_t)c->nbricks;
     bool ok = hipMalloc(&c->G.acc, sizeof(float) * 4 * 64 * nb) == hipSuccess &&
+              hipMalloc(&c->G.acc_dirty, sizeof(int) * nb) == hipSuccess &&
               hipMalloc(&c->G.vel, sizeof(float4) * 64 * nb) == hipSuccess &&
               hipMalloc(&c->G.stamp, sizeof(int) * nb) == hipSuccess &&
               hipMalloc(&c->G.ovf[0], sizeof(int) * nb) == hipSuccess &&
@@ -697,6 +698,7 @@ int mpm_create(const mpm_config* cfg, mpm_ctx** out) {
         return bail(MPM_ENOMEM);
     }
     if (hipMemsetAsync(c->G.acc, 0, sizeof(float) * 4 * 64 * nb, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->G.acc_dirty, 0, sizeof(int) * nb, c->stream) != hipSuccess ||
         hipMemsetAsync(c->G.vel, 0, sizeof(float4) * 64 * nb, c->stream) != hipSuccess ||
         hipMemsetAsync(c->G.stamp, 0xff, sizeof(int) * nb, c->stream) != hipSuccess ||
         hipMemsetAsync(c->B.brick_state, 0, sizeof(int) * nb, c->stream) != hipSuccess ||
@@ -739,6 +741,7 @@ int mpm_destroy(mpm_ctx* c) {
     drop_graphs(c);
     free_particle_buffers(c);
     (void)hipFree(c->G.acc);
+    (void)hipFree(c->G.acc_dirty);
     (void)hipFree(c->G.vel);
     (void)hipFree(c->G.stamp);
     (void)hipFree(c->G.ovf[0]);

@@ -170,6 +170,8 @@ void enqueue_copy_codes(hipStream_t st, uint32_t* dst, const uint32_t* src, int 
 // Substep kernels (mpm_step.hip).
 struct GridBuffers {
     float* acc;     // [NB^3 * 64 * 4] (m, px, py, pz) accumulators, zero between substeps
+    int* acc_dirty; // [NB^3] 1 where P2G's global atomics wrote the block's accumulators this
+                    // substep; the grid update reads and clears only those blocks' accumulators
     float4* vel;    // [NB^3 * 64] (vx, vy, vz, m) after the grid update
     int* stamp;     // [NB^3] substep index of the last update of each block
     int* ovf[2];    // overflow block lists, by substep parity

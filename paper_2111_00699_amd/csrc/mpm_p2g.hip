@@ -232,7 +232,8 @@ __device__ void snow_without_svd(const mlp::NetLds16* net, float* stage, const S
 // fb_limit serve that G2P.
 template <bool GLOBAL_ONLY, int NT, int SURM, bool FUSED>
 __device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, const Chunk* __restrict__ chunks,
-                                         int* __restrict__ ctl, float* __restrict__ acc, float4* __restrict__ stage,
+                                         int* __restrict__ ctl, float* __restrict__ acc,
+                                         int* __restrict__ acc_dirty, float4* __restrict__ stage,
                                          int stage_nodes, int4* __restrict__ box, int* __restrict__ brick_state,
                                          int* __restrict__ ovf, int parity, const Scenes& T, int pending,
                                          int nbricks, int act, const float4* __restrict__ vel,
@@ -473,6 +474,15 @@ __device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, con
                 axis_offsets(st.base[1], P.NB, 2, yo);
                 axis_offsets(st.base[2], P.NB * P.NB, 4, zo);
                 float* accs = acc + 4 * (int64_t)sc.brick_base * BLOCK_NODES;
+                {  // the stencil's nodes lie in blocks (base >> 2) + 1 and ((base + 2) >> 2) + 1 per axis
+                    int* dirty = acc_dirty + sc.brick_base;
+                    const int bl[3] = {(st.base[0] >> 2) + 1, (st.base[1] >> 2) + 1, (st.base[2] >> 2) + 1};
+                    const int bh[3] = {((st.base[0] + 2) >> 2) + 1, ((st.base[1] + 2) >> 2) + 1,
+                                       ((st.base[2] + 2) >> 2) + 1};
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        dirty[((k & 4 ? bh[2] : bl[2]) * P.NB + (k & 2 ? bh[1] : bl[1])) * P.NB + (k & 1 ? bh[0] : bl[0])] = 1;
+                }
 #pragma unroll
                 for (int o2 = 0; o2 < 3; ++o2)
 #pragma unroll
@@ -531,11 +541,13 @@ __device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, con
 
 #define MPM_P2G_PARAMS                                                                                          \
     float *__restrict__ S, int64_t cap, const Chunk *__restrict__ chunks, int *__restrict__ ctl,               \
-        float *__restrict__ acc, float4 *__restrict__ stage, int stage_nodes, int4 *__restrict__ box,          \
+        float *__restrict__ acc, int *__restrict__ acc_dirty, float4 *__restrict__ stage, int stage_nodes,     \
+        int4 *__restrict__ box,                                                                                 \
         int *__restrict__ brick_state, int *__restrict__ ovf, int parity, Scenes T, int pending, int nbricks, \
         int act, const float4 *__restrict__ vel, int *__restrict__ host_flag, int fb_limit
 #define MPM_P2G_ARGS \
-    S, cap, chunks, ctl, acc, stage, stage_nodes, box, brick_state, ovf, parity, T, pending, nbricks, act, vel, host_flag, fb_limit
+    S, cap, chunks, ctl, acc, acc_dirty, stage, stage_nodes, box, brick_state, ovf, parity, T, pending, nbricks, act, vel, \
+        host_flag, fb_limit
 
 template <bool GLOBAL_ONLY, int NT, int SURM>
 __global__ __launch_bounds__(NT) void k_p2g(MPM_P2G_PARAMS) {
@@ -573,7 +585,7 @@ void enqueue_p2g(hipStream_t st, const Launch& L, const Scenes& T, float* S, int
     const int nt = chunk_threads(chunk);
     const int surm = T.sur_any;  // 0, 1 (closed form) or 2 (network)
     auto launch = [&](auto kernel, int threads) {
-        hipLaunchKernelGGL(kernel, dim3(L.p2g_grid), dim3(threads), 0, st, S, cap, chunks, ctl, G.acc, G.stage,
+        hipLaunchKernelGGL(kernel, dim3(L.p2g_grid), dim3(threads), 0, st, S, cap, chunks, ctl, G.acc, G.acc_dirty, G.stage,
                            G.stage_nodes, G.box, brick_state, G.ovf[parity], parity, T, pending, nbricks, act, G.vel,
                            host_flag, fb_limit);
     };

@@ -32,7 +32,8 @@ namespace {
 // rebuild whose box (this substep's) holds the node, in chunk order, then
 // v = p/m + dt g where m > 0 (else 0) and the wall condition; writes (v, m),
 // clears the accumulator, and stamps the block.
-__global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, float4* __restrict__ vel,
+__global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, int* __restrict__ acc_dirty,
+                                             float4* __restrict__ vel,
                                              const int* __restrict__ active, int* __restrict__ ctl,
                                              const int* __restrict__ ovf, int* __restrict__ brick_state,
                                              int* __restrict__ stamp, const int* __restrict__ reg_n,
@@ -55,7 +56,9 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, float4* __
         const int bx = lb % NB, by = (lb / NB) % NB, bz = lb / (NB * NB);
         const int n0 = 4 * (bx - 1), n1 = 4 * (by - 1), n2 = 4 * (bz - 1);  // first node of the block
         const int g[3] = {n0 + lx, n1 + ly, n2 + lz};
-        float4 a = acc4[(int64_t)b * 64 + lane];
+        // the block's global-atomic sums, if P2G sent any here this substep
+        const bool dirty = __builtin_amdgcn_readfirstlane(acc_dirty[b]) != 0;
+        float4 a = dirty ? acc4[(int64_t)b * 64 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
         if (it < nact) {  // a physical block: gather the tiles registered with it (at most REG_MAX)
             const int m = min(__builtin_amdgcn_readfirstlane(reg_n[it]), REG_MAX);
             for (int rb = 0; rb < m; rb += 64) {  // 64 registrations a round, one per lane
@@ -128,9 +131,10 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, float4* __
             }
         }
         vel[(int64_t)b * 64 + lane] = make_float4(v[0], v[1], v[2], a.x);
-        acc4[(int64_t)b * 64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (dirty) acc4[(int64_t)b * 64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (lane == 0) {
             stamp[b] = step;
+            if (dirty) acc_dirty[b] = 0;
             if (it >= nact) brick_state[b] = 0;
         }
     }
@@ -374,7 +378,8 @@ void query_launch(Launch& L, int chunk) {
 
 void enqueue_grid(hipStream_t st, const Launch& L, const Scenes& T, const BinBuffers& B, int* ctl, GridBuffers& G,
                   int parity, int nbricks, int act) {
-    hipLaunchKernelGGL(k_grid, dim3(L.grid_grid), dim3(WG), 0, st, G.acc, G.vel, B.active, ctl, G.ovf[parity],
+    hipLaunchKernelGGL(k_grid, dim3(L.grid_grid), dim3(WG), 0, st, G.acc, G.acc_dirty, G.vel, B.active, ctl,
+                       G.ovf[parity],
                        B.brick_state, G.stamp, G.reg_n, G.reg, G.stage, G.box, parity, nbricks, T, act);
 }
 
