@@ -74,7 +74,7 @@ typedef enum { MPM_BC_STICKY = 0, MPM_BC_SLIP = 1, MPM_BC_SEPARATE = 2 } mpm_bc;
 #define MPM_FLAG_G2P_GLOBAL_GATHER 0x10u /* G2P gathers every node from the dense grid instead of an LDS
                                             copy of the chunk's node box */
 #define MPM_FLAG_P2G_SORTED_LANES 0x8u   /* store each chunk in plain sorted order instead of the
-                                            cell-round order that spreads a wave over cells */
+                                            order that deals it over the LDS passes by bank */
 #define MPM_FLAG_FRAME_GRAPHS 0x20u      /* mpm_frame records a whole frame (one rebuild at its start, then
                                             every scene's substeps) as a HIP graph per particle-buffer
                                             parity and replays it; within a frame the free-zone flag is not
@@ -225,11 +225,14 @@ int mpm_read_grid(mpm_ctx* ctx, int32_t scene, float* m_dev, float* v_dev);
  * (ties by scene index), inside a scene geometric blocks in code order;
  * chunks of at most config.chunk particles: consecutive blocks of one
  * 2x2x1 slab of blocks (equal block code >> 2) share a chunk while they fit,
- * a larger block is cut into runs of config.chunk; inside a chunk each
- * block's particles are stored by cell rounds: the first particle (in
- * sorted order) of every cell of the block in cell-code order, then the
- * second particle of every cell that has two, and so on (plain sorted order
- * with MPM_FLAG_P2G_SORTED_LANES).
+ * a larger block is cut into runs of config.chunk; inside a chunk of
+ * `count` particles the particles are ranked by the bank pair
+ * (x + 12 y + 8 z) mod 16 of their cell (x, y, z), then by block and cell
+ * code, ties in sorted order, and rank r is stored at slot 16 p + q of the
+ * chunk, where the ranks are dealt place by place (q = 0, 1, ...) over the
+ * chunk's P = ceil(count / 16) passes in the pass order 0, 2, 4, ..., 1, 3,
+ * 5, ..., the last pass (count - 16 (P - 1) places) dropping out once full
+ * (plain sorted order with MPM_FLAG_P2G_SORTED_LANES).
  * count must equal the scene's particle count at the last rebuild.
  * Synchronizes.                                                             */
 int mpm_read_binning(mpm_ctx* ctx, int32_t scene, int64_t count, uint32_t* keys_dev, int32_t* perm_dev);

@@ -313,40 +313,60 @@ struct OpActive {
 };
 
 // ------------------------------------------------------------ data movement
+// Slot of rank r when a chunk's `count` particles are dealt over its 16-lane
+// passes (pass k = slots 16k .. 16k+15; the last pass holds the remainder):
+// rank r goes to place q = r / P of pass r mod P in the order 0, 2, 4, ...,
+// 1, 3, 5, ... (P passes; places of the short last pass run out first), so
+// consecutive ranks land in different passes, mostly two passes (32 lanes)
+// apart.
+__device__ __forceinline__ int dealt_slot(int count, int r) {
+    const int P = (count + 15) >> 4, last = count - 16 * (P - 1), E = (P + 1) >> 1;
+    int q, i, evens = E;
+    if (r < last * P) {
+        q = r / P;
+        i = r - q * P;
+    } else {
+        const int r2 = r - last * P, Pm = P - 1;
+        q = last + r2 / Pm;
+        i = r2 - (q - last) * Pm;
+        if (P & 1) evens = E - 1;  // the last pass is the last even one: drop it
+    }
+    const int pass = i < evens ? 2 * i : 2 * (i - evens) + 1;
+    return pass * 16 + q;
+}
+
 // Gather the whole particle state into sorted order, one chunk per
-// workgroup.  A chunk holds one to four blocks (segments of its sorted run;
-// inside a segment particles are grouped by cell in cell-code order), and
-// each segment is stored by rounds: the first particle of every cell in cell
-// order, then the second particle of every cell that has two, and so on
-// (unless `spread` is 0: plain sorted order).  A wave then holds about one
-// particle per cell, and the 16 lanes an LDS access serves together hold a
-// 4x2x2 patch of cells.  Each particle's field FSID gets its block (its free
+// workgroup.  A chunk holds one to four blocks (segments of its sorted run).
+// Unless `spread` is 0 (plain sorted order), the chunk's particles are
+// ranked by the LDS bank pair of their cell in the P2G tile -- (x + 12 y +
+// 8 z) mod 16 for cell (x, y, z), the tile's layout with a row pitch of 12
+// (mod 16) and a plane pitch of 8 (mod 16) -- then by cell, and dealt over
+// the 16-lane passes of the P2G scatter: a pass then meets each bank pair
+// about as often as the chunk's cells allow, and particles of one cell sit in
+// different passes.  Each particle's field FSID gets its block (its free
 // zone).  Also records the insertion ids in plain sorted order for the
 // binning view.
+constexpr int PERMUTE_MAX = 512;  // the largest chunk
 __global__ __launch_bounds__(WG) void k_permute_chunks(const float* __restrict__ Sin, float* __restrict__ Sout,
                                                        const int* __restrict__ idin, int* __restrict__ idout,
                                                        int* __restrict__ sorted_ids, const uint32_t* __restrict__ src,
                                                        const uint32_t* __restrict__ keys,
                                                        const Chunk* __restrict__ chunks, const int* __restrict__ ctl,
                                                        int64_t cap, int spread, int shift) {
-    __shared__ int cnt[4][64], first[4][64], segfirst[4];
+    __shared__ int rk[PERMUTE_MAX];
     const int nch = ctl[CTL_NCHUNK];
     const uint32_t mmask = (1u << shift) - 1u;
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
         const Chunk ch = chunks[c];
-        if (spread) {
-            for (int t = threadIdx.x; t < 4 * 64; t += WG) {
-                cnt[t >> 6][t & 63] = 0;
-                first[t >> 6][t & 63] = INT32_MAX;
-            }
-            if (threadIdx.x < 4) segfirst[threadIdx.x] = INT32_MAX;
-            __syncthreads();
+        const bool deal = spread && ch.count <= PERMUTE_MAX;
+        if (deal) {
             for (int t = threadIdx.x; t < ch.count; t += WG) {
-                const uint32_t key = keys[ch.start + t];
-                const int seg = (int)((key >> 6) & 3u), cell = (int)(key & 63u);
-                atomicAdd(&cnt[seg][cell], 1);
-                atomicMin(&first[seg][cell], t);
-                atomicMin(&segfirst[seg], t);
+                const uint32_t key = keys[ch.start + t] & mmask;
+                const uint32_t bcode = key >> 6, cell = key & 63u;
+                const int x = 4 * (int)compact3(bcode) + (int)compact3(cell);
+                const int y = 4 * (int)compact3(bcode >> 1) + (int)compact3(cell >> 1);
+                const int z = 4 * (int)compact3(bcode >> 2) + (int)compact3(cell >> 2);
+                rk[t] = (((x + 12 * y + 8 * z) & 15) << 8) | (int)(key & 255u);  // bank, segment, cell
             }
             __syncthreads();
         }
@@ -354,16 +374,14 @@ __global__ __launch_bounds__(WG) void k_permute_chunks(const float* __restrict__
             const int j = ch.start + t;  // sorted position
             const uint32_t key = keys[j];
             int slot = t;
-            if (spread) {
-                const int seg = (int)((key >> 6) & 3u), cell = (int)(key & 63u);
-                const int r = t - first[seg][cell];  // rank inside its cell
-                int before = 0, pos = 0;
-                for (int q = 0; q < 64; ++q) {
-                    const int n_q = cnt[seg][q];
-                    before += min(n_q, r);                 // the segment's particles of earlier rounds
-                    pos += (q < cell && n_q > r) ? 1 : 0;  // cells ahead in this round
+            if (deal) {
+                const int mine = rk[t];
+                int r = 0;
+                for (int u = 0; u < ch.count; ++u) {
+                    const int o = rk[u];
+                    r += (o < mine || (o == mine && u < t)) ? 1 : 0;
                 }
-                slot = segfirst[seg] + before + pos;
+                slot = dealt_slot(ch.count, r);
             }
             const int k = (int)src[j];  // its position before the sort
             const int dst = ch.start + slot;
@@ -378,7 +396,7 @@ __global__ __launch_bounds__(WG) void k_permute_chunks(const float* __restrict__
             idout[dst] = id;
             sorted_ids[j] = id;
         }
-        if (spread) __syncthreads();
+        if (deal) __syncthreads();
     }
 }
 

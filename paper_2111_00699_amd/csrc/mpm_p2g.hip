@@ -24,11 +24,11 @@
 //     deterministic.  Each workgroup owns an
 //     equal slice of the staging buffer and packs its chunks' tiles there
 //     (offset recorded per chunk), so no allocation is shared.
-// The rebuild stores each chunk by cell rounds (first particle of every
-// cell, then the second, ...), so the 64 lanes of a wave sit in different
-// cells and rarely hit one LDS address (same-address atomics serialize),
-// and the tile's padded pitches put the 16 lanes of one LDS access on
-// different banks.
+// The rebuild stores each chunk dealt over its 16-lane LDS passes by the
+// bank pair of each particle's cell in this tile layout, so the 16 lanes of
+// one LDS access meet each bank pair about as rarely as the chunk's cells
+// allow and rarely share an address (conflicting lanes of a pass
+// serialize; lanes in different passes do not conflict).
 // Particles outside their free zone (before a late rebuild) scatter straight
 // to global atomics and activate the blocks they touch.
 #include <type_traits>

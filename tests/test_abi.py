@@ -122,17 +122,30 @@ def test_binding_refuses_to_run_without_the_library(monkeypatch, tmp_path):
 
 
 def test_documented_chunk_layout_rule_is_a_permutation():
-    """The cell-round storage order include/mpm.h documents is a permutation
-    of the chunk, every wave-sized run of it holds each cell at most once
-    while the cells are full, and a round lists its cells in code order."""
-    from tests.test_gpu_parity import round_order
+    """The dealt storage order include/mpm.h documents is a permutation of
+    every chunk size; in a dense half block (32 cells of 8 particles, one
+    chunk of 256) each 16-lane pass meets 16 different bank pairs and no cell
+    twice; and particles of one cell land in different passes."""
+    from tests.test_gpu_parity import _compact3, dealt_order, dealt_slot
 
-    cells = np.repeat(np.arange(64), 8)  # a full block: 8 particles in each of 64 cells
-    order = round_order(cells)
-    assert sorted(order.tolist()) == list(range(cells.size))
-    for w in range(0, cells.size, 64):
-        wave = cells[order[w:w + 64]]
-        assert len(set(wave.tolist())) == 64
-        assert np.all(np.diff(wave) > 0)
-    ragged = np.array([0, 0, 0, 3, 5, 5, 9])
-    assert ragged[round_order(ragged)].tolist() == [0, 3, 5, 9, 0, 5, 0]
+    for count in list(range(1, 40)) + [63, 64, 65, 127, 200, 255, 256, 257, 400, 511, 512]:
+        slots = [dealt_slot(count, r) for r in range(count)]
+        assert sorted(slots) == list(range(count)), count
+    # the first 32 cells of a block in Morton order (a 4 x 4 x 2 slab), 8 particles each
+    keys = np.repeat((5 << 6) + np.arange(32), 8)
+    order = dealt_order(keys)
+    assert sorted(order.tolist()) == list(range(keys.size))
+    cell = keys[order] & 63
+    x = 4 * _compact3(5) + _compact3(cell)
+    y = 4 * _compact3(5 >> 1) + _compact3(cell >> 1)
+    z = 4 * _compact3(5 >> 2) + _compact3(cell >> 2)
+    bank = (x + 12 * y + 8 * z) & 15
+    for p in range(0, keys.size, 16):
+        assert len(set(bank[p:p + 16].tolist())) == 16
+        assert len(set(cell[p:p + 16].tolist())) == 16
+    # ragged chunks: the particles of one cell spread over the passes
+    for size, want in ((32, 2), (48, 3)):
+        ragged = np.array([0, 0, 0] + list(range(1, size - 2)))
+        o = dealt_order(ragged)
+        passes = {int(np.flatnonzero(o == i)[0]) // 16 for i in range(3)}
+        assert len(passes) == want, size

@@ -96,15 +96,42 @@ def test_binning_is_bit_exact(torch_cuda, oracle, n, which):
     sim.close()
 
 
-def round_order(cells):
-    """Slots of a chunk in cell-round order: positions sorted by (rank of the
-    particle inside its cell, cell), for a chunk whose particles are grouped by
-    cell in ascending cell order (the layout include/mpm.h documents)."""
-    cells = np.asarray(cells)
-    rank = np.zeros(cells.size, dtype=np.int64)
-    for k in range(1, cells.size):
-        rank[k] = rank[k - 1] + 1 if cells[k] == cells[k - 1] else 0
-    return np.lexsort((cells, rank))
+def _compact3(v):
+    v = np.asarray(v, dtype=np.int64)
+    out = np.zeros_like(v)
+    for b in range(11):
+        out |= ((v >> (3 * b)) & 1) << b
+    return out
+
+
+def dealt_slot(count, r):
+    """Storage slot of rank r in a chunk of `count` particles: the ranks are
+    dealt over the chunk's 16-lane passes in the pass order 0, 2, 4, ..., 1,
+    3, 5, ..., the short last pass dropping out once full (the layout
+    include/mpm.h documents)."""
+    P = (count + 15) // 16
+    last = count - 16 * (P - 1)
+    order = list(range(0, P, 2)) + list(range(1, P, 2))
+    seq = [p * 16 + q for q in range(16) for p in order if not (p == P - 1 and q >= last)]
+    return seq[r]
+
+
+def dealt_order(keys):
+    """Positions of a chunk's particles (keys in sorted order, no rank bits)
+    for each storage slot: ranked by the bank pair (x + 12 y + 8 z) mod 16 of
+    their cell, then by block and cell, ties in sorted order; rank r is
+    stored at dealt_slot(count, r)."""
+    keys = np.asarray(keys, dtype=np.int64)
+    b, c = keys >> 6, keys & 63
+    x = 4 * _compact3(b) + _compact3(c)
+    y = 4 * _compact3(b >> 1) + _compact3(c >> 1)
+    z = 4 * _compact3(b >> 2) + _compact3(c >> 2)
+    k = (((x + 12 * y + 8 * z) & 15) << 8) | (keys & 255)
+    ranked = np.argsort(k, kind="stable")
+    order = np.empty(keys.size, dtype=np.int64)
+    for r, pos in enumerate(ranked):
+        order[dealt_slot(keys.size, r)] = pos
+    return order
 
 
 def chunk_runs(gcode, gstart, gcount, chunk=256):
@@ -139,17 +166,11 @@ def chunk_runs(gcode, gstart, gcount, chunk=256):
 
 
 def storage_order(perm, keys, gcode, gstart, gcount, chunk=256):
-    """Insertion ids in storage order after a rebuild: each chunk's blocks are
-    stored one after another, each by cell rounds."""
+    """Insertion ids in storage order after a rebuild: each chunk's particles
+    dealt over its 16-lane passes by bank pair (dealt_order)."""
     order = np.empty_like(perm)
     for c0, cc in chunk_runs(gcode, gstart, gcount, chunk):
-        blocks = (keys[c0:c0 + cc] >> 6).astype(np.int64)
-        seg0 = 0
-        for blk in np.unique(blocks):
-            n = int(np.sum(blocks == blk))
-            s = c0 + seg0
-            order[s:s + n] = perm[s + round_order(keys[s:s + n] & 63)]
-            seg0 += n
+        order[c0:c0 + cc] = perm[c0 + dealt_order(keys[c0:c0 + cc])]
     return order
 
 
