@@ -181,7 +181,7 @@ __global__ __launch_bounds__(NT) void k_g2p(float* __restrict__ S, int64_t cap, 
             for (int a = 0; a < 3; ++a) x[a] = S[(FX + a) * cap + p];
             fsid = S[FSID * cap + p];
         }
-        int lo[3] = {0, 0, 0}, e[3] = {0, 0, 0}, nt = 0;
+        int lo[3] = {0, 0, 0}, e[3] = {0, 0, 0}, nt = 0, R = 4, Q = 8;
         if (LDS_BOX) {
             const int4 bb = box[c];
             e[0] = bb.y & 255;
@@ -191,14 +191,18 @@ __global__ __launch_bounds__(NT) void k_g2p(float* __restrict__ S, int64_t cap, 
             lo[1] = (bb.x >> 10) & 1023;
             lo[2] = bb.x >> 20;
             nt = e[0] * e[1] * e[2];
-            if (nt > G2P_BOX) nt = 0;
-            load_node_box(tv, vels, NB, lo, e, nt, e[0], e[0] * e[1], threadIdx.x, NT);  // tight layout
+            // the P2G tile's padded pitches: with the rebuild's bank-dealt lane order the
+            // lanes of one LDS pass read different banks
+            R = pitch_row(e[0]);
+            Q = pitch_plane(R, e[1]);
+            if (Q * e[2] > G2P_BOX) nt = 0;
+            load_node_box(tv, vels, NB, lo, e, nt, R, Q, threadIdx.x, NT);
             __syncthreads();
         }
         Stencil st;
         if (mine && make_stencil(x, P, st, err)) {
             float vp[3], Cn[9];
-            g2p_gather(st, tv, vels, NB, lo, e, nt, e[0], e[0] * e[1], c4, vp, Cn);
+            g2p_gather(st, tv, vels, NB, lo, e, nt, R, Q, c4, vp, Cn);
 #pragma unroll
             for (int k = 0; k < 9; ++k) S[(FC + k) * cap + p] = Cn[k];
             bool fin = true;
