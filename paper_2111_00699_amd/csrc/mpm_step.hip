@@ -191,11 +191,16 @@ __global__ __launch_bounds__(NT) void k_g2p(float* __restrict__ S, int64_t cap, 
             lo[1] = (bb.x >> 10) & 1023;
             lo[2] = bb.x >> 20;
             nt = e[0] * e[1] * e[2];
-            // the P2G tile's padded pitches: with the rebuild's bank-dealt lane order the
-            // lanes of one LDS pass read different banks
+            // the P2G tile's padded pitches where they fit (with the rebuild's bank-dealt
+            // lane order the lanes of one LDS pass then read different banks), else the
+            // tight layout
             R = pitch_row(e[0]);
             Q = pitch_plane(R, e[1]);
-            if (Q * e[2] > G2P_BOX) nt = 0;
+            if (Q * e[2] > G2P_BOX) {
+                R = e[0];
+                Q = e[0] * e[1];
+                if (nt > G2P_BOX) nt = 0;
+            }
             load_node_box(tv, vels, NB, lo, e, nt, R, Q, threadIdx.x, NT);
             __syncthreads();
         }
