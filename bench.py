@@ -186,7 +186,7 @@ def bench_fountain(args):
     """The fountain: water emitted from the inlet once per 1/60 s frame until
     143,500 particles, on a 128^3 grid, frames of 167 substeps.  Reports ms per
     frame against the particle count, once with G2P fused into the next P2G
-    below 100,000 particles (the default) and once with G2P kept separate."""
+    (the default below 1,000,000 particles) and once with G2P kept separate."""
     import torch
 
     from paper_2111_00699_amd import mpm, scenes
@@ -207,7 +207,7 @@ def bench_fountain(args):
     log(f"[bench] fountain: {len(emissions)} emitting frames, {total} particles, {frames} frames of {nsub} substeps")
     stream = torch.cuda.current_stream()
     runs = {}
-    for name, flags in (("fused_below_100k", 0), ("separate_g2p", mpm.FLAG_SEPARATE_G2P)):
+    for name, flags in (("default_fused", 0), ("separate_g2p", mpm.FLAG_SEPARATE_G2P)):
         sim = mpm.Sim(cfg["n"], cfg["dt"], bc=cfg["bc"], bc_cells=cfg["bc_cells"], gravity=cfg["gravity"],
                       capacity=2 * total + 256, flags=flags | args.flags, chunk=args.chunk)
         # warmup: one frame of a throwaway emission, then a fresh context
@@ -241,7 +241,7 @@ def bench_fountain(args):
                       "value": work / (max(gpu_ms, wall * 1e3) * 1e-3), "rebuilds": st["rebuilds"],
                       "frames": [[f + 1, counts[f], round(ms[f], 3)] for f in range(frames)]}
         log(f"[bench] fountain {name}: {runs[name]['ms_total'] / frames:.2f} ms per frame on average")
-    r = runs["fused_below_100k"]
+    r = runs["default_fused"]
     out = {
         "metric": "particle-substeps/s",
         "value": r["value"],
@@ -253,9 +253,92 @@ def bench_fountain(args):
                                "from a 0.05-radius inlet until 143,500 particles, 128^3 grid, separating walls, "
                                f"{nsub} substeps per 1/60 s frame",
                    "particles_final": total, "emitting_frames": len(emissions), "grid": cfg["n"],
-                   "substeps_per_frame": nsub, "fuse_below": 100000},
+                   "substeps_per_frame": nsub, "fuse_below": 1000000},
         "runs": runs,
         "fused_vs_separate": runs["separate_g2p"]["ms_total"] / r["ms_total"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+ABLATIONS = (  # (name, library flags, chunk size); the baseline first
+    ("baseline", 0, 0),
+    ("rebuild_every_step", 0x1, 0),    # no free zone: rebuild and sort before every substep
+    ("p2g_global_atomics", 0x2, 0),    # P2G straight to global atomics, no LDS tile
+    ("plain_sorted_lanes", 0x8, 0),    # chunks in plain sorted order, not dealt over the LDS passes
+    ("g2p_global_gather", 0x10, 0),    # G2P gathers from the dense grid, no LDS node box
+    ("g2p_always_fused", 0x40, 0),     # G2P inside the next P2G at any size
+    ("g2p_always_separate", 0x80, 0),  # G2P as its own launch at any size
+    ("frame_graphs", 0x20, 0),         # frames replayed as HIP graphs
+    ("chunk_128", 0, 128),
+    ("chunk_512", 0, 512),
+)
+
+
+def bench_ablations(args):
+    """The paper's single-GPU ablations, on this library: each design choice
+    switched off by a flag (or a chunk size), ms per 1/60 s frame and the
+    extra cost against the default build.  Scenes: the Sand Blocks layout
+    (4 boxes of 12^3 and of 23^3 cells at 8 ppc, 55,296 and 389,344
+    particles; fixed-corotated jelly stands in for the paper's sand model) in a
+    128^3 grid with slip walls, and the snow scene (1.28M particles)."""
+    import torch
+
+    from paper_2111_00699_amd import mpm, scenes
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    frame = scenes.FRAME
+    jelly_dt = scenes.frame_substeps(5e-5)[1]
+    snow = scenes.snow_config()
+    cases = []
+    for l, frames in ((12, 10), (23, 4)):
+        x = scenes.sand_blocks(l=l, boxes=4, n=128)["x"]
+        cases.append((f"sand_blocks_4x{l}^3", x, scenes.JELLY, dict(n=128, dt=jelly_dt, bc="slip", bc_cells=3,
+                                                                    gravity=(0.0, -9.8, 0.0)), frames))
+    cases.append(("snow", scenes.snow_spheres(1)["x"], scenes.SNOW,
+                  dict(n=snow["n"], dt=snow["dt"], bc=snow["bc"], bc_cells=snow["bc_cells"],
+                       gravity=snow["gravity"]), 2))
+    table = {}
+    with torch.cuda.stream(stream):
+        for name, x, mat, cfg, frames in cases:
+            N = x.shape[1]
+            rows = {}
+            for cname, flags, chunk in ABLATIONS:
+                sim = mpm.Sim(cfg["n"], cfg["dt"], bc=cfg["bc"], bc_cells=cfg["bc_cells"], gravity=cfg["gravity"],
+                              capacity=2 * N + 256, flags=flags, chunk=chunk, stream=stream)
+                sim.add_particles(mat, x)
+                sim.frame(frame)  # warmup
+                sim.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                w0 = time.perf_counter()
+                e0.record(stream)
+                for _ in range(frames):
+                    sim.frame(frame)
+                e1.record(stream)
+                stream.synchronize()
+                ms = max(e0.elapsed_time(e1), (time.perf_counter() - w0) * 1e3) / frames
+                st = sim.stats()
+                sim.close()
+                rows[cname] = {"ms_per_frame": round(ms, 3), "rebuilds": st["rebuilds"]}
+                log(f"[bench] ablation {name} {cname}: {ms:.2f} ms per frame")
+            base = rows["baseline"]["ms_per_frame"]
+            for r in rows.values():
+                r["extra_cost"] = round(r["ms_per_frame"] / base - 1.0, 4)
+            table[name] = {"particles": N, "frames_timed": frames, "configs": rows}
+    snow_base = table["snow"]["configs"]["baseline"]["ms_per_frame"]
+    nsub = snow["substeps_per_frame"]
+    N = table["snow"]["particles"]
+    out = {
+        "metric": "particle-substeps/s",
+        "value": N * nsub / (snow_base * 1e-3),
+        "unit": "particle-substeps/s",
+        "n_gpus": 1, "steps": table["snow"]["frames_timed"], "warmup": 1,
+        "ms_per_step": snow_base, "ms_per_frame": snow_base,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "ablations: each design choice switched off in turn on the Sand Blocks layout "
+                               "(4 boxes of 12^3 and 23^3 cells, jelly stand-in, 128^3) and the snow scene; "
+                               "value is the snow baseline over its timed frames 2-3"},
+        "ablations": table,
     }
     print(json.dumps(out), flush=True)
 
@@ -378,7 +461,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--flags", type=int, default=0)
-    ap.add_argument("--workload", choices=("snow", "batched", "surrogate", "fountain"), default="snow")
+    ap.add_argument("--workload", choices=("snow", "batched", "surrogate", "fountain", "ablations"), default="snow")
     ap.add_argument("--train-snapshots", type=int, default=4, help="surrogate: training snapshots per scene")
     ap.add_argument("--train-steps", type=int, default=20000, help="surrogate: Adam steps")
     ap.add_argument("--sur-tol", type=float, default=2e-3, help="surrogate: residual tolerance")
@@ -387,7 +470,7 @@ def main():
                     help="only run a plain 1 GiB device-to-device copy 4 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.steps is None:
-        args.steps = {"snow": 60, "fountain": 60, "batched": 10, "surrogate": 5}[args.workload]
+        args.steps = {"snow": 60, "fountain": 60, "batched": 10, "surrogate": 5, "ablations": 0}[args.workload]
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
@@ -412,6 +495,9 @@ def main():
         return
     if args.workload == "fountain":
         bench_fountain(args)
+        return
+    if args.workload == "ablations":
+        bench_ablations(args)
         return
 
     from paper_2111_00699_amd import mpm, scenes

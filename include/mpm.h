@@ -182,7 +182,7 @@ int mpm_add_particles(mpm_ctx* ctx, int32_t scene, const mpm_material* mat, int6
  * when a particle left its free zone] -> P2G -> grid update -> G2P, one launch
  * per phase for all scenes.  A substep's G2P runs inside the next substep's
  * P2G launch (paper, "Merge Kernels": G2P2G) when the context holds fewer
- * than 100,000 particles (as in the paper) or MPM_FLAG_FUSED_G2P is set --
+ * than 1,000,000 particles or MPM_FLAG_FUSED_G2P is set --
  * unless MPM_FLAG_SEPARATE_G2P, MPM_FLAG_P2G_GLOBAL_ATOMICS,
  * MPM_FLAG_REBUILD_EVERY_STEP, MPM_FLAG_G2P_GLOBAL_GATHER,
  * MPM_FLAG_FRAME_GRAPHS or a learned / closed-form return map is in use.

@@ -452,10 +452,12 @@ int check_error_word(mpm_ctx* c) {
 
 // Whether a substep may leave its G2P to the next substep's P2G (the fused
 // kernel needs the LDS tile path, the exact return map and the node-box
-// gather).  By default only small systems fuse: the paper keeps G2P2G below
-// 100K particles, and on gfx950 it saves 10% of a 32K-particle substep
-// (mostly a launch) but nothing at 1.28M particles.
-constexpr int64_t FUSE_BELOW = 100000;
+// gather).  By default systems below a million particles fuse: the paper
+// keeps G2P2G below 100K particles (instruction-cache misses beyond that on
+// its GPU); on gfx950 it saves 8-10% of a frame at 6.6K-99K particles and
+// 6.6% at 389K, but changes nothing at 1.28M, where P2G is bound by its LDS
+// scatter.
+constexpr int64_t FUSE_BELOW = 1000000;
 bool fusion_allowed(const mpm_ctx* c) {
     const bool wanted = (c->cfg.flags & MPM_FLAG_FUSED_G2P) ||
                         (!(c->cfg.flags & MPM_FLAG_SEPARATE_G2P) && c->N < FUSE_BELOW);
