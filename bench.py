@@ -15,7 +15,7 @@ the K timed frames (inputs resident in HBM before timing starts).
 `roofline` covers the P2G kernel, timed with HIP events on the library's
 stream during the timed frames, against the HBM peak (`frac` from the
 algorithmic bytes, `traffic_frac` from the measured HBM bytes);
-`roofline_lds` puts the same launches against the LDS FP64 atomic rate that
+`roofline_lds` puts the same launches against the LDS 64-bit atomic rate that
 bounds them; `cpu_baseline` times the FP64 oracle on the host on a bounded
 sample.  The other workloads print their own line: the fountain (ms per
 frame against the growing particle count), 256 batched scenes, and the
@@ -33,11 +33,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# LDS FP64 atomic throughput of gfx950, measured with a probe of ds_add_f64 on
-# distinct addresses: 6.61 lane-operations per clock per compute unit, i.e.
-# 6.61 x 256 CUs x 2.4 GHz.  P2G's scatter issues 27 nodes x 4 channels of
-# them per in-zone particle.
-LDS_F64_ATOMIC_PEAK = 6.61 * 256 * 2.4e9
+# LDS 64-bit integer atomic throughput of gfx950, measured with a probe of
+# ds_add_u64 on distinct addresses: 9.1 lane-operations per clock per compute
+# unit, i.e. 9.1 x 256 CUs x 2.4 GHz.  P2G's fixed-point scatter issues 27
+# nodes x 4 channels of them per in-zone particle.
+LDS_U64_ATOMIC_PEAK = 9.1 * 256 * 2.4e9
 P2G_LDS_ATOMICS_PER_PARTICLE = 108
 # The surrogate MLP 12-64-64-12 as executed on MFMA (inputs and outputs padded
 # to 16): 16x64 + 64x64 + 64x16 = 6,144 multiply-adds per forward pass; a
@@ -567,11 +567,11 @@ def main():
                      "traffic_frac": (traffic / (p2g_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None,
                      "avg_launch_us": p2g_avg_ms * 1e3, "launches": p2g["launches"],
                      "bytes_per_particle": P2G_BYTES["snow"]},
-        # the bound P2G actually meets: its LDS FP64 atomics against their measured peak rate
-        "roofline_lds": {"kernel": "p2g", "bound": "lds_fp64_atomics",
+        # the bound P2G actually meets: its LDS atomics against their measured peak rate
+        "roofline_lds": {"kernel": "p2g", "bound": "lds_u64_atomics",
                          "achieved": P2G_LDS_ATOMICS_PER_PARTICLE * N / (p2g_avg_ms * 1e-3),
-                         "peak": LDS_F64_ATOMIC_PEAK, "unit": "lane-ops/s",
-                         "frac": P2G_LDS_ATOMICS_PER_PARTICLE * N / (p2g_avg_ms * 1e-3) / LDS_F64_ATOMIC_PEAK},
+                         "peak": LDS_U64_ATOMIC_PEAK, "unit": "lane-ops/s",
+                         "frac": P2G_LDS_ATOMICS_PER_PARTICLE * N / (p2g_avg_ms * 1e-3) / LDS_U64_ATOMIC_PEAK},
         "wall_ms": wall * 1e3,
         "gpu_event_ms": gpu_ms,
     }

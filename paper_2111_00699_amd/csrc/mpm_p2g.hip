@@ -5,17 +5,19 @@
 // Avoiding non-native intrinsics ("Avoid non-native intrinsics"): on V100
 // the paper drops shared-memory float atomics because they are emulated.
 // On gfx950 ds_add_f32 exists but runs at about 0.3 lane-ops per clock per
-// CU, while ds_add_f64 runs at about 6.6, and global float atomics (about
+// CU, while ds_add_f64 runs at about 6.6 and ds_add_u64 at 9.1 (and far
+// better under bank and address conflicts), and global float atomics (about
 // 0.4, executed memory-side) move a full write per update.  The same
 // principle -- use only the fast native operations -- leads here to:
 //   * a workgroup takes one chunk (<= 256 or 512 particles of one particle
 //     block), one particle per thread, loads coalesced;
 //   * phase 1 computes every particle's contribution and the bounding box of
 //     the stencils of the chunk's in-zone particles (block reduction);
-//   * the tile is that box (at most 512 nodes; a particle block's stencils
-//     cover 6^3 = 216 nodes right after a rebuild), four FP64 channels
-//     (weight sum and three momentum components) accumulated with
-//     ds_add_f64;
+//   * the tile is that box (at most 1024 padded nodes; a particle block's
+//     stencils cover 6^3 = 216 nodes right after a rebuild), four 64-bit
+//     fixed-point channels (weight sum and three momentum components, the
+//     latter scaled per chunk) accumulated with ds_add_u64: exact, so the
+//     sums do not depend on the order of the adds;
 //   * the tile is then STORED (plain, coalesced float4 stores) to the
 //     staging buffer; the rebuild registered each chunk with every physical
 //     block its in-zone stencils can reach, and the grid update gathers each
@@ -43,7 +45,24 @@ namespace {
 constexpr int CT = 1024;  // LDS tile capacity in nodes (padded layout, below)
 
 // LDS tile layout: the padded node-box layout (pitch_row, pitch_plane in
-// mpm_kernels.h), FP64 channels.
+// mpm_kernels.h), four 64-bit fixed-point channels: the weight sum in units
+// of 2^-51 and the three momentum components in units of 2^-FRAC_M of the
+// chunk's momentum scale (below).  Integer adds are exact and
+// order-independent, and ds_add_u64 meets far fewer conflict cycles than
+// ds_add_f64 (a replay of late-frame snow stencils: 14 against 22 cycles per
+// wave instruction).
+constexpr float W_SCALE = 0x1p51f;  // weight units per 1: w <= 27/64, so w W_SCALE < 2^50
+constexpr int FRAC_M = 50;          // momentum: |w m| scaled below 2^50 per contribution
+// A contribution below this weight goes to the global FP32 accumulator
+// instead: a node that only such contributions reach would be resolved to
+// too few fixed-point units for its velocity (momentum / mass).
+constexpr float TINY_W = 0x1p-32f;
+
+// Round-to-nearest integer of y (|y| < 2^51) as a 64-bit two's-complement
+// word: adding 1.5 2^52 in FP64 leaves the integer in the low mantissa bits.
+__device__ __forceinline__ unsigned long long fixed64(float y) {
+    return (unsigned long long)(__double_as_longlong((double)y + 0x1.8p52) - 0x4338000000000000LL);
+}
 
 // ------------------------------------------------ snow return map without SVD
 // Eigenvalues of the symmetric b = [b0 b1 b2; . b3 b4; . . b5] as
@@ -240,7 +259,7 @@ __device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, con
                                          int* __restrict__ host_flag, int fb_limit) {
     static_assert(!FUSED || (!GLOBAL_ONLY && SURM == 0), "the fused G2P needs the LDS tile and the exact map");
     __shared__ __align__(16) double tq[GLOBAL_ONLY ? 1 : 4 * CT];
-    __shared__ int red_i[6][NT / 64];
+    __shared__ int red_i[7][NT / 64];
     struct Empty {};
     __shared__ typename std::conditional<SURM == 2, mlp::NetLds16, Empty>::type net;
     __shared__ float sur_stage[SURM == 2 ? NT / 64 * 512 : 1];
@@ -377,6 +396,7 @@ __device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, con
         // ---- the box of the in-zone stencils of the chunk
         int lo[3] = {0, 0, 0}, ext[3] = {0, 0, 0};
         int nt = 0, off = 0, R = 4, Q = 8;  // tight node count, staging offset, LDS pitches
+        float m_scale = 1.0f, m_unit = 1.0f;  // momentum fixed-point scale of the chunk and its inverse
         if (GLOBAL_ONLY && tid == 0) box[c] = make_int4(0, 0, 0, 0);
         if (!GLOBAL_ONLY) {
             const bool tiled = have && in_zone;
@@ -386,19 +406,29 @@ __device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, con
                 mn[a] = wave_min(tiled ? st.base[a] : INT_MAX);
                 mx[a] = wave_max(tiled ? st.base[a] + 2 : INT_MIN);
             }
+            // bound on |q_a + Ad_a . o| over the stencil (o in {0,1,2}^3), the momentum a tiled
+            // particle sends to a node before its weight (non-negative: ordered as an int)
+            float mb = 0.0f;
+            if (tiled) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    mb = fmaxf(mb, fabsf(q[a]) + 2.0f * (fabsf(Ad[3 * a]) + fabsf(Ad[3 * a + 1]) + fabsf(Ad[3 * a + 2])));
+            }
+            const int mbw = wave_max(__float_as_int(mb));
             if (lane == 0) {
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     red_i[a][wv] = mn[a];
                     red_i[3 + a][wv] = mx[a];
                 }
+                red_i[6][wv] = mbw;
             }
             __syncthreads();
             if constexpr (FUSED) {  // every gather is done: clear the staged node box, keeping the tile zero
                 for (int t = tid; t < 2 * ngs; t += NT) tq[t] = 0.0;
                 __syncthreads();
             }
-            int hi[3];
+            int hi[3], mbk = 0;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 lo[a] = INT_MAX;
@@ -411,6 +441,16 @@ __device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, con
                     lo[a] = min(lo[a], red_i[a][k]);
                     hi[a] = max(hi[a], red_i[3 + a][k]);
                 }
+                mbk = max(mbk, red_i[6][k]);
+            }
+            // the chunk's momentum scale 2^(FRAC_M - em): every contribution |w m| < 27/64 * bound
+            // < 2^em stays below 2^FRAC_M units
+            {
+                int em = 0;
+                (void)frexpf(0.421875f * __int_as_float(mbk), &em);
+                em = min(max(em, -70), 77);
+                m_scale = ldexpf(1.0f, FRAC_M - em);
+                m_unit = ldexpf(1.0f, em - FRAC_M);
             }
             if (hi[0] >= lo[0]) {
 #pragma unroll
@@ -444,26 +484,44 @@ __device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, con
         if (have && ok) {
             if (!GLOBAL_ONLY && in_zone && nt > 0) {
                 const int tb = (st.base[0] - lo[0]) + R * (st.base[1] - lo[1]) + Q * (st.base[2] - lo[2]);
+                unsigned long long* tu = reinterpret_cast<unsigned long long*>(tq);
+                float qs[3], As[9];  // in momentum units (exact: a power-of-two scale)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) qs[a] = q[a] * m_scale;
+#pragma unroll
+                for (int k = 0; k < 9; ++k) As[k] = Ad[k] * m_scale;
 #pragma unroll
                 for (int o2 = 0; o2 < 3; ++o2)
 #pragma unroll
                     for (int o1 = 0; o1 < 3; ++o1) {
                         const float wyz = st.w[1][o1] * st.w[2][o2];
-                        float m0 = q[0] + o1 * Ad[1] + o2 * Ad[2];
-                        float m1 = q[1] + o1 * Ad[4] + o2 * Ad[5];
-                        float m2 = q[2] + o1 * Ad[7] + o2 * Ad[8];
+                        float m0 = qs[0] + o1 * As[1] + o2 * As[2];
+                        float m1 = qs[1] + o1 * As[4] + o2 * As[5];
+                        float m2 = qs[2] + o1 * As[7] + o2 * As[8];
                         const int row = tb + R * o1 + Q * o2;
 #pragma unroll
                         for (int o0 = 0; o0 < 3; ++o0) {
                             const float w = wyz * st.w[0][o0];
                             const int t = row + o0;
-                            atomicAdd(&tq[t], (double)w);
-                            atomicAdd(&tq[CT + t], (double)(w * m0));
-                            atomicAdd(&tq[2 * CT + t], (double)(w * m1));
-                            atomicAdd(&tq[3 * CT + t], (double)(w * m2));
-                            m0 += Ad[0];
-                            m1 += Ad[3];
-                            m2 += Ad[6];
+                            if (w >= TINY_W) {
+                                atomicAdd(&tu[t], fixed64(w * W_SCALE));
+                                atomicAdd(&tu[CT + t], fixed64(w * m0));
+                                atomicAdd(&tu[2 * CT + t], fixed64(w * m1));
+                                atomicAdd(&tu[3 * CT + t], fixed64(w * m2));
+                            } else {  // rare: to the node's global accumulator, in FP32
+                                const int gx = st.base[0] + o0, gy = st.base[1] + o1, gz = st.base[2] + o2;
+                                const int bk = (((gz >> 2) + 1) * P.NB + ((gy >> 2) + 1)) * P.NB + ((gx >> 2) + 1);
+                                float* a = acc + 4 * ((int64_t)(sc.brick_base + bk) * BLOCK_NODES + (gx & 3) +
+                                                      ((gy & 3) << 2) + ((gz & 3) << 4));
+                                unsafeAtomicAdd(a + 0, w * M.mp);
+                                unsafeAtomicAdd(a + 1, w * m0 * m_unit);
+                                unsafeAtomicAdd(a + 2, w * m1 * m_unit);
+                                unsafeAtomicAdd(a + 3, w * m2 * m_unit);
+                                acc_dirty[sc.brick_base + bk] = 1;
+                            }
+                            m0 += As[0];
+                            m1 += As[3];
+                            m2 += As[6];
                         }
                     }
             } else {
@@ -515,8 +573,10 @@ __device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, con
             for (int u = tid; u < nt; u += NT) {  // staged in the tight box layout
                 const int z = u / e01, y = (u - z * e01) / ext[0], xx = u - z * e01 - y * ext[0];
                 const int t = xx + R * y + Q * z;
-                slot[u] = make_float4((float)(tq[t] * (double)M.mp), (float)tq[CT + t], (float)tq[2 * CT + t],
-                                      (float)tq[3 * CT + t]);
+                const long long* ti = reinterpret_cast<const long long*>(tq);
+                const double mu = (double)m_unit;
+                slot[u] = make_float4((float)((double)ti[t] * (0x1p-51 * (double)M.mp)), (float)((double)ti[CT + t] * mu),
+                                      (float)((double)ti[2 * CT + t] * mu), (float)((double)ti[3 * CT + t] * mu));
 #pragma unroll
                 for (int ch4 = 0; ch4 < 4; ++ch4) tq[ch4 * CT + t] = 0.0;  // ready for the next chunk
             }
