@@ -50,6 +50,10 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0
 # update): P2G reads x, v, C, F_E, J_P (100 B) and writes F_E, J_P (40 B);
 # G2P reads x (12 B) and writes x, v, C (60 B).
 P2G_BYTES = {"jelly": 132, "snow": 140, "water": 68}
+# P2G with the previous substep's G2P inside it (the default): reads x, F_E,
+# J_P and the block word (56 B), writes x, F_E, J_P (52 B); v and C stay in
+# registers.
+P2G_FUSED_BYTES = {"snow": 108}
 G2P_BYTES = 72
 
 # HBM bytes per P2G launch measured with rocprofv3 counters (FETCH_SIZE x 2.0
@@ -60,19 +64,20 @@ G2P_BYTES = 72
 # The figure belongs to the P2G sources whose hash is stored beside it: after
 # any change to them the bench reports traffic as null until it is measured
 # again.
-P2G_TRAFFIC = {"sources_sha256_16": "6a682cf0f65deafb", "bytes": 221.74e6}
+P2G_TRAFFIC = {"kernel": "p2g", "sources_sha256_16": "733c6e3204a4b83a", "bytes": 225.82e6}
 P2G_SOURCES = ("paper_2111_00699_amd/csrc/mpm_p2g.hip", "paper_2111_00699_amd/csrc/mpm_internal.h",
                "paper_2111_00699_amd/csrc/mpm_kernels.h", "paper_2111_00699_amd/csrc/mpm_api.hip")
 
 
-def p2g_traffic_bytes():
+def p2g_traffic_bytes(kernel):
     import hashlib
 
     h = hashlib.sha256()
     for f in P2G_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    return P2G_TRAFFIC["bytes"] if h.hexdigest()[:16] == P2G_TRAFFIC["sources_sha256_16"] else None
+    ok = h.hexdigest()[:16] == P2G_TRAFFIC["sources_sha256_16"] and kernel == P2G_TRAFFIC["kernel"]
+    return P2G_TRAFFIC["bytes"] if ok else None
 
 
 def log(msg):
@@ -405,7 +410,7 @@ def bench_surrogate(args):
             sim.use_surrogate(mode, sur if mode == 1 else None, tol=args.sur_tol, dt_ref=cfg["dt"])
         sim.substep(nsub // 3)  # warm-up
         sim.synchronize()
-        sim.profile(mpm.PHASE_P2G)
+        sim.profile(mpm.PHASE_P2G | mpm.PHASE_G2P)
         st0 = sim.stats()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -517,7 +522,7 @@ def main():
         log(f"[bench] warmup frame {f + 1}/{args.warmup} enqueued")
     sim.synchronize()
     st0 = sim.stats()
-    sim.profile(mpm.PHASE_P2G)
+    sim.profile(mpm.PHASE_P2G | mpm.PHASE_G2P)
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -538,9 +543,11 @@ def main():
     value = N * substeps / (ms * 1e-3)
     p2g = prof["p2g"]
     p2g_avg_ms = p2g["ms"] / max(p2g["launches"], 1)
-    achieved = P2G_BYTES["snow"] * N / (p2g_avg_ms * 1e-3) / 1e9
+    fused = prof["g2p"]["launches"] * 2 < p2g["launches"]  # G2P ran inside P2G
+    p2g_bytes = P2G_FUSED_BYTES["snow"] if fused else P2G_BYTES["snow"]
+    achieved = p2g_bytes * N / (p2g_avg_ms * 1e-3) / 1e9
     rebuilds = st1["rebuilds"] - st0["rebuilds"]
-    traffic = p2g_traffic_bytes()
+    traffic = p2g_traffic_bytes("p2g_fused" if fused else "p2g")
     out = {
         "metric": "particle-substeps/s",
         "value": value,
@@ -561,14 +568,15 @@ def main():
                    "particles": N, "grid": cfg["n"], "substeps_per_frame": nsub, "frames_timed": args.steps,
                    "rebuilds_in_timed_frames": rebuilds,
                    "substeps_per_rebuild": substeps / max(rebuilds, 1), "chunk": args.chunk or 256},
-        "roofline": {"kernel": "p2g", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "roofline": {"kernel": "p2g_fused" if fused else "p2g", "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "traffic_unit": "HBM bytes per launch",
                      "traffic_frac": (traffic / (p2g_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None,
                      "avg_launch_us": p2g_avg_ms * 1e3, "launches": p2g["launches"],
-                     "bytes_per_particle": P2G_BYTES["snow"]},
+                     "bytes_per_particle": p2g_bytes},
         # the bound P2G actually meets: its LDS atomics against their measured peak rate
-        "roofline_lds": {"kernel": "p2g", "bound": "lds_u64_atomics",
+        "roofline_lds": {"kernel": "p2g_fused" if fused else "p2g", "bound": "lds_u64_atomics",
                          "achieved": P2G_LDS_ATOMICS_PER_PARTICLE * N / (p2g_avg_ms * 1e-3),
                          "peak": LDS_U64_ATOMIC_PEAK, "unit": "lane-ops/s",
                          "frac": P2G_LDS_ATOMICS_PER_PARTICLE * N / (p2g_avg_ms * 1e-3) / LDS_U64_ATOMIC_PEAK},

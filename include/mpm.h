@@ -81,8 +81,8 @@ typedef enum { MPM_BC_STICKY = 0, MPM_BC_SLIP = 1, MPM_BC_SEPARATE = 2 } mpm_bc;
                                             read (particles that leave their zone transfer through global
                                             atomics).  Needs config.stream != 0.  A graph is recorded again
                                             after mpm_add_particles, a new frame_dt or a new chunk size. */
-#define MPM_FLAG_FUSED_G2P 0x40u        /* always run each substep's G2P inside the next substep's P2G
-                                            (see mpm_substep)                                          */
+#define MPM_FLAG_FUSED_G2P 0x40u        /* run each substep's G2P inside the next substep's P2G (the
+                                            default; see mpm_substep)                                  */
 #define MPM_FLAG_SEPARATE_G2P 0x80u     /* never: every substep launches its own G2P               */
 
 #define MPM_MAX_SCENES 256
@@ -181,9 +181,8 @@ int mpm_add_particles(mpm_ctx* ctx, int32_t scene, const mpm_material* mat, int6
 /* Enqueue `nsteps` substeps of every scene.  Each is: [rebuild-mapping + sort
  * when a particle left its free zone] -> P2G -> grid update -> G2P, one launch
  * per phase for all scenes.  A substep's G2P runs inside the next substep's
- * P2G launch (paper, "Merge Kernels": G2P2G) when the context holds fewer
- * than 1,000,000 particles or MPM_FLAG_FUSED_G2P is set --
- * unless MPM_FLAG_SEPARATE_G2P, MPM_FLAG_P2G_GLOBAL_ATOMICS,
+ * P2G launch (paper, "Merge Kernels": G2P2G) unless MPM_FLAG_SEPARATE_G2P,
+ * MPM_FLAG_P2G_GLOBAL_ATOMICS,
  * MPM_FLAG_REBUILD_EVERY_STEP, MPM_FLAG_G2P_GLOBAL_GATHER,
  * MPM_FLAG_FRAME_GRAPHS or a learned / closed-form return map is in use.
  * Calls that read, extend, sample or rebuild the state run the outstanding

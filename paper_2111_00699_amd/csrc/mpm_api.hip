@@ -452,15 +452,12 @@ int check_error_word(mpm_ctx* c) {
 
 // Whether a substep may leave its G2P to the next substep's P2G (the fused
 // kernel needs the LDS tile path, the exact return map and the node-box
-// gather).  By default systems below a million particles fuse: the paper
-// keeps G2P2G below 100K particles (instruction-cache misses beyond that on
-// its GPU); on gfx950 it saves 8-10% of a frame at 6.6K-99K particles and
-// 6.6% at 389K, but changes nothing at 1.28M, where P2G is bound by its LDS
-// scatter.
-constexpr int64_t FUSE_BELOW = 1000000;
+// gather).  The paper keeps G2P2G below 100K particles (instruction-cache
+// misses beyond that on its GPU); on gfx950 with the fixed-point tile it
+// saves 8-10% of a frame at 6.6K-99K particles and 3% at 1.28M, so it is
+// the default at every size.
 bool fusion_allowed(const mpm_ctx* c) {
-    const bool wanted = (c->cfg.flags & MPM_FLAG_FUSED_G2P) ||
-                        (!(c->cfg.flags & MPM_FLAG_SEPARATE_G2P) && c->N < FUSE_BELOW);
+    const bool wanted = (c->cfg.flags & MPM_FLAG_FUSED_G2P) || !(c->cfg.flags & MPM_FLAG_SEPARATE_G2P);
     return wanted && !c->sur_any &&
            !(c->cfg.flags & (MPM_FLAG_P2G_GLOBAL_ATOMICS | MPM_FLAG_REBUILD_EVERY_STEP |
                              MPM_FLAG_G2P_GLOBAL_GATHER | MPM_FLAG_FRAME_GRAPHS));

@@ -145,6 +145,36 @@ def test_single_particle(torch_cuda, oracle):
     sim.close()
 
 
+def test_particle_at_a_cell_edge_keeps_its_tiny_node(torch_cuda, oracle):
+    """Lone particles whose fractional offset is one or a few ulps below 1.5
+    (and above 0.5): their far nodes receive weights of 1e-12 and less and
+    nothing else.  Such contributions bypass the fixed-point tile (which
+    would resolve them to a handful of units) and keep those nodes'
+    velocities; the grid is compared node by node (max norm)."""
+    n = 64
+    x = []
+    for k, ulps in enumerate((1, 3, 40)):
+        t = np.float32(21.5) - np.float32(ulps * 2.0 ** -19)   # x n = 21.5 - ulps * ulp(21.5)
+        lo = np.float32(30.5) + np.float32(ulps * 2.0 ** -19)  # x n = 30.5 + ulps * ulp: f just above 0.5
+        x.append([t / np.float32(n), np.float32(24.3 + 9 * k) / np.float32(n), lo / np.float32(n)])
+    x = np.array(x, dtype=np.float32).T.copy()
+    st = scenes.nontrivial_state(x, seed=11, kind="snow")
+    cfg = dict(n=n, dt=1e-4, bc="separate")
+    print_case("cell_edge", N=x.shape[1])
+    sim = make_sim(torch_cuda, cfg)
+    sim.add_particles(scenes.SNOW, st["x"], v=st["v"], C=st["C"], F=st["F"], s=st["s"])
+    sim.substep(1)
+    gs = gpu_state(sim)
+    gm, gv = (t.cpu().numpy() for t in sim.read_grid())
+    sim.close()
+    os_, om, ov, bad = oracle.substep(cfg, scenes.SNOW, st)
+    assert bad == 0
+    assert om[om > 0].min() < 1e-12 * om.max()  # the case the test is about
+    compare_state(gs, os_, "snow", n=n)
+    assert normwise(gm, om) <= TOL
+    assert normwise(gv, ov) <= TOL
+
+
 @pytest.mark.parametrize("bc", ["sticky", "slip", "separate"])
 def test_particles_against_every_wall(torch_cuda, oracle, bc):
     """Slabs of particles within 0.6-4 cells of each of the six walls, moving
