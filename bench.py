@@ -59,12 +59,12 @@ G2P_BYTES = 72
 # HBM bytes per P2G launch measured with rocprofv3 counters (FETCH_SIZE x 2.0
 # + WRITE_SIZE x 1.0, the factors a plain 1 GiB copy reads back, averaged over
 # the 20,040 launches of the 60 timed frames of the default run);
-# profiles/substep_snow256_counters.md.
-# (The snow scene's 1.28M particles keep G2P a launch of its own.)
+# profiles/substep_snow256_counters.md.  The figure is for the kernel named
+# beside it (the fused P2G, the default).
 # The figure belongs to the P2G sources whose hash is stored beside it: after
 # any change to them the bench reports traffic as null until it is measured
 # again.
-P2G_TRAFFIC = {"kernel": "p2g", "sources_sha256_16": "733c6e3204a4b83a", "bytes": 225.82e6}
+P2G_TRAFFIC = {"kernel": "p2g_fused", "sources_sha256_16": "8b961a32d448ce69", "bytes": 195.71e6}
 P2G_SOURCES = ("paper_2111_00699_amd/csrc/mpm_p2g.hip", "paper_2111_00699_amd/csrc/mpm_internal.h",
                "paper_2111_00699_amd/csrc/mpm_kernels.h", "paper_2111_00699_amd/csrc/mpm_api.hip")
 
