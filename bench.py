@@ -33,6 +33,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# P2G launches are timed with HIP events on a sample: every PROFILE_EVERY-th
+# launch of the timed frames (bracketing all of them would cost the frame
+# time about 4%).
+PROFILE_EVERY = 16
 # LDS 64-bit integer atomic throughput of gfx950, measured with a probe of
 # ds_add_u64 on distinct addresses: 9.1 lane-operations per clock per compute
 # unit, i.e. 9.1 x 256 CUs x 2.4 GHz.  P2G's fixed-point scatter issues 27
@@ -522,7 +526,8 @@ def main():
         log(f"[bench] warmup frame {f + 1}/{args.warmup} enqueued")
     sim.synchronize()
     st0 = sim.stats()
-    sim.profile(mpm.PHASE_P2G | mpm.PHASE_G2P)
+    # every 16th launch: the events cost a few microseconds of stream time each
+    sim.profile(mpm.PHASE_P2G | mpm.PHASE_G2P | mpm.PROFILE_EVERY(PROFILE_EVERY))
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -543,7 +548,7 @@ def main():
     value = N * substeps / (ms * 1e-3)
     p2g = prof["p2g"]
     p2g_avg_ms = p2g["ms"] / max(p2g["launches"], 1)
-    fused = prof["g2p"]["launches"] * 2 < p2g["launches"]  # G2P ran inside P2G
+    fused = prof["g2p"]["launches"] * 2 < p2g["launches"]  # G2P ran inside P2G (sampled alike)
     p2g_bytes = P2G_FUSED_BYTES["snow"] if fused else P2G_BYTES["snow"]
     achieved = p2g_bytes * N / (p2g_avg_ms * 1e-3) / 1e9
     rebuilds = st1["rebuilds"] - st0["rebuilds"]
@@ -573,7 +578,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "traffic_unit": "HBM bytes per launch",
                      "traffic_frac": (traffic / (p2g_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None,
-                     "avg_launch_us": p2g_avg_ms * 1e3, "launches": p2g["launches"],
+                     "avg_launch_us": p2g_avg_ms * 1e3, "launches_timed": p2g["launches"],
+                     "sampled_every": PROFILE_EVERY,
                      "bytes_per_particle": p2g_bytes},
         # the bound P2G actually meets: its LDS atomics against their measured peak rate
         "roofline_lds": {"kernel": "p2g_fused" if fused else "p2g", "bound": "lds_u64_atomics",

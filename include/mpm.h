@@ -150,6 +150,10 @@ typedef struct {
 #define MPM_PHASE_P2G 0x2u
 #define MPM_PHASE_GRID 0x4u
 #define MPM_PHASE_G2P 0x8u
+/* Bracket only every n-th launch of each phase (n in 1..65535), so that the
+ * events (each a few microseconds of stream time) barely disturb what is
+ * being measured. */
+#define MPM_PROFILE_EVERY(n) ((uint32_t)(n) << 16)
 
 typedef struct {
     int64_t launches[4]; /* rebuild, p2g, grid, g2p */
@@ -272,9 +276,10 @@ int mpm_autotune(mpm_ctx* ctx, float frame_dt, int32_t frames, int32_t* chunk_ou
 /* Clear the sticky device error word.                                      */
 int mpm_clear_error(mpm_ctx* ctx);
 
-/* Bracket the phases in `phase_mask` (MPM_PHASE_*) of every later substep
- * with HIP events on the context's stream; 0 turns it off.  Resets the
- * accumulated data.                                                          */
+/* Bracket the phases in `phase_mask` (MPM_PHASE_*, optionally with
+ * MPM_PROFILE_EVERY(n)) of every later substep, or of every n-th launch of
+ * each phase, with HIP events on the context's stream; 0 turns it off.
+ * Synchronizes and resets the accumulated data.                             */
 int mpm_profile(mpm_ctx* ctx, uint32_t phase_mask);
 
 /* Synchronize and return the accumulated per-phase launch counts and

@@ -115,6 +115,8 @@ struct mpm_ctx {
     std::vector<Pair> prof;
     int prof_next = 0;
     int64_t prof_launch[4] = {0, 0, 0, 0};
+    uint32_t prof_every = 1;                 // bracket every prof_every-th launch of a phase
+    int64_t prof_seen[4] = {0, 0, 0, 0};     // launches of each phase since mpm_profile
     double prof_ms[4] = {0, 0, 0, 0};
 
     std::string err;
@@ -330,6 +332,7 @@ int prof_accumulate(mpm_ctx* c, mpm_ctx::Pair& p) {
 int prof_begin(mpm_ctx* c, int phase, int* slot) {
     *slot = -1;
     if (!(c->prof_mask & (1u << phase))) return MPM_OK;
+    if (c->prof_seen[phase]++ % c->prof_every != 0) return MPM_OK;
     if (c->prof.empty()) {
         c->prof.resize(PROF_SLOTS);
         for (auto& p : c->prof) {
@@ -1082,10 +1085,12 @@ int mpm_profile(mpm_ctx* c, uint32_t mask) {
     HIP_OK(c, hipStreamSynchronize(c->stream));
     for (auto& p : c->prof) p.live = false;
     c->prof_mask = 0;
+    c->prof_every = (mask >> 16) ? (mask >> 16) : 1u;
     for (int i = 0; i < 4; ++i) {
         if (mask & (1u << i)) c->prof_mask |= 1u << i;
         c->prof_launch[i] = 0;
         c->prof_ms[i] = 0.0;
+        c->prof_seen[i] = 0;
     }
     return MPM_OK;
 }

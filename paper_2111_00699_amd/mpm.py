@@ -23,6 +23,11 @@ FLAG_REBUILD_EVERY_STEP, FLAG_P2G_GLOBAL_ATOMICS, FLAG_MANUAL_REBUILD, FLAG_P2G_
 FLAG_G2P_GLOBAL_GATHER, FLAG_FRAME_GRAPHS, FLAG_FUSED_G2P, FLAG_SEPARATE_G2P = 0x10, 0x20, 0x40, 0x80
 MAX_SCENES = 256
 PHASE_REBUILD, PHASE_P2G, PHASE_GRID, PHASE_G2P = 0x1, 0x2, 0x4, 0x8
+
+
+def PROFILE_EVERY(n: int) -> int:
+    """Mask bits that bracket only every n-th launch of a phase."""
+    return (int(n) & 0xFFFF) << 16
 PHASES = ("rebuild", "p2g", "grid", "g2p")
 
 

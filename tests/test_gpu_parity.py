@@ -465,6 +465,18 @@ def test_profile_counts_launches(torch_cuda):
         assert prof["g2p"]["launches"] == g2p_after, flags
         assert all(prof[k]["ms"] > 0 for k in ("p2g", "grid", "g2p"))
         sim.close()
+    # sampled: every 4th launch of each phase is bracketed (launches 0, 4, 8 of 10)
+    from paper_2111_00699_amd import mpm
+
+    sim = make_sim(torch_cuda, scenes.jelly_config())
+    sim.add_particles(scenes.JELLY, sc["x"])
+    sim.profile(mpm.PHASE_P2G | mpm.PHASE_GRID | mpm.PROFILE_EVERY(4))
+    sim.substep(10)
+    prof = sim.profile_read()
+    assert prof["p2g"]["launches"] == 3 and prof["grid"]["launches"] == 3
+    assert prof["g2p"]["launches"] == 0 and prof["rebuild"]["launches"] == 0
+    assert prof["p2g"]["ms"] > 0
+    sim.close()
 
 
 def test_fused_g2p_matches_separate_g2p_bit_for_bit(torch_cuda):
