@@ -268,6 +268,10 @@ __device__ __forceinline__ void eig_sym3(float b00, float b01, float b02, float 
     float u00 = 1, u01 = 0, u02 = 0, u10 = 0, u11 = 1, u12 = 0, u20 = 0, u21 = 0, u22 = 1;
 #pragma unroll
     for (int sweep = 0; sweep < 3; ++sweep) {  // quadratic convergence: 3 sweeps reach FP32 rounding
+        // the third sweep only if some lane of the wave still has off-diagonal mass above
+        // FP32 rounding (|offdiag| > 1e-7 |diag|)
+        if (sweep == 2 && __all(b01 * b01 + b02 * b02 + b12 * b12 <= 1e-14f * (b00 * b00 + b11 * b11 + b22 * b22)))
+            break;
         jacobi_rotate(b00, b11, b01, b02, b12, u00, u01, u10, u11, u20, u21);  // (0,1), r = 2
         jacobi_rotate(b00, b22, b02, b01, b12, u00, u02, u10, u12, u20, u22);  // (0,2), r = 1
         jacobi_rotate(b11, b22, b12, b01, b02, u01, u02, u11, u12, u21, u22);  // (1,2), r = 0

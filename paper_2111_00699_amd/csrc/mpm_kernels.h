@@ -111,30 +111,38 @@ __device__ __forceinline__ void g2p_gather(const Stencil& st, const float4* tv, 
         r[a] = st.base[a] - lo[a];
         inbox = inbox && r[a] >= 0 && r[a] + 2 < e[a];
     }
+    // Separable sums: along each x-row (o1, o2) r_a = sum_o0 wx[o0] v_a and
+    // rx_a = sum_o0 o0 wx[o0] v_a, then v' += wyz r, Mo_a0 += wyz rx_a,
+    // Mo_a1 += o1 wyz r_a, Mo_a2 += o2 wyz r_a (terms with a zero offset are
+    // not formed).
     float Mo[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // sum w v_a o_b
 #pragma unroll
     for (int a = 0; a < 3; ++a) vp[a] = 0.0f;
+    const float wx1 = st.w[0][1], wx2 = st.w[0][2], wx2d = 2.0f * st.w[0][2];
+    auto row = [&](int o1, int o2, const float4 g0, const float4 g1, const float4 g2) {
+        const float wyz = st.w[1][o1] * st.w[2][o2];
+        const float rr[3] = {st.w[0][0] * g0.x + wx1 * g1.x + wx2 * g2.x, st.w[0][0] * g0.y + wx1 * g1.y + wx2 * g2.y,
+                             st.w[0][0] * g0.z + wx1 * g1.z + wx2 * g2.z};
+        const float rx[3] = {wx1 * g1.x + wx2d * g2.x, wx1 * g1.y + wx2d * g2.y, wx1 * g1.z + wx2d * g2.z};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float t = wyz * rr[a];
+            vp[a] += t;
+            Mo[a * 3 + 0] += wyz * rx[a];
+            if (o1 == 1) Mo[a * 3 + 1] += t;
+            if (o1 == 2) Mo[a * 3 + 1] += 2.0f * t;
+            if (o2 == 1) Mo[a * 3 + 2] += t;
+            if (o2 == 2) Mo[a * 3 + 2] += 2.0f * t;
+        }
+    };
     if (inbox) {
         const int tb = r[0] + R * r[1] + Q * r[2];
 #pragma unroll
         for (int o2 = 0; o2 < 3; ++o2)
 #pragma unroll
             for (int o1 = 0; o1 < 3; ++o1) {
-                const float wyz = st.w[1][o1] * st.w[2][o2];
-                const int row = tb + R * o1 + Q * o2;
-#pragma unroll
-                for (int o0 = 0; o0 < 3; ++o0) {
-                    const float w = wyz * st.w[0][o0];
-                    const float4 g = tv[row + o0];
-                    const float wv[3] = {w * g.x, w * g.y, w * g.z};
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        vp[a] += wv[a];
-                        Mo[a * 3 + 0] += o0 * wv[a];
-                        Mo[a * 3 + 1] += o1 * wv[a];
-                        Mo[a * 3 + 2] += o2 * wv[a];
-                    }
-                }
+                const int t = tb + R * o1 + Q * o2;
+                row(o1, o2, tv[t], tv[t + 1], tv[t + 2]);
             }
     } else {
         int xo[3], yo[3], zo[3];
@@ -145,20 +153,8 @@ __device__ __forceinline__ void g2p_gather(const Stencil& st, const float4* tv, 
         for (int o2 = 0; o2 < 3; ++o2)
 #pragma unroll
             for (int o1 = 0; o1 < 3; ++o1) {
-                const float wyz = st.w[1][o1] * st.w[2][o2];
-#pragma unroll
-                for (int o0 = 0; o0 < 3; ++o0) {
-                    const float w = wyz * st.w[0][o0];
-                    const float4 g = vels[xo[o0] + yo[o1] + zo[o2]];
-                    const float wv[3] = {w * g.x, w * g.y, w * g.z};
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        vp[a] += wv[a];
-                        Mo[a * 3 + 0] += o0 * wv[a];
-                        Mo[a * 3 + 1] += o1 * wv[a];
-                        Mo[a * 3 + 2] += o2 * wv[a];
-                    }
-                }
+                const int t = yo[o1] + zo[o2];
+                row(o1, o2, vels[xo[0] + t], vels[xo[1] + t], vels[xo[2] + t]);
             }
     }
     // C' = 4/dx^2 sum w v (x_i - x_p)^T = (4/dx) (Mo - v' f^T)
