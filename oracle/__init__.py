@@ -8,7 +8,8 @@ single-threaded); this module is a ctypes shim that marshals numpy arrays.
 
 State dictionaries use structure-of-arrays numpy float64 arrays:
 ``x (3,N)``, ``v (3,N)``, ``C (9,N)``, ``F (9,N)`` (entry (a,b) at a*3+b),
-``s (N,)`` (J_P for snow, J for water, ignored for jelly).
+``s (N,)`` (J_P for snow, 1 + q with q the hardening state for sand, J for
+water, ignored for jelly).
 """
 from __future__ import annotations
 
@@ -22,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mpm_oracle.c")
 _LIB = os.path.join(_HERE, "libmpm_oracle.so")
 
-KIND = {"jelly": 0, "snow": 1, "water": 2}
+KIND = {"jelly": 0, "snow": 1, "water": 2, "sand": 3}
 BC = {"sticky": 0, "slip": 1, "separate": 2}
 
 
@@ -37,7 +38,8 @@ def build(force: bool = False) -> str:
 
 class _Mat(ct.Structure):
     _fields_ = [("kind", ct.c_int)] + [(k, ct.c_double) for k in
-                                       ("E", "nu", "rho", "ppc", "theta_c", "theta_s", "xi", "bulk")]
+                                       ("E", "nu", "rho", "ppc", "theta_c", "theta_s", "xi", "bulk",
+                                        "h0", "h1", "h2", "h3")]
 
 
 class _Cfg(ct.Structure):
@@ -63,6 +65,9 @@ def lib():
             "om_fixed_corotated": (None, [D, ct.c_double, ct.c_double, D]),
             "om_stress": (None, [ct.POINTER(_Mat), D, ct.c_double, D]),
             "om_snow_project": (None, [ct.POINTER(_Mat), D, ct.c_double, D, D]),
+            "om_hencky": (None, [D, ct.c_double, ct.c_double, D]),
+            "om_sand_alpha": (ct.c_double, [ct.POINTER(_Mat), ct.c_double]),
+            "om_sand_project": (None, [ct.POINTER(_Mat), D, ct.c_double, D, D]),
             "om_weights": (None, [ct.c_double, ct.POINTER(ct.c_int), D]),
             "om_p2g": (L, [ct.POINTER(_Cfg), ct.POINTER(_Mat), L, D, D, D, D, D, D, D]),
             "om_grid_update": (None, [ct.POINTER(_Cfg), D, D]),
@@ -88,7 +93,8 @@ def _p(a, ctype):
 def _mat(m: dict) -> _Mat:
     kind = m["kind"] if isinstance(m["kind"], int) else KIND[m["kind"]]
     return _Mat(kind, *(float(m.get(k, 0.0)) for k in
-                        ("E", "nu", "rho", "ppc", "theta_c", "theta_s", "xi", "bulk")))
+                        ("E", "nu", "rho", "ppc", "theta_c", "theta_s", "xi", "bulk",
+                         "h0", "h1", "h2", "h3")))
 
 
 def _cfg(c: dict) -> _Cfg:
@@ -150,6 +156,29 @@ def snow_project(mat: dict, Fhat: np.ndarray, Jp: float):
     m = _mat(mat)
     lib().om_snow_project(ct.byref(m), _p(Fhat, ct.c_double), float(Jp), _p(Fe, ct.c_double), ct.byref(jp))
     return Fe.reshape(3, 3), jp.value
+
+
+def hencky(F: np.ndarray, mu: float, la: float) -> np.ndarray:
+    """Kirchhoff stress of the sand's log-strain (Hencky) elasticity."""
+    F = np.ascontiguousarray(F, dtype=np.float64).reshape(9)
+    tau = np.zeros(9)
+    lib().om_hencky(_p(F, ct.c_double), mu, la, _p(tau, ct.c_double))
+    return tau.reshape(3, 3)
+
+
+def sand_alpha(mat: dict, q: float) -> float:
+    m = _mat(mat)
+    return lib().om_sand_alpha(ct.byref(m), float(q))
+
+
+def sand_project(mat: dict, Fhat: np.ndarray, q: float):
+    """Drucker-Prager return map: (elastic gradient, new hardening state q)."""
+    Fhat = np.ascontiguousarray(Fhat, dtype=np.float64).reshape(9)
+    Fe = np.zeros(9)
+    qo = ct.c_double(0.0)
+    m = _mat(mat)
+    lib().om_sand_project(ct.byref(m), _p(Fhat, ct.c_double), float(q), _p(Fe, ct.c_double), ct.byref(qo))
+    return Fe.reshape(3, 3), qo.value
 
 
 def weights(t: float):

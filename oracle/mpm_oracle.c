@@ -22,6 +22,7 @@
  * Layout conventions (shared only as a documented data format):
  *   particle arrays are structure-of-arrays: x[3][N], v[3][N], C[9][N],
  *   F[9][N] with matrix entry (a,b) at component a*3+b, s[N] (J_P for snow,
+ *   1 + q, q the hardening state, for sand,
  *   J for water, unused for jelly).  Dense grid node (i,j,k) sits at
  *   (i,j,k)*dx and is stored at ((i*(n+1))+j)*(n+1)+k; vector grid fields are
  *   [3][(n+1)^3].
@@ -32,8 +33,10 @@
 #include <string.h>
 
 typedef struct {
-    int kind; /* 0 fixed-corotated jelly, 1 snow (clamped SVD + hardening), 2 water */
+    int kind; /* 0 fixed-corotated jelly, 1 snow (clamped SVD + hardening), 2 water,
+                 3 sand (Hencky elasticity, Drucker-Prager return map with hardening) */
     double E, nu, rho, ppc, theta_c, theta_s, xi, bulk;
+    double h0, h1, h2, h3; /* sand friction angle (degrees) phi(q) = h0 + (h1 q - h3) exp(-h2 q) */
 } om_material;
 
 typedef struct {
@@ -44,7 +47,7 @@ typedef struct {
     double dt;
 } om_config;
 
-enum { OM_JELLY = 0, OM_SNOW = 1, OM_WATER = 2 };
+enum { OM_JELLY = 0, OM_SNOW = 1, OM_WATER = 2, OM_SAND = 3 };
 
 /* ---------------------------------------------------------------- 3x3 util */
 static void mat_mul(const double A[9], const double B[9], double out[9]) {
@@ -178,6 +181,86 @@ void om_fixed_corotated(const double F[9], double mu, double la, double tau[9]) 
     for (int a = 0; a < 3; ++a) tau[a * 3 + a] += la * (J - 1.0) * J;
 }
 
+/* Hencky (St. Venant-Kirchhoff in logarithmic strain) Kirchhoff stress, the
+ * elasticity of the Drucker-Prager sand of Klar et al. 2016 (the sand model
+ * the paper uses is not given in it; this one stands in).  With
+ * F = U diag(sig) V^T and eps_k = log sig_k the energy is
+ * psi = mu sum eps_k^2 + la/2 (sum eps_k)^2, whose Kirchhoff stress is
+ * tau = U diag(2 mu eps_k + la sum eps) U^T.  The sign an inverted gradient
+ * gives its smallest singular value is dropped (eps_k = log |sig_k|, and
+ * |sig_k| is floored at OM_SAND_SIG_FLOOR).                                  */
+#define OM_SAND_SIG_FLOOR 1e-6
+static double sand_log(double sig) {
+    double a = fabs(sig);
+    return log(a > OM_SAND_SIG_FLOOR ? a : OM_SAND_SIG_FLOOR);
+}
+
+void om_hencky(const double F[9], double mu, double la, double tau[9]) {
+    double U[9], S[3], V[9], e[3];
+    om_svd3(F, U, S, V);
+    for (int k = 0; k < 3; ++k) e[k] = sand_log(S[k]);
+    double tr = e[0] + e[1] + e[2];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double acc = 0.0;
+            for (int k = 0; k < 3; ++k) acc += U[a * 3 + k] * (2.0 * mu * e[k] + la * tr) * U[b * 3 + k];
+            tau[a * 3 + b] = acc;
+        }
+}
+
+/* Drucker-Prager friction coefficient of hardening state q: the friction
+ * angle phi = h0 + (h1 q - h3) exp(-h2 q) degrees, and
+ * alpha = sqrt(2/3) * 2 sin(phi) / (3 - sin(phi)), the cone that matches the
+ * Mohr-Coulomb surface of angle phi in triaxial compression.               */
+double om_sand_alpha(const om_material* m, double q) {
+    const double pi = 3.14159265358979323846;
+    double phi = (m->h0 + (m->h1 * q - m->h3) * exp(-m->h2 * q)) * pi / 180.0;
+    double sp = sin(phi);
+    return sqrt(2.0 / 3.0) * 2.0 * sp / (3.0 - sp);
+}
+
+/* Sand return map (Klar et al. 2016, in logarithmic strain): with
+ * eps = log sig of the trial gradient, its trace t and deviator d,
+ *   t > 0 (expansion): all elastic strain is released (eps' = 0) and the
+ *     hardening state grows by |eps|;
+ *   else, with dg = |d| + (3 la + 2 mu)/(2 mu) t alpha(q):
+ *     dg <= 0: the state is inside the cone and unchanged;
+ *     dg > 0: the deviator shrinks along itself by dg (eps' = eps - dg d/|d|,
+ *       the trace, i.e. the volume, is kept) and q grows by dg.
+ * Fe = U diag(exp eps') V^T; q_out the new hardening state.                */
+void om_sand_project(const om_material* m, const double Fhat[9], double q, double Fe[9], double* q_out) {
+    double mu, la, U[9], S[3], V[9], e[3], en[3], US[9];
+    lame(m, &mu, &la);
+    om_svd3(Fhat, U, S, V);
+    for (int k = 0; k < 3; ++k) e[k] = sand_log(S[k]);
+    double t = e[0] + e[1] + e[2];
+    double d[3], nd = 0.0, ne = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        d[k] = e[k] - t / 3.0;
+        nd += d[k] * d[k];
+        ne += e[k] * e[k];
+    }
+    nd = sqrt(nd);
+    ne = sqrt(ne);
+    double dq = 0.0;
+    if (t > 0.0) {
+        for (int k = 0; k < 3; ++k) en[k] = 0.0;
+        dq = ne;
+    } else {
+        double dg = nd + (3.0 * la + 2.0 * mu) / (2.0 * mu) * t * om_sand_alpha(m, q);
+        if (dg <= 0.0) {
+            for (int k = 0; k < 3; ++k) en[k] = e[k];
+        } else {
+            for (int k = 0; k < 3; ++k) en[k] = e[k] - dg * d[k] / nd;
+            dq = dg;
+        }
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) US[i * 3 + k] = U[i * 3 + k] * exp(en[k]);
+    mat_mul_bt(US, V, Fe);
+    *q_out = q + dq;
+}
+
 /* Kirchhoff stress of the stored particle state.                            */
 void om_stress(const om_material* m, const double F[9], double s, double tau[9]) {
     double mu, la;
@@ -187,6 +270,8 @@ void om_stress(const om_material* m, const double F[9], double s, double tau[9])
     } else if (m->kind == OM_SNOW) {
         double h = exp(m->xi * (1.0 - s)); /* hardening from the plastic volume J_P */
         om_fixed_corotated(F, mu * h, la * h, tau);
+    } else if (m->kind == OM_SAND) {
+        om_hencky(F, mu, la, tau);
     } else { /* water: psi = K/2 (J-1)^2, tau = J dpsi/dJ I */
         double J = s;
         for (int i = 0; i < 9; ++i) tau[i] = 0.0;
@@ -356,6 +441,11 @@ long om_g2p(const om_config* cfg, const om_material* mat, long N, double* x, dou
                 om_snow_project(mat, Fn, s[p], Fe, &Jp);
                 memcpy(Fn, Fe, sizeof Fe);
                 s[p] = Jp;
+            } else if (mat->kind == OM_SAND) { /* s holds 1 + q */
+                double Fe[9], q;
+                om_sand_project(mat, Fn, s[p] - 1.0, Fe, &q);
+                memcpy(Fn, Fe, sizeof Fe);
+                s[p] = 1.0 + q;
             }
             for (int c = 0; c < 9; ++c) F[c * N + p] = Fn[c];
         }

@@ -48,6 +48,10 @@ def uniform(seed: int, count: int, stream: int = 0, lo: float = 0.0, hi: float =
 JELLY = dict(kind="jelly", E=1e4, nu=0.2, rho=1.0, ppc=8.0)
 SNOW = dict(kind="snow", E=1.4e5, nu=0.2, rho=400.0, ppc=8.0, theta_c=2.5e-2, theta_s=7.5e-3, xi=10.0)
 WATER = dict(kind="water", rho=1000.0, ppc=8.0, bulk=1e4)
+# Drucker-Prager sand (Klar et al. 2016's hardening constants h0..h3; its Young's
+# modulus scaled down tenfold so that the Sand Blocks time step of 1/48 s / 36
+# stays below the elastic wave's CFL limit on cells of 1/128)
+SAND = dict(kind="sand", E=3.537e4, nu=0.3, rho=2200.0, ppc=8.0, h0=35.0, h1=9.0, h2=0.2, h3=10.0)
 
 FRAME = 1.0 / 60.0
 
@@ -89,7 +93,8 @@ def nontrivial_state(x: np.ndarray, seed: int = 5, kind: str = "jelly") -> dict:
     """A random, non-trivial particle state around positions x (3,N):
     v ~ U(-0.5,0.5) m/s, C ~ U(-5,5) 1/s, F = I + U(-0.05,0.05) per entry
     (det F > 0.8 for such perturbations), and J_P ~ U(0.9,1.05) (snow) or
-    J ~ U(0.95,1.05) (water)."""
+    J ~ U(0.95,1.05) (water), or 1 + q with the hardening state q ~ U(0,0.5)
+    (sand)."""
     N = x.shape[1]
     v = uniform(seed, 3 * N, 1, -0.5, 0.5).reshape(3, N)
     C = uniform(seed, 9 * N, 2, -5.0, 5.0).reshape(9, N)
@@ -101,6 +106,8 @@ def nontrivial_state(x: np.ndarray, seed: int = 5, kind: str = "jelly") -> dict:
         st["s"] = uniform(seed, N, 4, 0.9, 1.05).astype(np.float32)
     elif kind == "water":
         st["s"] = uniform(seed, N, 4, 0.95, 1.05).astype(np.float32)
+    elif kind == "sand":
+        st["s"] = uniform(seed, N, 4, 1.0, 1.5).astype(np.float32)
     return st
 
 

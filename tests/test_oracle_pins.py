@@ -73,7 +73,8 @@ def _state(seed, n=32, N=500, kind="jelly"):
     return scenes.nontrivial_state(x, seed=seed, kind=kind)
 
 
-@pytest.mark.parametrize("kind,mat", [("jelly", scenes.JELLY), ("snow", scenes.SNOW), ("water", scenes.WATER)])
+@pytest.mark.parametrize("kind,mat", [("jelly", scenes.JELLY), ("snow", scenes.SNOW), ("water", scenes.WATER),
+                                      ("sand", scenes.SAND)])
 def test_p2g_conserves_mass_and_momentum(oracle, kind, mat):
     st = _state(21, kind=kind)
     n = 32
@@ -132,13 +133,16 @@ def _psi(mat, F, s):
     if J < 0:
         sig[-1] = -sig[-1]
     mu, la = lame(mat["E"], mat["nu"])
+    if mat["kind"] == "sand":  # Hencky: quadratic in the logarithmic strain
+        e = np.log(np.abs(sig))
+        return mu * np.sum(e * e) + 0.5 * la * np.sum(e) ** 2
     if mat["kind"] == "snow":
         h = np.exp(mat["xi"] * (1 - s))
         mu, la = mu * h, la * h
     return mu * np.sum((sig - 1) ** 2) + 0.5 * la * (J - 1) ** 2
 
 
-@pytest.mark.parametrize("mat", [scenes.JELLY, scenes.SNOW, scenes.WATER])
+@pytest.mark.parametrize("mat", [scenes.JELLY, scenes.SNOW, scenes.WATER, scenes.SAND])
 def test_p2g_force_is_energy_gradient(oracle, mat):
     """MLS-MPM: the stress part of the nodal momentum is dt * f_i with
     f_i = -dE/dx_i, E = sum_p V0 psi(F_p(x)), where moving node i by delta
