@@ -6,7 +6,7 @@ its free zone, P2G with the fused snow return map and stress, grid update
 with boundary conditions, G2P with the free-zone test).  Prints ONE JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                    [--workload snow|fountain|batched|surrogate]
+                    [--workload snow|fountain|batched|surrogate|ablations|sand]
 
 By default K = 60 timed frames after W = 1 warmup frame, so `value` is the
 average over 60 frames of the falling, landing and settling snow, as the
@@ -269,6 +269,78 @@ def bench_fountain(args):
     print(json.dumps(out), flush=True)
 
 
+SAND_SIZES = (12, 23, 46)  # box side in cells: 55,296 / 389,344 / 3,114,752 particles (4 boxes)
+
+
+def bench_sand(args):
+    """Sand Blocks, the paper's main benchmark: 4 boxes of l^3 cells
+    (l = 12, 23, 46) of Drucker-Prager sand at 8 ppc dropped into a
+    frictionless 128^3 box; frames of 1/48 s in 36 substeps, one warmup frame
+    and `steps` timed frames (60, as the paper averages).  Reports ms per
+    frame per size; `value` is the largest size's particle-substeps/s."""
+    import torch
+
+    from paper_2111_00699_amd import mpm, scenes
+
+    torch.cuda.set_device(0)
+    cfg = scenes.sand_config()
+    nsub = cfg["substeps_per_frame"]
+    frames = args.steps
+    stream = torch.cuda.current_stream()
+    runs = {}
+    for l in SAND_SIZES:
+        x = scenes.sand_blocks(l=l, boxes=4, n=cfg["n"])["x"]
+        N = x.shape[1]
+        sim = mpm.Sim(cfg["n"], cfg["dt"], bc=cfg["bc"], bc_cells=cfg["bc_cells"], gravity=cfg["gravity"],
+                      capacity=2 * N + 256, flags=args.flags, chunk=args.chunk)
+        sim.add_particles(scenes.SAND, x)
+        for _ in range(args.warmup):
+            sim.substep(nsub)
+        sim.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(frames + 1)]
+        r0 = sim.stats()["rebuilds"]
+        w0 = time.perf_counter()
+        ev[0].record(stream)
+        for f in range(frames):
+            sim.substep(nsub)
+            ev[f + 1].record(stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - w0) * 1e3
+        ms = [ev[f].elapsed_time(ev[f + 1]) for f in range(frames)]
+        st = sim.stats()
+        p = sim.read_particles()
+        xs = p["x"].cpu().numpy()
+        q = p["s"].cpu().numpy() - 1.0
+        sim.close()
+        if st["error"]:
+            raise RuntimeError(f"sand blocks l={l}: device error word {st['error']}")
+        total = max(sum(ms), wall)
+        runs[f"4x{l}^3"] = {"particles": N, "ms_per_frame": round(total / frames, 3),
+                            "gpu_event_ms": round(sum(ms), 2), "wall_ms": round(wall, 2),
+                            "value": N * nsub * frames / (total * 1e-3),
+                            "rebuilds_per_frame": round((st["rebuilds"] - r0) / frames, 2),
+                            "final_y_range": [float(xs[1].min()), float(xs[1].max())],
+                            "plastic_fraction": float((q > 0).mean()),
+                            "ms_per_frame_min_max": [round(min(ms), 3), round(max(ms), 3)]}
+        log(f"[bench] sand blocks 4x{l}^3 N={N}: {total / frames:.3f} ms per frame, "
+            f"{runs[f'4x{l}^3']['rebuilds_per_frame']} rebuilds per frame")
+    big = runs[f"4x{SAND_SIZES[-1]}^3"]
+    out = {
+        "metric": "particle-substeps/s",
+        "value": big["value"],
+        "unit": "particle-substeps/s",
+        "n_gpus": 1, "steps": frames, "warmup": args.warmup,
+        "ms_per_step": big["ms_per_frame"], "ms_per_frame": big["ms_per_frame"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "sand blocks: 4 boxes of l^3 cells (l = 12, 23, 46) of Drucker-Prager sand at 8 ppc "
+                               "in a 128^3 slip box, 36 substeps per 1/48 s frame; value is l = 46 "
+                               "(3,114,752 particles)",
+                   "grid": cfg["n"], "substeps_per_frame": nsub, "frame_s": cfg["frame"]},
+        "runs": runs,
+    }
+    print(json.dumps(out), flush=True)
+
+
 ABLATIONS = (  # (name, library flags, chunk size); the baseline first
     ("baseline", 0, 0),
     ("rebuild_every_step", 0x1, 0),    # no free zone: rebuild and sort before every substep
@@ -285,31 +357,32 @@ ABLATIONS = (  # (name, library flags, chunk size); the baseline first
 
 def bench_ablations(args):
     """The paper's single-GPU ablations, on this library: each design choice
-    switched off by a flag (or a chunk size), ms per 1/60 s frame and the
-    extra cost against the default build.  Scenes: the Sand Blocks layout
-    (4 boxes of 12^3 and of 23^3 cells at 8 ppc, 55,296 and 389,344
-    particles; fixed-corotated jelly stands in for the paper's sand model) in a
-    128^3 grid with slip walls, and the snow scene (1.28M particles)."""
+    switched off by a flag (or a chunk size), ms per frame and the extra cost
+    against the default build.  Scenes: Sand Blocks (4 boxes of 12^3 and of
+    23^3 cells at 8 ppc, 55,296 and 389,344 particles, Drucker-Prager sand)
+    in a 128^3 grid with slip walls, frames of 1/48 s in 36 substeps as in
+    the paper, timed from the second frame; and the snow scene (1.28M
+    particles, 1/60 s frames of 334 substeps)."""
     import torch
 
     from paper_2111_00699_amd import mpm, scenes
 
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
-    frame = scenes.FRAME
-    jelly_dt = scenes.frame_substeps(5e-5)[1]
     snow = scenes.snow_config()
+    sand = scenes.sand_config()
     cases = []
-    for l, frames in ((12, 10), (23, 4)):
+    for l, frames in ((12, 10), (23, 10)):
         x = scenes.sand_blocks(l=l, boxes=4, n=128)["x"]
-        cases.append((f"sand_blocks_4x{l}^3", x, scenes.JELLY, dict(n=128, dt=jelly_dt, bc="slip", bc_cells=3,
-                                                                    gravity=(0.0, -9.8, 0.0)), frames))
+        cases.append((f"sand_blocks_4x{l}^3", x, scenes.SAND, dict(n=sand["n"], dt=sand["dt"], bc=sand["bc"],
+                                                                   bc_cells=sand["bc_cells"], gravity=sand["gravity"]),
+                      frames, sand["frame"]))
     cases.append(("snow", scenes.snow_spheres(1)["x"], scenes.SNOW,
                   dict(n=snow["n"], dt=snow["dt"], bc=snow["bc"], bc_cells=snow["bc_cells"],
-                       gravity=snow["gravity"]), 2))
+                       gravity=snow["gravity"]), 2, scenes.FRAME))
     table = {}
     with torch.cuda.stream(stream):
-        for name, x, mat, cfg, frames in cases:
+        for name, x, mat, cfg, frames, frame in cases:
             N = x.shape[1]
             rows = {}
             for cname, flags, chunk in ABLATIONS:
@@ -345,7 +418,8 @@ def bench_ablations(args):
         "ms_per_step": snow_base, "ms_per_frame": snow_base,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "ablations: each design choice switched off in turn on the Sand Blocks layout "
-                               "(4 boxes of 12^3 and 23^3 cells, jelly stand-in, 128^3) and the snow scene; "
+                               "(4 boxes of 12^3 and 23^3 cells, Drucker-Prager sand, 128^3, 36 substeps per 1/48 s "
+                               "frame) and the snow scene; "
                                "value is the snow baseline over its timed frames 2-3"},
         "ablations": table,
     }
@@ -470,7 +544,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--flags", type=int, default=0)
-    ap.add_argument("--workload", choices=("snow", "batched", "surrogate", "fountain", "ablations"), default="snow")
+    ap.add_argument("--workload", choices=("snow", "batched", "surrogate", "fountain", "ablations", "sand"),
+                    default="snow")
     ap.add_argument("--train-snapshots", type=int, default=4, help="surrogate: training snapshots per scene")
     ap.add_argument("--train-steps", type=int, default=20000, help="surrogate: Adam steps")
     ap.add_argument("--sur-tol", type=float, default=2e-3, help="surrogate: residual tolerance")
@@ -479,7 +554,8 @@ def main():
                     help="only run a plain 1 GiB device-to-device copy 4 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.steps is None:
-        args.steps = {"snow": 60, "fountain": 60, "batched": 10, "surrogate": 5, "ablations": 0}[args.workload]
+        args.steps = {"snow": 60, "fountain": 60, "batched": 10, "surrogate": 5, "ablations": 0,
+                      "sand": 60}[args.workload]
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
@@ -507,6 +583,9 @@ def main():
         return
     if args.workload == "ablations":
         bench_ablations(args)
+        return
+    if args.workload == "sand":
+        bench_sand(args)
         return
 
     from paper_2111_00699_amd import mpm, scenes

@@ -57,7 +57,7 @@ typedef enum {
     MPM_ESTATE = -4   /* the sticky device error word is set */
 } mpm_status;
 
-typedef enum { MPM_JELLY = 0, MPM_SNOW = 1, MPM_WATER = 2 } mpm_kind;
+typedef enum { MPM_JELLY = 0, MPM_SNOW = 1, MPM_WATER = 2, MPM_SAND = 3 } mpm_kind;
 typedef enum { MPM_BC_STICKY = 0, MPM_BC_SLIP = 1, MPM_BC_SEPARATE = 2 } mpm_bc;
 
 /* bits of the sticky device error word */
@@ -119,10 +119,22 @@ typedef struct {
  *   jelly: fixed-corotated elasticity (E, nu)
  *   snow : fixed-corotated with hardening exp(xi (1 - J_P)) and singular values
  *          clamped to [1 - theta_c, 1 + theta_s]
- *   water: tau = bulk (J - 1) J I                                           */
+ *   water: tau = bulk (J - 1) J I
+ *   sand : a stand-in for the sand model the paper cites (not given in it):
+ *          Hencky elasticity tau = U diag(2 mu eps + lambda tr eps) U^T with
+ *          eps = log |sig| (floored at log 1e-6), and the Drucker-Prager
+ *          return map of Klar et al. 2016 in logarithmic strain: expansion
+ *          (tr eps > 0) releases all elastic strain; otherwise, with d the
+ *          deviator of eps and dg = |d| + (3 lambda + 2 mu)/(2 mu) tr eps alpha,
+ *          dg > 0 scales d down by dg (the volume is kept).  alpha =
+ *          sqrt(2/3) 2 sin phi / (3 - sin phi) for the friction angle
+ *          phi = h0 + (h1 q - h3) exp(-h2 q) degrees, q the hardening state,
+ *          which grows by the log strain each return map removes.  The
+ *          particle's s holds 1 + q (so the default s = 1 is q = 0).        */
 typedef struct {
     int32_t kind; /* mpm_kind */
     float E, nu, rho, ppc, theta_c, theta_s, xi, bulk;
+    float h0, h1, h2, h3; /* sand hardening constants (degrees, degrees, 1, degrees); ignored otherwise */
 } mpm_material;
 
 typedef struct {

@@ -153,12 +153,19 @@ Mat derive_material(const mpm_material& m, const Step& P) {
     M.hi = 1.0f + m.theta_s;
     M.xi = m.xi;
     M.bulk = m.bulk;
+    const float deg = 3.14159265358979f / 180.0f;
+    M.h0 = m.h0 * deg;
+    M.h1 = m.h1 * deg;
+    M.h2 = m.h2;
+    M.h3 = m.h3 * deg;
+    M.kdp = (3.0f * M.la + 2.0f * M.mu) / (2.0f * M.mu);
     return M;
 }
 
 bool same_material(const mpm_material& a, const mpm_material& b) {
     return a.kind == b.kind && a.E == b.E && a.nu == b.nu && a.rho == b.rho && a.ppc == b.ppc &&
-           a.theta_c == b.theta_c && a.theta_s == b.theta_s && a.xi == b.xi && a.bulk == b.bulk;
+           a.theta_c == b.theta_c && a.theta_s == b.theta_s && a.xi == b.xi && a.bulk == b.bulk && a.h0 == b.h0 &&
+           a.h1 == b.h1 && a.h2 == b.h2 && a.h3 == b.h3;
 }
 
 Step make_step(const mpm_scene& d) {
@@ -776,7 +783,8 @@ int mpm_add_particles(mpm_ctx* c, int32_t scene, const mpm_material* mat, int64_
     if (c->N + count > (int64_t)1 << 30) return fail(c, MPM_EINVAL, "too many particles");
     SceneHost& sh = c->sh[scene];
     if (mat) {
-        if (mat->kind < 0 || mat->kind > 2) return fail(c, MPM_EINVAL, "bad material kind");
+        if (mat->kind < 0 || mat->kind > 3) return fail(c, MPM_EINVAL, "bad material kind");
+        if (mat->kind == MPM_SAND && !(mat->E > 0)) return fail(c, MPM_EINVAL, "sand needs E > 0");
         if (!(mat->ppc > 0) || !(mat->rho > 0)) return fail(c, MPM_EINVAL, "ppc and rho must be positive");
         if (mat->kind != MPM_WATER && !(mat->nu > -1.0f && mat->nu < 0.5f)) return fail(c, MPM_EINVAL, "bad nu");
         if (sh.has_mat && !same_material(sh.mat, *mat))

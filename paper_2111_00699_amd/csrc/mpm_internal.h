@@ -64,6 +64,8 @@ struct Mat {
     float scale;       // 4 dt V0 / dx^2 (stress term of the APIC affine matrix)
     float lo, hi;      // snow singular-value bounds 1 - theta_c, 1 + theta_s
     float xi, bulk;
+    float h0, h1, h2, h3;  // sand friction angle phi(q) = h0 + (h1 q - h3) exp(-h2 q), radians
+    float kdp;             // sand (3 lambda + 2 mu) / (2 mu)
 };
 
 // Per-substep constants.
@@ -328,6 +330,72 @@ __device__ __forceinline__ void left_svd(const float F[9], float U[9], float sig
     }
 }
 
+// Sand: Hencky elasticity in the logarithmic strain eps = log |sig| and the
+// Drucker-Prager return map of Klar et al. 2016 (a stand-in for the sand model
+// the paper cites).  When `pending`, the trial gradient Fh = U diag(sig) V^T
+// is mapped: expansion (tr eps > 0) releases all elastic strain; otherwise
+// dg = |dev eps| + kdp tr(eps) alpha(q) > 0 scales the deviator down by dg.
+// The new gradient U diag(exp eps') V^T is Fh + U diag(exp(eps')/sig - 1) U^T Fh,
+// and s = 1 + q grows by the log strain removed.  sig and J come back as those
+// of the stored gradient; e its log strain.
+__device__ __forceinline__ void sand_return_map(const Mat& M, int pending, const float U[9], const float Fh[9],
+                                                float F[9], float sig[3], float& s, float e[3]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) e[k] = __logf(fmaxf(fabsf(sig[k]), 1e-6f));
+    if (!pending) return;
+    const float t = e[0] + e[1] + e[2];
+    float d[3];
+    float nd = 0.0f, ne = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        d[k] = e[k] - t * (1.0f / 3.0f);
+        nd += d[k] * d[k];
+        ne += e[k] * e[k];
+    }
+    nd = sqrtf(nd);
+    float en[3] = {e[0], e[1], e[2]};
+    float dq = 0.0f;
+    if (t > 0.0f) {
+        en[0] = en[1] = en[2] = 0.0f;
+        dq = sqrtf(ne);
+    } else {
+        const float q = s - 1.0f;
+        const float phi = M.h0 + (M.h1 * q - M.h3) * __expf(-M.h2 * q);
+        const float sp = __sinf(phi);
+        const float alpha = 0.81649658f * 2.0f * sp / (3.0f - sp);  // sqrt(2/3) 2 sin / (3 - sin)
+        const float dg = nd + M.kdp * t * alpha;
+        if (dg > 0.0f) {
+            const float r = dg / nd;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) en[k] = e[k] - r * d[k];
+            dq = dg;
+        }
+    }
+    if (dq > 0.0f) {
+        float r[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float sn = __expf(en[k]);
+            r[k] = sn / copysignf(fmaxf(fabsf(sig[k]), 1e-6f), sig[k]) - 1.0f;
+            sig[k] = sn;
+            e[k] = en[k];
+        }
+        float R[6];
+        sym_from_eig(U, r[0], r[1], r[2], R);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const float f0 = Fh[0 * 3 + b], f1 = Fh[1 * 3 + b], f2 = Fh[2 * 3 + b];
+            F[0 * 3 + b] = f0 + (R[0] * f0 + R[1] * f1 + R[2] * f2);
+            F[1 * 3 + b] = f1 + (R[1] * f0 + R[3] * f1 + R[4] * f2);
+            F[2 * 3 + b] = f2 + (R[2] * f0 + R[4] * f1 + R[5] * f2);
+        }
+        s += dq;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) F[i] = Fh[i];
+    }
+}
+
 // Apply the deferred deformation update of the last G2P (when `pending`),
 // the snow return map, and produce the Kirchhoff stress tau (6 entries).
 // F (9) and s are updated in place.
@@ -354,6 +422,13 @@ __device__ __forceinline__ void material_step(const Mat& M, float dt, int pendin
     float U[9], sig[3], J;
     left_svd(Fh, U, sig, J);
     float mu = M.mu, la = M.la;
+    if (M.kind == MPM_SAND) {
+        float e[3];
+        sand_return_map(M, pending, U, Fh, F, sig, s, e);
+        const float tr = la * (e[0] + e[1] + e[2]);
+        sym_from_eig(U, 2.0f * mu * e[0] + tr, 2.0f * mu * e[1] + tr, 2.0f * mu * e[2] + tr, tau);
+        return;
+    }
     if (M.kind == MPM_SNOW) {
         if (pending) {
             float sc[3], r[3];

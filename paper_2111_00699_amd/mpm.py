@@ -14,7 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmpm.so")
 
-KIND = {"jelly": 0, "snow": 1, "water": 2}
+KIND = {"jelly": 0, "snow": 1, "water": 2, "sand": 3}
 BC = {"sticky": 0, "slip": 1, "separate": 2}
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -1, -2, -3, -4
@@ -50,7 +50,8 @@ class SceneStats(ct.Structure):
 
 class Material(ct.Structure):
     _fields_ = [("kind", ct.c_int32)] + [(k, ct.c_float) for k in
-                                         ("E", "nu", "rho", "ppc", "theta_c", "theta_s", "xi", "bulk")]
+                                         ("E", "nu", "rho", "ppc", "theta_c", "theta_s", "xi", "bulk",
+                                          "h0", "h1", "h2", "h3")]
 
 
 class Stats(ct.Structure):
@@ -125,7 +126,8 @@ def load() -> ct.CDLL:
 def material(m: dict) -> Material:
     kind = m["kind"] if isinstance(m["kind"], int) else KIND[m["kind"]]
     return Material(kind, *(float(m.get(k, 0.0)) for k in
-                            ("E", "nu", "rho", "ppc", "theta_c", "theta_s", "xi", "bulk")))
+                            ("E", "nu", "rho", "ppc", "theta_c", "theta_s", "xi", "bulk",
+                             "h0", "h1", "h2", "h3")))
 
 
 def _ptr(t):

@@ -192,6 +192,12 @@ def jelly_config(n: int = 64) -> dict:
     return dict(n=n, bc="sticky", bc_cells=3, gravity=(0.0, -9.8, 0.0), dt=1e-4, substeps_per_frame=167)
 
 
+def sand_config(n: int = 128) -> dict:
+    """Sand Blocks: a frictionless (slip) box, 36 substeps per 1/48 s frame."""
+    return dict(n=n, bc="slip", bc_cells=3, gravity=(0.0, -9.8, 0.0), dt=(1.0 / 48.0) / 36, substeps_per_frame=36,
+                frame=1.0 / 48.0)
+
+
 def fountain_config(n: int = 128) -> dict:
     ns, dt = frame_substeps(1e-4)
     return dict(n=n, bc="separate", bc_cells=3, gravity=(0.0, -9.8, 0.0), dt=dt, substeps_per_frame=ns)

@@ -201,10 +201,11 @@ def test_binning_after_motion_composes(torch_cuda, oracle):
 
 
 # --------------------------------------------------------- one substep parity
-MATS = {"jelly": (scenes.JELLY, "sticky"), "snow": (scenes.SNOW, "separate"), "water": (scenes.WATER, "slip")}
+MATS = {"jelly": (scenes.JELLY, "sticky"), "snow": (scenes.SNOW, "separate"), "water": (scenes.WATER, "slip"),
+        "sand": (scenes.SAND, "slip")}
 
 
-@pytest.mark.parametrize("kind", ["jelly", "snow", "water"])
+@pytest.mark.parametrize("kind", ["jelly", "snow", "water", "sand"])
 @pytest.mark.parametrize("mode", ["tile", "global", "every_step", "sorted_lanes", "g2p_global", "chunk128", "chunk512"])
 def test_single_substep_matches_oracle(torch_cuda, oracle, kind, mode):
     mat, bc = MATS[kind]
@@ -242,6 +243,51 @@ def test_ragged_multi_block_substep(torch_cuda, oracle):
     os_, om, ov, _ = oracle.substep(cfg, scenes.SNOW, st)
     compare_state(gs, os_, "snow")
     sim.close()
+
+
+def test_sand_return_map_cases_on_gpu(torch_cuda, oracle):
+    """Sand gradients spread over expansion (all strain released), the cone
+    (plastic flow) and the elastic interior: one substep, and the three cases
+    each cover a good share of the particles (classified on the oracle)."""
+    sc = scenes.jelly_cube(0)
+    st = scenes.nontrivial_state(sc["x"], seed=17, kind="sand")
+    st["F"] = (np.eye(3).reshape(9, 1) + 2.0 * (st["F"].astype(np.float64) - np.eye(3).reshape(9, 1))).astype(np.float32)
+    cfg = dict(n=64, dt=2e-4, bc="slip")
+    print_case("sand_cases", N=st["x"].shape[1])
+    sim = make_sim(torch_cuda, cfg)
+    sim.add_particles(scenes.SAND, st["x"], v=st["v"], C=st["C"], F=st["F"], s=st["s"])
+    sim.substep(1)
+    gs = gpu_state(sim)
+    sim.close()
+    os_, _, _, bad = oracle.substep(cfg, scenes.SAND, st)
+    assert bad == 0
+    compare_state(gs, os_, "sand", n=64)
+    N = st["x"].shape[1]
+    Fh = np.einsum("nab,nbc->nac", np.eye(3) + cfg["dt"] * os_["C"].T.reshape(N, 3, 3),
+                   st["F"].astype(np.float64).T.reshape(N, 3, 3))
+    tr = np.log(np.abs(np.linalg.det(Fh)))
+    dq = os_["s"] - st["s"].astype(np.float64)
+    tip, cone, inside = tr > 0, (tr <= 0) & (dq > 0), (tr <= 0) & (dq == 0)
+    assert min(tip.sum(), cone.sum(), inside.sum()) > N // 10, (tip.sum(), cone.sum(), inside.sum())
+
+
+def test_sand_blocks_substeps(torch_cuda, oracle):
+    """The Sand Blocks layout (4 boxes of 12^3 cells, 55,296 particles) at the
+    paper's time step, from a non-trivial state, 6 substeps on the slip box."""
+    x = scenes.sand_blocks(l=12, boxes=4, n=128)["x"]
+    st = scenes.nontrivial_state(x, seed=23, kind="sand")
+    cfg = scenes.sand_config()
+    cfg = dict(n=cfg["n"], dt=cfg["dt"], bc=cfg["bc"], bc_cells=cfg["bc_cells"], gravity=cfg["gravity"])
+    print_case("sand_blocks6", N=x.shape[1])
+    sim = make_sim(torch_cuda, cfg)
+    sim.add_particles(scenes.SAND, st["x"], v=st["v"], C=st["C"], F=st["F"], s=st["s"])
+    sim.substep(6)
+    gs = gpu_state(sim)
+    assert sim.stats()["error"] == 0
+    sim.close()
+    os_, _, _, bad = oracle.substep(cfg, scenes.SAND, st, steps=6)
+    assert bad == 0
+    compare_state(gs, os_, "sand", n=128)
 
 
 # --------------------------------------------------------- multi-step runs
