@@ -84,18 +84,20 @@ def test_full_snow_scene_substep_matches_oracle(torch_cuda, oracle):
     assert normwise(gv, ov) <= TOL
 
 
-def test_full_sand_blocks_substep_matches_oracle(torch_cuda, oracle):
-    """The largest single-grid Sand Blocks case the bench runs: 4 boxes of
-    46^3 cells (3,114,752 particles) at n = 128, one substep from a random
-    state, every particle and the whole node grid against the oracle."""
+@pytest.mark.parametrize("boxes,n", [(4, 128), (16, 256)])
+def test_full_sand_blocks_substep_matches_oracle(torch_cuda, oracle, boxes, n):
+    """The Sand Blocks cases of 46^3-cell boxes the bench runs: 4 boxes
+    (3,114,752 particles, n = 128) and 16 boxes (12,459,008 particles,
+    n = 256). One substep from a random state, every particle and the whole
+    node grid against the oracle."""
     from paper_2111_00699_amd import mpm
 
-    x = scenes.sand_blocks(l=46, boxes=4, n=128)["x"]
+    x = scenes.sand_blocks(l=46, boxes=boxes, n=n)["x"]
     st = scenes.nontrivial_state(x, seed=29, kind="sand")
     N = x.shape[1]
-    c = scenes.sand_config()
+    c = scenes.sand_config(n)
     cfg = dict(n=c["n"], dt=c["dt"], bc=c["bc"], bc_cells=c["bc_cells"], gravity=c["gravity"])
-    print_case("full_sand_blocks", N=N)
+    print_case("full_sand_blocks", boxes=boxes, n=n, N=N)
     sim = mpm.Sim(cfg["n"], cfg["dt"], bc=cfg["bc"], bc_cells=cfg["bc_cells"], gravity=cfg["gravity"],
                   capacity=2 * N + 256)
     sim.add_particles(scenes.SAND, st["x"], v=st["v"], C=st["C"], F=st["F"], s=st["s"])
@@ -103,6 +105,7 @@ def test_full_sand_blocks_substep_matches_oracle(torch_cuda, oracle):
     gs = gpu_state(sim)
     gm, gv = (t.cpu().numpy() for t in sim.read_grid())
     sim.close()
+    del x
     os_, om, ov, bad = oracle.substep(cfg, scenes.SAND, st)
     assert bad == 0
     compare_state(gs, os_, "sand", n=cfg["n"])
