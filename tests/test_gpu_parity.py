@@ -525,7 +525,8 @@ def test_profile_counts_launches(torch_cuda):
     sim.close()
 
 
-def test_fused_g2p_matches_separate_g2p_bit_for_bit(torch_cuda):
+@pytest.mark.parametrize("kind", ["snow", "sand"])
+def test_fused_g2p_matches_separate_g2p_bit_for_bit(torch_cuda, kind):
     """The G2P fused into the next P2G computes the same values in the same
     order as the G2P launch: 40 substeps with reads in the middle, particles
     added between substeps and rebuilds at fixed substeps give identical
@@ -535,13 +536,15 @@ def test_fused_g2p_matches_separate_g2p_bit_for_bit(torch_cuda):
     from paper_2111_00699_amd import mpm
 
     sc = scenes.jelly_cube(0)
-    st = scenes.nontrivial_state(sc["x"], seed=29, kind="snow")
+    st = scenes.nontrivial_state(sc["x"], seed=29, kind=kind)
     extra = scenes.uniform(31, 3 * 500, 0, 0.1, 0.2).reshape(3, -1).astype(np.float32)
     cfg = dict(n=64, dt=1e-4, bc="separate")
+    mat = MATS[kind][0]
+    print_case("fused_vs_separate", kind=kind, N=st["x"].shape[1])
     out = {}
     for flags in (mpm.FLAG_FUSED_G2P, mpm.FLAG_SEPARATE_G2P):
         sim = make_sim(torch_cuda, cfg, flags=flags | mpm.FLAG_MANUAL_REBUILD)
-        sim.add_particles(scenes.SNOW, st["x"], v=st["v"], C=st["C"], F=st["F"], s=st["s"])
+        sim.add_particles(mat, st["x"], v=st["v"], C=st["C"], F=st["F"], s=st["s"])
         sim.substep(10)
         sim.rebuild()
         sim.substep(10)
