@@ -59,6 +59,9 @@ P2G_BYTES = {"jelly": 132, "snow": 140, "water": 68}
 # registers.
 P2G_FUSED_BYTES = {"snow": 108}
 G2P_BYTES = 72
+# Algorithmic bytes per particle-substep of the whole substep (P2G + G2P of
+# the two-kernel form): what one fused launch is priced at.
+SUBSTEP_BYTES = {m: P2G_BYTES[m] + G2P_BYTES for m in P2G_BYTES}
 
 # HBM bytes per P2G launch measured with rocprofv3 counters (FETCH_SIZE x 2.0
 # + WRITE_SIZE x 1.0, the factors a plain 1 GiB copy reads back, averaged over
@@ -89,18 +92,48 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(sc, cfg, steps=14):
+def oracle_threads():
+    """Host threads the oracle may use: OMP_NUM_THREADS when set, else the
+    CPUs this process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return int(env) if env.isdigit() and int(env) > 0 else len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(sc, cfg, serial_steps=3, threaded_steps=5):
+    """The FP64 oracle on the host cores, on bounded samples of the snow
+    scene: the serial oracle on one thread and its multi-threaded form on
+    every host thread this process may use, each from the frame-0 state (at
+    rest) and the frame-10 state.  No sphere comes near the floor before
+    frame 13, so the frame-10 state is the free-fall closed form of the
+    initial one (scenes.free_fall_state).  `value` is the multi-threaded rate."""
     import oracle
     from paper_2111_00699_amd import scenes
 
     oracle.build()
     N = sc["x"].shape[1]
-    t0 = time.perf_counter()
-    _, _, _, bad = oracle.substep(cfg, scenes.SNOW, sc, steps=steps)
-    dt = time.perf_counter() - t0
-    return {"value": N * steps / dt, "unit": "particle-substeps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} substeps of the full snow scene ({N} particles) from its initial state, "
-                      f"FP64 dense-grid oracle, single thread, {dt:.1f} s"}
+    states = {"frame 0": {"x": sc["x"]},
+              "frame 10": scenes.free_fall_state(sc["x"], cfg, 10 * cfg["substeps_per_frame"])}
+    threads = oracle_threads()
+    out = {}
+    for label, nthr, steps in (("single_thread", 1, serial_steps), ("all_threads", threads, threaded_steps)):
+        per = {}
+        total = 0.0
+        for name, st in states.items():
+            t0 = time.perf_counter()
+            _, _, _, bad = oracle.substep(cfg, scenes.SNOW, st, steps=steps, threads=nthr)
+            dt = time.perf_counter() - t0
+            assert bad == 0
+            per[name] = N * steps / dt
+            total += dt
+        out[label] = {"value": 2 * N * steps / total, "threads": nthr, "seconds": total,
+                      "per_state": per, "substeps_per_state": steps}
+        log(f"[bench] oracle {label}: {out[label]['value']:.3e} particle-substeps/s ({total:.1f} s)")
+    a = out["all_threads"]
+    return {"value": a["value"], "unit": "particle-substeps/s", "cores": threads, "kind": "oracle",
+            "sample": f"full snow scene ({N} particles, 256^3 dense FP64 grid): {threaded_steps} substeps from the "
+                      f"frame-0 and the frame-10 state each on {threads} host threads (OpenMP form of the oracle, "
+                      f"{a['seconds']:.1f} s), and {serial_steps} substeps from each on one thread (serial oracle)",
+            "single_thread": out["single_thread"], "all_threads": a}
 
 
 def bench_batched(args):
@@ -635,8 +668,12 @@ def main():
     p2g = prof["p2g"]
     p2g_avg_ms = p2g["ms"] / max(p2g["launches"], 1)
     fused = prof["g2p"]["launches"] * 2 < p2g["launches"]  # G2P ran inside P2G (sampled alike)
-    p2g_bytes = P2G_FUSED_BYTES["snow"] if fused else P2G_BYTES["snow"]
+    # algorithmic bytes of one launch: the per particle-substep state traffic
+    # of the substep's two-kernel form (P2G + G2P, 212 B for snow), since the
+    # fused launch does one full substep's particle work for every particle
+    p2g_bytes = SUBSTEP_BYTES["snow"] if fused else P2G_BYTES["snow"]
     achieved = p2g_bytes * N / (p2g_avg_ms * 1e-3) / 1e9
+    kernel_bytes = P2G_FUSED_BYTES["snow"] if fused else P2G_BYTES["snow"]
     rebuilds = st1["rebuilds"] - st0["rebuilds"]
     traffic = p2g_traffic_bytes("p2g_fused" if fused else "p2g")
     out = {
@@ -664,9 +701,15 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "traffic_unit": "HBM bytes per launch",
                      "traffic_frac": (traffic / (p2g_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None,
+                     "traffic_source": ("rocprofv3 --pmc FETCH_SIZE, WRITE_SIZE of the same kernel sources "
+                                        "(profiles/substep_snow256_counters.md)") if traffic else
+                                       "null: the kernel changed since its counters were taken",
                      "avg_launch_us": p2g_avg_ms * 1e3, "launches_timed": p2g["launches"],
                      "sampled_every": PROFILE_EVERY,
-                     "bytes_per_particle": p2g_bytes},
+                     "bytes_per_particle": p2g_bytes,
+                     "bytes_basis": "per particle-substep state traffic of P2G + G2P (snow: 212 B)",
+                     "kernel_bytes_per_particle": kernel_bytes,
+                     "kernel_bytes_frac": kernel_bytes * N / (p2g_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         # the bound P2G actually meets: its LDS atomics against their measured peak rate
         "roofline_lds": {"kernel": "p2g_fused" if fused else "p2g", "bound": "lds_u64_atomics",
                          "achieved": P2G_LDS_ATOMICS_PER_PARTICLE * N / (p2g_avg_ms * 1e-3),

@@ -31,7 +31,7 @@ def build(force: bool = False) -> str:
     """Compile the oracle with gcc (no fast-math) into oracle/libmpm_oracle.so."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-fno-fast-math", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-fno-fast-math", "-fopenmp", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -73,6 +73,7 @@ def lib():
             "om_grid_update": (None, [ct.POINTER(_Cfg), D, D]),
             "om_g2p": (L, [ct.POINTER(_Cfg), ct.POINTER(_Mat), L, D, D, D, D, D, D]),
             "om_substep": (L, [ct.POINTER(_Cfg), ct.POINTER(_Mat), L, D, D, D, D, D, D, D]),
+            "om_substep_omp": (L, [ct.POINTER(_Cfg), ct.POINTER(_Mat), L, D, D, D, D, D, D, D, ct.c_int]),
             "om_keys": (L, [L, F32, ct.c_int, U32, I32]),
             "om_stable_sort": (None, [L, U32, I32, U32]),
             "om_gblocks": (L, [L, U32, U32, I32, I32]),
@@ -220,9 +221,11 @@ def g2p(cfg: dict, mat: dict, st: dict, gv: np.ndarray):
     return s, bad
 
 
-def substep(cfg: dict, mat: dict, st: dict, steps: int = 1):
+def substep(cfg: dict, mat: dict, st: dict, steps: int = 1, threads: int = 1):
     """Advance `steps` substeps.  Returns (state, grid mass, grid velocity of
-    the last substep, total skipped-particle count)."""
+    the last substep, total skipped-particle count).  threads > 1 (or 0 for
+    every core) runs the multi-threaded form, whose sums are ordered
+    differently (equal up to FP64 rounding)."""
     s = _state(st)
     n = int(cfg["n"])
     NN = num_nodes(n)
@@ -231,8 +234,12 @@ def substep(cfg: dict, mat: dict, st: dict, steps: int = 1):
     N = s["x"].shape[1]
     bad = 0
     for _ in range(steps):
-        bad += lib().om_substep(ct.byref(c), ct.byref(m), N, *(_p(s[k], ct.c_double) for k in "xvCFs"),
-                                _p(gm, ct.c_double), _p(gv, ct.c_double))
+        args = (ct.byref(c), ct.byref(m), N, *(_p(s[k], ct.c_double) for k in "xvCFs"),
+                _p(gm, ct.c_double), _p(gv, ct.c_double))
+        if threads == 1:
+            bad += lib().om_substep(*args)
+        else:
+            bad += lib().om_substep_omp(*args, int(threads))
     return s, gm, gv, bad
 
 

@@ -28,6 +28,7 @@
  *   [3][(n+1)^3].
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -308,46 +309,70 @@ static long node_index(int n, int i, int j, int k) { return ((long)i * (n + 1) +
 
 /* ------------------------------------------------------------------- P2G
  * m_i = sum_p w_ip m_p,  p_i = sum_p w_ip (m_p v_p + A_p (x_i - x_p)),
- * A_p = m_p C_p - (4 dt V0 / dx^2) tau_p.  Returns the number of particles
- * whose stencil leaves the node range [0, n] (they are skipped).            */
-long om_p2g(const om_config* cfg, const om_material* mat, long N, const double* x, const double* v,
-            const double* C, const double* F, const double* s, double* gm, double* gp) {
+ * A_p = m_p C_p - (4 dt V0 / dx^2) tau_p.  Particles whose stencil leaves the
+ * node range [0, n] are skipped and counted.                                 */
+
+/* Stencil of particle p (base node, weights, f = x/dx - base per axis) and
+ * its affine momentum matrix A_p.  Returns 1 if the stencil leaves the grid. */
+static int p2g_prepare(const om_config* cfg, const om_material* mat, long N, long p, const double* x,
+                       const double* C, const double* F, const double* s, int base[3], double w[3][3],
+                       double f[3], double A[9]) {
     const int n = cfg->n;
     const double dx = 1.0 / n;
     const double V0 = dx * dx * dx / mat->ppc;
     const double mp = mat->rho * V0;
+    double Fp[9], Cp[9], tau[9];
+    for (int c = 0; c < 9; ++c) { Fp[c] = F ? F[c * N + p] : (c % 4 == 0); Cp[c] = C[c * N + p]; }
+    om_stress(mat, Fp, s ? s[p] : 1.0, tau);
+    for (int c = 0; c < 9; ++c) A[c] = mp * Cp[c] - (4.0 * cfg->dt * V0 / (dx * dx)) * tau[c];
+    int out = 0;
+    for (int a = 0; a < 3; ++a) {
+        double t = x[a * N + p] / dx;
+        om_weights(t, &base[a], w[a]);
+        f[a] = t - base[a];
+        if (base[a] < 0 || base[a] + 2 > n) out = 1;
+    }
+    return out;
+}
+
+/* Add one particle's mass and momentum to its 27 nodes.                    */
+static void p2g_scatter(int n, double mp, const double vp[3], const int base[3], double w[3][3],
+                        const double f[3], const double A[9], double* gm, double* gp) {
+    const double dx = 1.0 / n;
+    const long NN = (long)(n + 1) * (n + 1) * (n + 1);
+    for (int o0 = 0; o0 < 3; ++o0)
+        for (int o1 = 0; o1 < 3; ++o1)
+            for (int o2 = 0; o2 < 3; ++o2) {
+                double wt = w[0][o0] * w[1][o1] * w[2][o2];
+                double d[3] = {(o0 - f[0]) * dx, (o1 - f[1]) * dx, (o2 - f[2]) * dx};
+                long id = node_index(n, base[0] + o0, base[1] + o1, base[2] + o2);
+                gm[id] += wt * mp;
+                for (int a = 0; a < 3; ++a) {
+                    double Ad = A[a * 3 + 0] * d[0] + A[a * 3 + 1] * d[1] + A[a * 3 + 2] * d[2];
+                    gp[a * NN + id] += wt * (mp * vp[a] + Ad);
+                }
+            }
+}
+
+static double particle_mass(const om_config* cfg, const om_material* mat) {
+    const double dx = 1.0 / cfg->n;
+    return mat->rho * dx * dx * dx / mat->ppc;
+}
+
+long om_p2g(const om_config* cfg, const om_material* mat, long N, const double* x, const double* v,
+            const double* C, const double* F, const double* s, double* gm, double* gp) {
+    const int n = cfg->n;
+    const double mp = particle_mass(cfg, mat);
     const long NN = (long)(n + 1) * (n + 1) * (n + 1);
     memset(gm, 0, sizeof(double) * NN);
     memset(gp, 0, sizeof(double) * 3 * NN);
     long bad = 0;
     for (long p = 0; p < N; ++p) {
-        double Fp[9], Cp[9], tau[9], A[9];
-        for (int c = 0; c < 9; ++c) { Fp[c] = F ? F[c * N + p] : (c % 4 == 0); Cp[c] = C[c * N + p]; }
-        om_stress(mat, Fp, s ? s[p] : 1.0, tau);
-        for (int c = 0; c < 9; ++c) A[c] = mp * Cp[c] - (4.0 * cfg->dt * V0 / (dx * dx)) * tau[c];
         int base[3];
-        double w[3][3], f[3];
-        int out = 0;
-        for (int a = 0; a < 3; ++a) {
-            double t = x[a * N + p] / dx;
-            om_weights(t, &base[a], w[a]);
-            f[a] = t - base[a];
-            if (base[a] < 0 || base[a] + 2 > n) out = 1;
-        }
-        if (out) { ++bad; continue; }
+        double w[3][3], f[3], A[9];
+        if (p2g_prepare(cfg, mat, N, p, x, C, F, s, base, w, f, A)) { ++bad; continue; }
         double vp[3] = {v[p], v[N + p], v[2 * N + p]};
-        for (int o0 = 0; o0 < 3; ++o0)
-            for (int o1 = 0; o1 < 3; ++o1)
-                for (int o2 = 0; o2 < 3; ++o2) {
-                    double wt = w[0][o0] * w[1][o1] * w[2][o2];
-                    double d[3] = {(o0 - f[0]) * dx, (o1 - f[1]) * dx, (o2 - f[2]) * dx};
-                    long id = node_index(n, base[0] + o0, base[1] + o1, base[2] + o2);
-                    gm[id] += wt * mp;
-                    for (int a = 0; a < 3; ++a) {
-                        double Ad = A[a * 3 + 0] * d[0] + A[a * 3 + 1] * d[1] + A[a * 3 + 2] * d[2];
-                        gp[a * NN + id] += wt * (mp * vp[a] + Ad);
-                    }
-                }
+        p2g_scatter(n, mp, vp, base, w, f, A, gm, gp);
     }
     return bad;
 }
@@ -356,100 +381,109 @@ long om_p2g(const om_config* cfg, const om_material* mat, long N, const double* 
  * v_i = p_i / m_i + dt g where m_i > 0, else 0; then the wall condition on
  * every node with a coordinate below bc_cells or above n - bc_cells.
  * Overwrites gp with the nodal velocity.                                    */
-void om_grid_update(const om_config* cfg, const double* gm, double* gv) {
+static void grid_node(const om_config* cfg, const double* gm, double* gv, int i, int j, int k) {
     const int n = cfg->n, b = cfg->bc_cells;
     const long NN = (long)(n + 1) * (n + 1) * (n + 1);
+    long id = node_index(n, i, j, k);
+    double vel[3] = {0, 0, 0};
+    if (gm[id] > 0.0)
+        for (int a = 0; a < 3; ++a) vel[a] = gv[a * NN + id] / gm[id] + cfg->dt * cfg->gravity[a];
+    int idx[3] = {i, j, k};
+    int lowside[3], highside[3], any = 0;
+    for (int a = 0; a < 3; ++a) {
+        lowside[a] = idx[a] < b;
+        highside[a] = idx[a] > n - b;
+        any |= lowside[a] | highside[a];
+    }
+    if (any) {
+        if (cfg->bc == 0) {
+            vel[0] = vel[1] = vel[2] = 0.0;
+        } else {
+            for (int a = 0; a < 3; ++a) {
+                if (cfg->bc == 1) {
+                    if (lowside[a] || highside[a]) vel[a] = 0.0;
+                } else {
+                    if (lowside[a] && vel[a] < 0.0) vel[a] = 0.0;
+                    if (highside[a] && vel[a] > 0.0) vel[a] = 0.0;
+                }
+            }
+        }
+    }
+    for (int a = 0; a < 3; ++a) gv[a * NN + id] = vel[a];
+}
+
+void om_grid_update(const om_config* cfg, const double* gm, double* gv) {
+    const int n = cfg->n;
     for (int i = 0; i <= n; ++i)
         for (int j = 0; j <= n; ++j)
-            for (int k = 0; k <= n; ++k) {
-                long id = node_index(n, i, j, k);
-                double vel[3] = {0, 0, 0};
-                if (gm[id] > 0.0)
-                    for (int a = 0; a < 3; ++a) vel[a] = gv[a * NN + id] / gm[id] + cfg->dt * cfg->gravity[a];
-                int idx[3] = {i, j, k};
-                int lowside[3], highside[3], any = 0;
-                for (int a = 0; a < 3; ++a) {
-                    lowside[a] = idx[a] < b;
-                    highside[a] = idx[a] > n - b;
-                    any |= lowside[a] | highside[a];
-                }
-                if (any) {
-                    if (cfg->bc == 0) {
-                        vel[0] = vel[1] = vel[2] = 0.0;
-                    } else {
-                        for (int a = 0; a < 3; ++a) {
-                            if (cfg->bc == 1) {
-                                if (lowside[a] || highside[a]) vel[a] = 0.0;
-                            } else {
-                                if (lowside[a] && vel[a] < 0.0) vel[a] = 0.0;
-                                if (highside[a] && vel[a] > 0.0) vel[a] = 0.0;
-                            }
-                        }
-                    }
-                }
-                for (int a = 0; a < 3; ++a) gv[a * NN + id] = vel[a];
-            }
+            for (int k = 0; k <= n; ++k) grid_node(cfg, gm, gv, i, j, k);
 }
 
 /* -------------------------------------------------------------------- G2P
  * v' = sum w v_i, C' = 4/dx^2 sum w v_i (x_i - x_p)^T, x' = x + dt v',
- * then the material update with the new C'.  In-place on x, v, C, F, s.    */
-long om_g2p(const om_config* cfg, const om_material* mat, long N, double* x, double* v, double* C, double* F,
-            double* s, const double* gv) {
+ * then the material update with the new C'.  In-place on x, v, C, F, s.
+ * One particle; returns 1 (and leaves it unchanged) if its stencil leaves
+ * the grid.                                                                 */
+static int g2p_particle(const om_config* cfg, const om_material* mat, long N, long p, double* x, double* v,
+                        double* C, double* F, double* s, const double* gv) {
     const int n = cfg->n;
     const double dx = 1.0 / n, dt = cfg->dt;
     const long NN = (long)(n + 1) * (n + 1) * (n + 1);
-    long bad = 0;
-    for (long p = 0; p < N; ++p) {
-        int base[3], out = 0;
-        double w[3][3], f[3];
-        for (int a = 0; a < 3; ++a) {
-            double t = x[a * N + p] / dx;
-            om_weights(t, &base[a], w[a]);
-            f[a] = t - base[a];
-            if (base[a] < 0 || base[a] + 2 > n) out = 1;
-        }
-        if (out) { ++bad; continue; }
-        double vn[3] = {0, 0, 0}, Cn[9] = {0};
-        for (int o0 = 0; o0 < 3; ++o0)
-            for (int o1 = 0; o1 < 3; ++o1)
-                for (int o2 = 0; o2 < 3; ++o2) {
-                    double wt = w[0][o0] * w[1][o1] * w[2][o2];
-                    double d[3] = {(o0 - f[0]) * dx, (o1 - f[1]) * dx, (o2 - f[2]) * dx};
-                    long id = node_index(n, base[0] + o0, base[1] + o1, base[2] + o2);
-                    for (int a = 0; a < 3; ++a) {
-                        double vi = gv[a * NN + id];
-                        vn[a] += wt * vi;
-                        for (int b = 0; b < 3; ++b) Cn[a * 3 + b] += 4.0 / (dx * dx) * wt * vi * d[b];
-                    }
-                }
-        for (int a = 0; a < 3; ++a) {
-            v[a * N + p] = vn[a];
-            x[a * N + p] += dt * vn[a];
-        }
-        for (int c = 0; c < 9; ++c) C[c * N + p] = Cn[c];
-        double G[9]; /* I + dt C' */
-        for (int c = 0; c < 9; ++c) G[c] = dt * Cn[c] + (c % 4 == 0 ? 1.0 : 0.0);
-        if (mat->kind == OM_WATER) {
-            s[p] *= mat_det(G);
-        } else {
-            double Fp[9], Fn[9];
-            for (int c = 0; c < 9; ++c) Fp[c] = F[c * N + p];
-            mat_mul(G, Fp, Fn);
-            if (mat->kind == OM_SNOW) {
-                double Fe[9], Jp;
-                om_snow_project(mat, Fn, s[p], Fe, &Jp);
-                memcpy(Fn, Fe, sizeof Fe);
-                s[p] = Jp;
-            } else if (mat->kind == OM_SAND) { /* s holds 1 + q */
-                double Fe[9], q;
-                om_sand_project(mat, Fn, s[p] - 1.0, Fe, &q);
-                memcpy(Fn, Fe, sizeof Fe);
-                s[p] = 1.0 + q;
-            }
-            for (int c = 0; c < 9; ++c) F[c * N + p] = Fn[c];
-        }
+    int base[3], out = 0;
+    double w[3][3], f[3];
+    for (int a = 0; a < 3; ++a) {
+        double t = x[a * N + p] / dx;
+        om_weights(t, &base[a], w[a]);
+        f[a] = t - base[a];
+        if (base[a] < 0 || base[a] + 2 > n) out = 1;
     }
+    if (out) return 1;
+    double vn[3] = {0, 0, 0}, Cn[9] = {0};
+    for (int o0 = 0; o0 < 3; ++o0)
+        for (int o1 = 0; o1 < 3; ++o1)
+            for (int o2 = 0; o2 < 3; ++o2) {
+                double wt = w[0][o0] * w[1][o1] * w[2][o2];
+                double d[3] = {(o0 - f[0]) * dx, (o1 - f[1]) * dx, (o2 - f[2]) * dx};
+                long id = node_index(n, base[0] + o0, base[1] + o1, base[2] + o2);
+                for (int a = 0; a < 3; ++a) {
+                    double vi = gv[a * NN + id];
+                    vn[a] += wt * vi;
+                    for (int b = 0; b < 3; ++b) Cn[a * 3 + b] += 4.0 / (dx * dx) * wt * vi * d[b];
+                }
+            }
+    for (int a = 0; a < 3; ++a) {
+        v[a * N + p] = vn[a];
+        x[a * N + p] += dt * vn[a];
+    }
+    for (int c = 0; c < 9; ++c) C[c * N + p] = Cn[c];
+    double G[9]; /* I + dt C' */
+    for (int c = 0; c < 9; ++c) G[c] = dt * Cn[c] + (c % 4 == 0 ? 1.0 : 0.0);
+    if (mat->kind == OM_WATER) {
+        s[p] *= mat_det(G);
+    } else {
+        double Fp[9], Fn[9];
+        for (int c = 0; c < 9; ++c) Fp[c] = F[c * N + p];
+        mat_mul(G, Fp, Fn);
+        if (mat->kind == OM_SNOW) {
+            double Fe[9], Jp;
+            om_snow_project(mat, Fn, s[p], Fe, &Jp);
+            memcpy(Fn, Fe, sizeof Fe);
+            s[p] = Jp;
+        } else if (mat->kind == OM_SAND) { /* s holds 1 + q */
+            double Fe[9], q;
+            om_sand_project(mat, Fn, s[p] - 1.0, Fe, &q);
+            memcpy(Fn, Fe, sizeof Fe);
+            s[p] = 1.0 + q;
+        }
+        for (int c = 0; c < 9; ++c) F[c * N + p] = Fn[c];
+    }
+    return 0;
+}
+
+long om_g2p(const om_config* cfg, const om_material* mat, long N, double* x, double* v, double* C, double* F,
+            double* s, const double* gv) {
+    long bad = 0;
+    for (long p = 0; p < N; ++p) bad += g2p_particle(cfg, mat, N, p, x, v, C, F, s, gv);
     return bad;
 }
 
@@ -460,6 +494,87 @@ long om_substep(const om_config* cfg, const om_material* mat, long N, double* x,
     long bad = om_p2g(cfg, mat, N, x, v, C, F, s, gm, gv);
     om_grid_update(cfg, gm, gv);
     bad += om_g2p(cfg, mat, N, x, v, C, F, s, gv);
+    return bad;
+}
+
+/* ------------------------------------------------ multi-threaded substep
+ * The same substep split over OpenMP threads, for timing on many host cores
+ * and for long runs in tests.  Particle work (stress, G2P and the material
+ * update) is split over particles and the grid update over node planes.
+ * P2G keeps one summation order whatever the thread count: the particles
+ * are binned, in input order, into slabs of OM_SLAB cells along x by their
+ * stencil base; the even slabs scatter first and the odd ones after (inside a
+ * slab the particles go in input order; slabs of one parity never share a
+ * node, since a slab's stencils span OM_SLAB + 2 nodes).  The result is the
+ * single-threaded substep's up to the order of the floating-point sums.
+ * threads <= 0 takes the OpenMP default.                                    */
+#define OM_SLAB 4
+long om_substep_omp(const om_config* cfg, const om_material* mat, long N, double* x, double* v, double* C,
+                    double* F, double* s, double* gm, double* gv, int threads) {
+    const int n = cfg->n;
+    const long NN = (long)(n + 1) * (n + 1) * (n + 1);
+    const double mp = particle_mass(cfg, mat);
+    const int nslab = n / OM_SLAB + 1;
+    if (threads <= 0) threads = omp_get_max_threads();
+    int* base = malloc(sizeof(int) * 3 * (N > 0 ? N : 1));
+    double* W = malloc(sizeof(double) * 9 * (N > 0 ? N : 1));
+    double* fr = malloc(sizeof(double) * 3 * (N > 0 ? N : 1));
+    double* A = malloc(sizeof(double) * 9 * (N > 0 ? N : 1));
+    long* start = calloc(nslab + 1, sizeof(long));
+    long* order = malloc(sizeof(long) * (N > 0 ? N : 1));
+    long bad = 0;
+
+#pragma omp parallel for num_threads(threads) schedule(static)
+    for (long i = 0; i < NN; ++i) gm[i] = 0.0;
+#pragma omp parallel for num_threads(threads) schedule(static)
+    for (long i = 0; i < 3 * NN; ++i) gv[i] = 0.0;
+
+#pragma omp parallel for num_threads(threads) schedule(dynamic, 1024) reduction(+ : bad)
+    for (long p = 0; p < N; ++p) {
+        int b[3];
+        double w[3][3];
+        int out = p2g_prepare(cfg, mat, N, p, x, C, F, s, b, w, &fr[3 * p], &A[9 * p]);
+        for (int a = 0; a < 3; ++a) {
+            base[3 * p + a] = out ? -1 : b[a];
+            for (int o = 0; o < 3; ++o) W[9 * p + 3 * a + o] = w[a][o];
+        }
+        bad += out;
+    }
+    /* stable counting sort of the in-range particles by slab */
+    for (long p = 0; p < N; ++p)
+        if (base[3 * p] >= 0) start[base[3 * p] / OM_SLAB + 1]++;
+    for (int k = 0; k < nslab; ++k) start[k + 1] += start[k];
+    {
+        long* fill = malloc(sizeof(long) * (nslab > 0 ? nslab : 1));
+        memcpy(fill, start, sizeof(long) * nslab);
+        for (long p = 0; p < N; ++p)
+            if (base[3 * p] >= 0) order[fill[base[3 * p] / OM_SLAB]++] = p;
+        free(fill);
+    }
+    for (int parity = 0; parity < 2; ++parity) {
+#pragma omp parallel for num_threads(threads) schedule(dynamic, 1)
+        for (int k = parity; k < nslab; k += 2)
+            for (long j = start[k]; j < start[k + 1]; ++j) {
+                long p = order[j];
+                double w[3][3], vp[3] = {v[p], v[N + p], v[2 * N + p]};
+                for (int a = 0; a < 3; ++a)
+                    for (int o = 0; o < 3; ++o) w[a][o] = W[9 * p + 3 * a + o];
+                p2g_scatter(n, mp, vp, &base[3 * p], w, &fr[3 * p], &A[9 * p], gm, gv);
+            }
+    }
+#pragma omp parallel for num_threads(threads) schedule(static)
+    for (int i = 0; i <= n; ++i)
+        for (int j = 0; j <= n; ++j)
+            for (int k = 0; k <= n; ++k) grid_node(cfg, gm, gv, i, j, k);
+#pragma omp parallel for num_threads(threads) schedule(dynamic, 1024) reduction(+ : bad)
+    for (long p = 0; p < N; ++p) bad += g2p_particle(cfg, mat, N, p, x, v, C, F, s, gv);
+
+    free(base);
+    free(W);
+    free(fr);
+    free(A);
+    free(start);
+    free(order);
     return bad;
 }
 

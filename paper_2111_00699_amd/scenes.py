@@ -149,6 +149,22 @@ def snow_spheres(seed: int = 1, n: int = 256, target: float = 1.33e6, count: int
     return {"x": x, "centers": centers, "radii": r}
 
 
+def free_fall_state(x: np.ndarray, cfg: dict, k: int) -> dict:
+    """State of particles released at rest at x after k substeps of free fall
+    (no stress, no wall contact): the symplectic-Euler closed form
+    v_k = k dt g, x_k = x_0 + dt^2 g k (k + 1) / 2.  Raises if a particle's
+    stencil would have reached a wall layer by then."""
+    dt = cfg["dt"]
+    g = np.asarray(cfg["gravity"], dtype=np.float64)[:, None]
+    xk = x.astype(np.float64) + dt * dt * g * (k * (k + 1) / 2.0)
+    dx = 1.0 / cfg["n"]
+    b = cfg.get("bc_cells", 3)
+    if xk.min() < (b + 2) * dx or xk.max() > 1.0 - (b + 2) * dx:
+        raise ValueError("free_fall_state: the particles reach a wall layer before substep %d" % k)
+    v = np.repeat(k * dt * g, x.shape[1], axis=1)
+    return {"x": xk.astype(np.float32), "v": v.astype(np.float32)}
+
+
 def fountain_emission(frame: int, seed: int = 2, n: int = 128, radius: float = 0.05,
                       center=(0.5, 0.1, 0.5), height: float = 0.05, speed: float = 3.0) -> dict:
     """One frame's emission: stratified 8-ppc samples in the inlet cylinder
@@ -164,6 +180,62 @@ def fountain_emission(frame: int, seed: int = 2, n: int = 128, radius: float = 0
     v = np.zeros_like(x)
     v[1] = speed
     return {"x": x, "v": v}
+
+
+def fountain_midrun(seed: int = 2, n: int = 128, limit: int = 143500) -> dict:
+    """The fountain partway through a run, built directly (not simulated): a
+    pool at rest on the floor (x, z in [0.25, 0.75), from the wall layer up
+    three cells) and the jet above the inlet (radius 0.05 around x = z = 0.5,
+    y in [0.15, top)) moving up at the ballistic speed sqrt(9 - 2 g (y - 0.1))
+    of water leaving the inlet at 3 m/s; 8 ppc stratified.  The inlet
+    cylinder itself (y in [0.1, 0.15)) is left free for the next frame's
+    emission.  `top` is the highest cell row that keeps the total within
+    `limit` particles."""
+    dx = 1.0 / n
+    b = 3
+    lo = int(round(0.25 * n))
+    hi = int(round(0.75 * n))
+    pool = stratified_cells(box_cells((lo, b, lo), (hi, b + 3, hi)), n, seed, stream=2000)
+    r = 0.05
+    lc = np.floor(np.array([0.5 - r, 0.15, 0.5 - r]) / dx).astype(int)
+    hc = np.ceil(np.array([0.5 + r, 0.5, 0.5 + r]) / dx).astype(int)
+    jet = stratified_cells(box_cells(lc, hc), n, seed, stream=2001)
+    jd = jet.astype(np.float64)
+    jet = jet[:, ((jd[0] - 0.5) ** 2 + (jd[2] - 0.5) ** 2 <= r * r) & (jd[1] >= 0.15)]
+    room = limit - pool.shape[1]
+    if jet.shape[1] > room:  # drop the highest rows (the cells are y-major in box_cells)
+        order = np.argsort(jet[1], kind="stable")
+        jet = jet[:, np.sort(order[:room])]
+    x = np.ascontiguousarray(np.concatenate([pool, jet], axis=1))
+    v = np.zeros_like(x)
+    vy = np.sqrt(np.maximum(9.0 - 2.0 * 9.8 * (jet[1].astype(np.float64) - 0.1), 0.0))
+    v[1, pool.shape[1]:] = vy.astype(np.float32)
+    return {"x": x, "v": v}
+
+
+def snow_collision(seed: int = 7, n: int = 128, r: float = 0.07, speed: float = 2.0) -> dict:
+    """Two pairs of snow spheres (radius r, 8 ppc stratified) thrown at each
+    other in mid-air at +-speed along x, 0.02 apart: they meet about 5 ms in
+    and are pressed together for the rest of a 1/60 s frame, well away from
+    every wall.  Pairs at z = 0.3 and 0.7, all centres at y = 0.6."""
+    dx = 1.0 / n
+    pieces, vel = [], []
+    k = 0
+    for zc in (0.3, 0.7):
+        for side in (-1.0, 1.0):
+            c = np.array([0.5 + side * (r + 0.01), 0.6, zc])
+            lc = np.floor((c - r) / dx).astype(int)
+            hc = np.ceil((c + r) / dx).astype(int)
+            x = stratified_cells(box_cells(lc, hc), n, seed, stream=3000 + k)
+            d = x.astype(np.float64) - c[:, None]
+            x = x[:, np.sum(d * d, axis=0) <= r * r]
+            v = np.zeros_like(x)
+            v[0] = -side * speed
+            pieces.append(x)
+            vel.append(v)
+            k += 1
+    return {"x": np.ascontiguousarray(np.concatenate(pieces, axis=1)),
+            "v": np.ascontiguousarray(np.concatenate(vel, axis=1))}
 
 
 def sand_blocks(l: int = 12, boxes: int = 4, n: int = 128, seed: int = 6) -> dict:

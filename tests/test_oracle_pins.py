@@ -482,3 +482,30 @@ def test_free_zone_sizes_from_paper(oracle):
     blocks = {(i >> 2) for i in nodes}
     assert len(blocks) == g["physical_blocks_per_axis"]
     assert min(nodes) == 4 * (B - 1) and max(nodes) == 4 * (B + 1) + 3
+
+
+# ------------------------------------------------ multi-threaded oracle form
+@pytest.mark.parametrize("kind", ["jelly", "snow", "water", "sand"])
+def test_threaded_substep_equals_serial(oracle, kind):
+    """The OpenMP form of the substep (slab-ordered P2G sums) gives the serial
+    oracle's state up to FP64 summation order, and the same bits whatever the
+    thread count.  Particles straddle slab borders (a cube spanning many
+    slabs) and some sit outside the grid (skipped and counted alike)."""
+    mat = {"jelly": scenes.JELLY, "snow": scenes.SNOW, "water": scenes.WATER, "sand": scenes.SAND}[kind]
+    x = scenes.uniform(71, 3 * 6000, 0, 0.06, 0.94).reshape(3, -1)
+    x[:, :3] = [[0.001, 0.5, 0.999], [0.5, 0.5, 0.5], [0.5, 0.001, 0.5]]  # stencils off the grid
+    st = scenes.nontrivial_state(x.astype(np.float32), seed=31, kind=kind)
+    cfg = dict(n=32, dt=1e-4, bc="separate")
+    ref, rm, rv, rbad = oracle.substep(cfg, mat, st, steps=3)
+    assert rbad == 3 * 3 * 2  # 3 particles skipped in P2G and G2P of each substep
+    runs = {t: oracle.substep(cfg, mat, st, steps=3, threads=t) for t in (1, 2, 3, 8)}
+    for t, (got, gm, gv, bad) in runs.items():
+        assert bad == rbad
+        for k in ("x", "v", "C", "F", "s"):
+            scale = max(np.abs(ref[k]).max(), 1e-300)
+            assert np.abs(got[k] - ref[k]).max() <= 1e-12 * scale, (t, k)
+        assert np.abs(gm - rm).max() <= 1e-12 * np.abs(rm).max()
+        assert np.abs(gv - rv).max() <= 1e-12 * np.abs(rv).max()
+        if t > 1:  # threads=1 is the serial oracle itself
+            for k in ("x", "v", "C", "F", "s"):
+                assert np.array_equal(got[k], runs[8][0][k]), (t, k)
