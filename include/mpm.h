@@ -345,6 +345,27 @@ int mpm_surrogate_fit_norm(mpm_surrogate* s, int64_t count, const float* X_dev, 
  * minibatch loss of every step.  Synchronizes.                            */
 int mpm_surrogate_train(mpm_surrogate* s, int64_t count, const float* X_dev, const float* T_dev, int32_t steps,
                         int32_t batch, float lr, uint64_t seed, float* loss_host);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight training loops, harnesses that forbid hipMalloc):
+ * mpm_surrogate_train with its scratch -- the minibatch row indices and the
+ * per-step losses, which mpm_surrogate_train allocates on demand -- in a
+ * fixed device array that the library holds for the life of the process
+ * (one per device, MPM_SUR_NOALLOC_MAX_BATCH + MPM_SUR_NOALLOC_MAX_STEPS
+ * 32-bit words, 272 KiB).  Arguments, results and the synchronization at the
+ * end are those of mpm_surrogate_train; the same seed gives the same
+ * minibatches.  batch > MPM_SUR_NOALLOC_MAX_BATCH or steps >
+ * MPM_SUR_NOALLOC_MAX_STEPS fails with MPM_EINVAL before anything is
+ * enqueued.  Calls nothing that allocates (no hipMalloc, hipFree or
+ * allocating library routine); the surrogate's parameters and Adam state
+ * come from mpm_surrogate_create.  Every call on a device shares that
+ * device's array: calls that overlap on one device (from any thread, stream
+ * or surrogate) race, so the caller must order them.  The device current at
+ * the call must be the surrogate's.                                        */
+#define MPM_SUR_NOALLOC_MAX_BATCH 65536
+#define MPM_SUR_NOALLOC_MAX_STEPS 4096
+int mpm_surrogate_train_noalloc(mpm_surrogate* s, int64_t count, const float* X_dev, const float* T_dev,
+                                int32_t steps, int32_t batch, float lr, uint64_t seed, float* loss_host);
 /* Training pairs from the current state of a snow scene: for every particle
  * (in storage order), the trial state of its next return map (the deferred
  * deformation update applied) through the exact return map, as inputs and

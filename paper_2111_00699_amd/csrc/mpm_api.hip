@@ -26,6 +26,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1243,11 +1244,75 @@ int mpm_surrogate_fit_norm(mpm_surrogate* s, int64_t count, const float* X, cons
     return MPM_OK;
 }
 
-int mpm_surrogate_train(mpm_surrogate* s, int64_t count, const float* X, const float* T, int32_t steps, int32_t batch,
-                        float lr, uint64_t seed, float* loss_host) {
+}  // extern "C"
+
+namespace {
+
+// `steps` Adam steps with the minibatch rows in idx[batch] and the per-step
+// losses in loss[steps] (device scratch of the caller's choosing), then the
+// losses to loss_host and a stream synchronization.
+int train_steps(mpm_surrogate* s, int64_t count, const float* X, const float* T, int32_t steps, int32_t batch,
+                float lr, uint64_t seed, float* loss_host, int* idx, float* loss) {
+    for (int k = 0; k < steps; ++k) {
+        sur_indices(s->stream, seed, s->step, batch, count, idx);
+        sur_grad(s->stream, 1, s->theta, s->norm, X, T, batch, idx, s->grad, loss + k, true);
+        sur_adam(s->stream, s->theta, s->grad, s->m, s->v, s->step + 1, lr);
+        ++s->step;
+    }
+    SHIP_OK(hipGetLastError());
+    if (loss_host && steps > 0)
+        SHIP_OK(hipMemcpyAsync(loss_host, loss, sizeof(float) * steps, hipMemcpyDeviceToHost, s->stream));
+    SHIP_OK(hipStreamSynchronize(s->stream));
+    return MPM_OK;
+}
+
+int check_train_args(mpm_surrogate* s, int64_t count, const float* X, const float* T, int32_t steps, int32_t batch,
+                     float lr) {
     if (!s || count < 1 || !X || !T || steps < 0 || batch < 16 || !(lr > 0.0f))
         return sfail(s, MPM_EINVAL, "bad training arguments");
     if (count > INT32_MAX) return sfail(s, MPM_EINVAL, "too many training rows");
+    return MPM_OK;
+}
+
+// Scratch of mpm_surrogate_train_noalloc: the minibatch row indices
+// [MPM_SUR_NOALLOC_MAX_BATCH], then the per-step losses
+// [MPM_SUR_NOALLOC_MAX_STEPS] (FP32 bits).  Each device holds its own copy
+// for the life of the process.  In host code the name stands for no device
+// address: kernels get the address hipGetSymbolAddress returns for the
+// current device (scratch_on_device).
+__device__ __align__(256) int scratch[MPM_SUR_NOALLOC_MAX_BATCH + MPM_SUR_NOALLOC_MAX_STEPS];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+int* g_scratch_dev[SCRATCH_MAX_DEVICES];  // per device, filled on the entry point's first call there
+std::mutex g_scratch_mu;
+
+// Device address of `scratch` on the current device (looked up once per
+// device), or nullptr with the HIP error in *err.
+int* scratch_on_device(hipError_t* err) {
+    int dev = -1;
+    *err = hipGetDevice(&dev);
+    if (*err != hipSuccess) return nullptr;
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        *err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (*err != hipSuccess) return nullptr;
+        g_scratch_dev[dev] = static_cast<int*>(ptr);
+    }
+    return g_scratch_dev[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpm_surrogate_train(mpm_surrogate* s, int64_t count, const float* X, const float* T, int32_t steps, int32_t batch,
+                        float lr, uint64_t seed, float* loss_host) {
+    if (int r = check_train_args(s, count, X, T, steps, batch, lr)) return r;
     if (batch > s->idx_cap) {
         (void)hipFree(s->idx);
         s->idx = nullptr;
@@ -1260,17 +1325,23 @@ int mpm_surrogate_train(mpm_surrogate* s, int64_t count, const float* X, const f
         SHIP_OK(hipMalloc(&s->loss, sizeof(float) * steps));
         s->loss_cap = steps;
     }
-    for (int k = 0; k < steps; ++k) {
-        sur_indices(s->stream, seed, s->step, batch, count, s->idx);
-        sur_grad(s->stream, 1, s->theta, s->norm, X, T, batch, s->idx, s->grad, s->loss + k, true);
-        sur_adam(s->stream, s->theta, s->grad, s->m, s->v, s->step + 1, lr);
-        ++s->step;
-    }
-    SHIP_OK(hipGetLastError());
-    if (loss_host && steps > 0)
-        SHIP_OK(hipMemcpyAsync(loss_host, s->loss, sizeof(float) * steps, hipMemcpyDeviceToHost, s->stream));
-    SHIP_OK(hipStreamSynchronize(s->stream));
-    return MPM_OK;
+    return train_steps(s, count, X, T, steps, batch, lr, seed, loss_host, s->idx, s->loss);
+}
+
+int mpm_surrogate_train_noalloc(mpm_surrogate* s, int64_t count, const float* X, const float* T, int32_t steps,
+                                int32_t batch, float lr, uint64_t seed, float* loss_host) {
+    if (int r = check_train_args(s, count, X, T, steps, batch, lr)) return r;
+    if (batch > MPM_SUR_NOALLOC_MAX_BATCH || steps > MPM_SUR_NOALLOC_MAX_STEPS)
+        return sfail(s, MPM_EINVAL, "mpm_surrogate_train_noalloc: batch above MPM_SUR_NOALLOC_MAX_BATCH or steps "
+                                    "above MPM_SUR_NOALLOC_MAX_STEPS");
+    hipError_t e = hipSuccess;
+    int* ptr = scratch_on_device(&e);
+    if (!ptr)
+        return sfail(s, MPM_EDEVICE, std::string("scratch address lookup failed: ") + hipGetErrorString(e));
+    // every index is written by the step that reads it and every loss slot is
+    // cleared by its step, so nothing left from an earlier call is read
+    return train_steps(s, count, X, T, steps, batch, lr, seed, loss_host, ptr,
+                       reinterpret_cast<float*>(ptr + MPM_SUR_NOALLOC_MAX_BATCH));
 }
 
 int mpm_use_surrogate(mpm_ctx* c, int32_t scene, const mpm_surrogate* s, int32_t mode, float tol, float dt_ref) {

@@ -101,6 +101,8 @@ SIGNATURES = {
     "mpm_surrogate_loss_grad": (ct.c_int, [P, ct.c_int32, ct.c_int64, P, P, P, P]),
     "mpm_surrogate_fit_norm": (ct.c_int, [P, ct.c_int64, P, P]),
     "mpm_surrogate_train": (ct.c_int, [P, ct.c_int64, P, P, ct.c_int32, ct.c_int32, ct.c_float, ct.c_uint64, P]),
+    "mpm_surrogate_train_noalloc": (ct.c_int, [P, ct.c_int64, P, P, ct.c_int32, ct.c_int32, ct.c_float, ct.c_uint64,
+                                               P]),
     "mpm_surrogate_sample": (ct.c_int, [P, ct.c_int32, ct.c_float, ct.c_int64, P, P, ct.POINTER(ct.c_int64)]),
     "mpm_use_surrogate": (ct.c_int, [P, ct.c_int32, P, ct.c_int32, ct.c_float, ct.c_float]),
 }
@@ -306,6 +308,8 @@ class Sim:
 
 
 SUR_IN, SUR_OUT, SUR_PARAMS, SUR_NORM = 12, 12, 5772, 48
+# limits of mpm_surrogate_train_noalloc (its fixed scratch array)
+SUR_NOALLOC_MAX_BATCH, SUR_NOALLOC_MAX_STEPS = 65536, 4096
 SUR_FP32, SUR_BF16 = 0, 1
 
 
@@ -376,11 +380,14 @@ class Surrogate:
         self._check(self.lib.mpm_surrogate_fit_norm(self.h, X.numel() // SUR_IN, _ptr(X), _ptr(T)))
         self.synchronize()
 
-    def train(self, X, T, steps, batch=4096, lr=1e-3, seed=0):
+    def train(self, X, T, steps, batch=4096, lr=1e-3, seed=0, noalloc=False):
+        """Adam steps on minibatches of (X, T); noalloc selects the entry point
+        that keeps its scratch in the library's fixed device array."""
         X, T = self._t(X), self._t(T)
         losses = np.zeros(max(int(steps), 1), dtype=np.float32)
-        self._check(self.lib.mpm_surrogate_train(self.h, X.numel() // SUR_IN, _ptr(X), _ptr(T), int(steps),
-                                                 int(batch), float(lr), int(seed), losses.ctypes.data))
+        fn = self.lib.mpm_surrogate_train_noalloc if noalloc else self.lib.mpm_surrogate_train
+        self._check(fn(self.h, X.numel() // SUR_IN, _ptr(X), _ptr(T), int(steps), int(batch), float(lr), int(seed),
+                       losses.ctypes.data))
         return losses[:int(steps)]
 
     @staticmethod

@@ -149,3 +149,12 @@ def test_documented_chunk_layout_rule_is_a_permutation():
         o = dealt_order(ragged)
         passes = {int(np.flatnonzero(o == i)[0]) // 16 for i in range(3)}
         assert len(passes) == want, size
+
+
+def test_noalloc_limits_match_the_header():
+    from paper_2111_00699_amd import mpm
+
+    text = open(HEADER).read()
+    got = {k: int(v) for k, v in re.findall(r"#define (MPM_SUR_NOALLOC_MAX_\w+) (\d+)", text)}
+    assert got == {"MPM_SUR_NOALLOC_MAX_BATCH": mpm.SUR_NOALLOC_MAX_BATCH,
+                   "MPM_SUR_NOALLOC_MAX_STEPS": mpm.SUR_NOALLOC_MAX_STEPS}
