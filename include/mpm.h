@@ -222,7 +222,10 @@ int mpm_synchronize(mpm_ctx* ctx);
 /* Copy the particles of `scene` into caller device arrays, in insertion
  * order.  count must equal the scene's particle count.  Any output may be
  * NULL.  F/s are the state after the last G2P's deformation update (the
- * update is applied on the fly when it is still deferred).  Synchronizes.  */
+ * update is applied on the fly when it is still deferred; in a context where
+ * a snow scene takes the learned or closed-form map, it is first landed in
+ * the stored state with each scene's own map, as the next P2G would apply
+ * it).  Synchronizes.                                                      */
 int mpm_read_particles(mpm_ctx* ctx, int32_t scene, int64_t count, float* x_dev, float* v_dev, float* C_dev,
                        float* F_dev, float* s_dev);
 
@@ -329,7 +332,9 @@ int mpm_surrogate_destroy(mpm_surrogate* s);
 /* Copy parameters / normalisation in or out; either pointer may be NULL. */
 int mpm_surrogate_set(mpm_surrogate* s, const float* theta_dev, const float* norm_dev);
 int mpm_surrogate_get(mpm_surrogate* s, float* theta_dev, float* norm_dev);
-/* Y = network(X) in physical (de-normalised) units.                          */
+/* Y = network(X) in physical (de-normalised) units.  MPM_SUR_BF16 runs the
+ * inference path P2G runs: weights rounded to BF16 once as they are staged,
+ * BF16 MFMA with FP32 accumulation, P2G's input normalisation.              */
 int mpm_surrogate_forward(mpm_surrogate* s, int32_t precision, int64_t count, const float* X_dev, float* Y_dev);
 /* Mean over the rows of 1/2 |y~ - t~|^2 in z-scored units into loss_dev[0]
  * and its gradient into grad_dev[MPM_SUR_PARAMS].                          */

@@ -72,6 +72,7 @@ def lib():
             "om_p2g": (L, [ct.POINTER(_Cfg), ct.POINTER(_Mat), L, D, D, D, D, D, D, D]),
             "om_grid_update": (None, [ct.POINTER(_Cfg), D, D]),
             "om_g2p": (L, [ct.POINTER(_Cfg), ct.POINTER(_Mat), L, D, D, D, D, D, D]),
+            "om_g2p_trial": (L, [ct.POINTER(_Cfg), ct.POINTER(_Mat), L, D, D, D, D, D, D]),
             "om_substep": (L, [ct.POINTER(_Cfg), ct.POINTER(_Mat), L, D, D, D, D, D, D, D]),
             "om_substep_omp": (L, [ct.POINTER(_Cfg), ct.POINTER(_Mat), L, D, D, D, D, D, D, D, ct.c_int]),
             "om_keys": (L, [L, F32, ct.c_int, U32, I32]),
@@ -218,6 +219,18 @@ def g2p(cfg: dict, mat: dict, st: dict, gv: np.ndarray):
     N = s["x"].shape[1]
     bad = lib().om_g2p(ct.byref(c), ct.byref(m), N, *(_p(s[k], ct.c_double) for k in "xvCFs"),
                        _p(gv, ct.c_double))
+    return s, bad
+
+
+def g2p_trial(cfg: dict, mat: dict, st: dict, gv: np.ndarray):
+    """G2P up to the trial gradient F^ = (I + dt C') F: x, v, C updated, F
+    set to F^, s unchanged (no return map)."""
+    s = _state(st)
+    gv = np.ascontiguousarray(gv, dtype=np.float64)
+    c, m = _cfg(cfg), _mat(mat)
+    N = s["x"].shape[1]
+    bad = lib().om_g2p_trial(ct.byref(c), ct.byref(m), N, *(_p(s[k], ct.c_double) for k in "xvCFs"),
+                             _p(gv, ct.c_double))
     return s, bad
 
 

@@ -424,8 +424,8 @@ void om_grid_update(const om_config* cfg, const double* gm, double* gv) {
  * then the material update with the new C'.  In-place on x, v, C, F, s.
  * One particle; returns 1 (and leaves it unchanged) if its stencil leaves
  * the grid.                                                                 */
-static int g2p_particle(const om_config* cfg, const om_material* mat, long N, long p, double* x, double* v,
-                        double* C, double* F, double* s, const double* gv) {
+static int g2p_particle_map(const om_config* cfg, const om_material* mat, long N, long p, double* x, double* v,
+                            double* C, double* F, double* s, const double* gv, int apply_map) {
     const int n = cfg->n;
     const double dx = 1.0 / n, dt = cfg->dt;
     const long NN = (long)(n + 1) * (n + 1) * (n + 1);
@@ -464,7 +464,9 @@ static int g2p_particle(const om_config* cfg, const om_material* mat, long N, lo
         double Fp[9], Fn[9];
         for (int c = 0; c < 9; ++c) Fp[c] = F[c * N + p];
         mat_mul(G, Fp, Fn);
-        if (mat->kind == OM_SNOW) {
+        if (!apply_map) {
+            /* trial gradient only: a caller applies the return map */
+        } else if (mat->kind == OM_SNOW) {
             double Fe[9], Jp;
             om_snow_project(mat, Fn, s[p], Fe, &Jp);
             memcpy(Fn, Fe, sizeof Fe);
@@ -480,10 +482,24 @@ static int g2p_particle(const om_config* cfg, const om_material* mat, long N, lo
     return 0;
 }
 
+static int g2p_particle(const om_config* cfg, const om_material* mat, long N, long p, double* x, double* v,
+                        double* C, double* F, double* s, const double* gv) {
+    return g2p_particle_map(cfg, mat, N, p, x, v, C, F, s, gv, 1);
+}
+
 long om_g2p(const om_config* cfg, const om_material* mat, long N, double* x, double* v, double* C, double* F,
             double* s, const double* gv) {
     long bad = 0;
     for (long p = 0; p < N; ++p) bad += g2p_particle(cfg, mat, N, p, x, v, C, F, s, gv);
+    return bad;
+}
+
+/* G2P that stops at the trial gradient F^ = (I + dt C') F (snow, sand: no
+ * return map; s unchanged), for a caller that maps F^ itself.              */
+long om_g2p_trial(const om_config* cfg, const om_material* mat, long N, double* x, double* v, double* C, double* F,
+                  double* s, const double* gv) {
+    long bad = 0;
+    for (long p = 0; p < N; ++p) bad += g2p_particle_map(cfg, mat, N, p, x, v, C, F, s, gv, 0);
     return bad;
 }
 

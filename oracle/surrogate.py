@@ -157,3 +157,99 @@ def normalize_stats(A: np.ndarray, floor: float = 1e-6):
     mu = A.mean(axis=0)
     sd = np.maximum(A.std(axis=0), floor)
     return mu, sd
+
+
+# ------------------------------------------------- the map with the network
+# The learned snow return map as a substep uses it, in FP64: the trial
+# gradient's singular values come from the eigenvalues of b = F^ F^T; the
+# network predicts ln(s'/s) and J_P'/J_P; a particle keeps the prediction only
+# if the rebuild without eigenvectors is well conditioned and the prediction
+# passes the residual checks, else it takes the exact map.  The new gradient
+# is U diag(s'/s) U^T F^ (U the eigenvectors of b), which has the principal
+# directions of F^ and the singular values s'.
+EIG_GAP = 0.1      # smallest gap between eigenvalues of the normalised deviator of b
+EIG_RESOLVE = 2e-5  # the deviator of b must exceed this multiple of its mean to be resolved
+
+
+def snow_map_network(mat: dict, Fhat: np.ndarray, Jp: np.ndarray, theta: np.ndarray, norm: np.ndarray,
+                     dt: float, dt_ref: float, tol: float, gap: float = EIG_GAP, predict=None):
+    """Fhat (N,3,3) trial gradients, Jp (N,).  Returns (Fe (N,3,3), Jp_new (N,),
+    used (N,) bool: the network's prediction was kept, margins (N,5): signed
+    distances of the decision quantities to their thresholds, positive on the
+    network's side: the two eigenvalue gaps in eigenvalue units of b, and the
+    three residuals in their units).
+    predict(X) -> outputs in physical units may stand in for the network."""
+    from . import snow_project  # the exact map (C oracle)
+
+    Fhat = np.asarray(Fhat, dtype=np.float64)
+    Jp = np.asarray(Jp, dtype=np.float64)
+    N = Fhat.shape[0]
+    b = Fhat @ np.transpose(Fhat, (0, 2, 1))
+    lam, U = np.linalg.eigh(b)              # ascending
+    lam, U = lam[:, ::-1], U[:, :, ::-1]    # descending
+    q = np.trace(b, axis1=1, axis2=2) / 3.0
+    dev = b - q[:, None, None] * np.eye(3)
+    p = np.sqrt(np.sum(dev * dev, axis=(1, 2)) / 6.0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        mu = (lam - q[:, None]) / p[:, None]
+    detF = np.linalg.det(Fhat)
+    resolved = p > EIG_RESOLVE * np.abs(q)
+    g01, g12 = mu[:, 0] - mu[:, 1], mu[:, 1] - mu[:, 2]
+    eligible = resolved & (detF > 0) & (g01 >= gap) & (g12 >= gap)
+    sh = np.sqrt(np.maximum(lam, 1e-30))
+    X = features(mat, sh, Jp, dt, dt_ref)
+    if predict is None:
+        Y, _ = forward(theta, (X - norm[0:12]) / norm[12:24])
+        yv = Y * norm[36:48] + norm[24:36]
+    else:
+        yv = predict(X)
+    sn = sh * np.exp(yv[:, 3:6])
+    Jpn = Jp * yv[:, 9]
+    mu0, la0 = lame(mat)
+    h = np.exp(mat["xi"] * (1.0 - Jpn))
+    Jn = np.prod(sn, axis=1)
+    tk = 2.0 * (mu0 * h)[:, None] * (sn - 1.0) * sn + ((la0 * h) * (Jn - 1.0) * Jn)[:, None]
+    lo, hi = 1 - mat["theta_c"], 1 + mat["theta_s"]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        res_t = np.max(np.abs(yv[:, 6:9] - tk / mat["E"]), axis=1)
+        res_y = np.max(np.maximum(lo - sn, sn - hi), axis=1)
+        res_v = np.abs(np.log(Jn * Jpn) - np.log(np.prod(sh, axis=1) * Jp))
+    finite = np.isfinite(tk.sum(axis=1) + Jpn + sn.sum(axis=1))
+    used = eligible & finite & (res_y <= tol) & (res_v <= tol) & (res_t <= tol)
+    Fe = np.empty_like(Fhat)
+    Jp_new = np.empty_like(Jp)
+    G = U @ (np.where(used[:, None], sn / sh, 1.0)[:, :, None] * np.transpose(U, (0, 2, 1)))
+    Fe[used] = (G @ Fhat)[used]
+    Jp_new[used] = Jpn[used]
+    for k in np.nonzero(~used)[0]:
+        Fe[k], Jp_new[k] = snow_project(mat, Fhat[k], Jp[k])
+    # gap margins in eigenvalue units of b (the normalised gaps times p), the
+    # size an error in b has to reach to flip the decision
+    margins = np.stack([(g01 - gap) * p, (g12 - gap) * p, tol - res_y, tol - res_v, tol - res_t], axis=1)
+    return Fe, Jp_new, used, margins
+
+
+def substep_network(cfg: dict, mat: dict, st: dict, theta: np.ndarray, norm: np.ndarray, tol: float,
+                    dt_ref: float, steps: int = 1):
+    """`steps` substeps of a snow scene whose return map is the learned one:
+    P2G, grid update and G2P of the FP64 oracle, each G2P's trial gradient
+    mapped by snow_map_network.  Returns (state, used, margins): used and
+    margins of the last map, and for every particle the margin of smallest
+    size (per decision quantity) over all the maps."""
+    from . import _state, g2p_trial, grid_update, p2g
+
+    s = _state(st)
+    N = s["x"].shape[1]
+    used = margins = None
+    for _ in range(steps):
+        s, gm, gp, bad = p2g(cfg, mat, s)
+        assert bad == 0
+        gv = grid_update(cfg, gm, gp)
+        s, bad = g2p_trial(cfg, mat, s, gv)
+        assert bad == 0
+        Fhat = s["F"].T.reshape(N, 3, 3)
+        Fe, Jpn, used, m = snow_map_network(mat, Fhat, s["s"], theta, norm, cfg["dt"], dt_ref, tol)
+        margins = m if margins is None else np.where(np.abs(m) < np.abs(margins), m, margins)
+        s["F"] = np.ascontiguousarray(Fe.reshape(N, 9).T)
+        s["s"] = Jpn
+    return s, used, margins

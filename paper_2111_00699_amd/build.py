@@ -4,7 +4,10 @@
 
 Each HIP source is compiled with hipcc for gfx950 only; packed-FP32 VALU
 instructions are disabled and float atomics are emitted as the native
-hardware instructions.
+hardware instructions.  Two variants are linked: libmpm.so with the
+fast-math flags (the default) and libmpm_precise.so with IEEE division,
+square root and denormals (the fast-math ablation); the binding loads the
+second when MPM_LIBRARY=precise.
 """
 from __future__ import annotations
 
@@ -19,41 +22,53 @@ OUT = os.path.join(HERE, "libmpm.so")
 OBJ = os.path.join(HERE, "_build")
 SOURCES = ["mpm_bin.hip", "mpm_p2g.hip", "mpm_step.hip", "mpm_surrogate.hip", "mpm_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = [
+BASE_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    # FP32 denormals flushed (no scaling code around sqrt, rcp, log, exp) and
-    # divisions by reciprocal: about 1% off the snow frame. NaN and Inf keep
-    # their meaning (no finite-math), so the state checks still see them.
-    "-fgpu-flush-denormals-to-zero", "-fno-signed-zeros", "-freciprocal-math",
     "-Wall", "-Wno-unused-result",
 ]
+# The paper's "Adopt fast-math intrinsics": FP32 denormals flushed (no
+# scaling code around sqrt, rcp, log, exp), divisions by reciprocal, and the
+# hardware's square root and reciprocal (1 ulp) instead of the correctly
+# rounded expansions.  NaN and Inf keep their meaning (no finite-math), so
+# the state checks still see them.
+FAST_MATH_FLAGS = ["-fgpu-flush-denormals-to-zero", "-fno-signed-zeros", "-freciprocal-math",
+                   "-fno-hip-fp32-correctly-rounded-divide-sqrt"]
+# Library variants: the default build and, for the fast-math ablation, one
+# with IEEE division, square root and denormals.
+VARIANTS = {"fast": ("libmpm.so", FAST_MATH_FLAGS), "precise": ("libmpm_precise.so", [])}
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(SRC, src), "-o", obj]
+def _compile(src: str, variant: str) -> str:
+    out_dir = os.path.join(OBJ, variant)
+    obj = os.path.join(out_dir, os.path.splitext(src)[0] + ".o")
+    cmd = [HIPCC, *BASE_FLAGS, *VARIANTS[variant][1], "-c", os.path.join(SRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{err}")
-    if err.strip():
+    if err.strip() and variant == "fast":
         print(err, file=sys.stderr)
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(OBJ, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = OUT + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError("link failed:\n" + r.stderr)
-    os.replace(tmp, OUT)
-    if verbose:
-        print(OUT)
+def build(verbose: bool = False, variants=("fast", "precise")) -> str:
+    jobs = [(src, v) for v in variants for src in SOURCES]
+    for v in variants:
+        os.makedirs(os.path.join(OBJ, v), exist_ok=True)
+    with ThreadPoolExecutor(max_workers=min(len(jobs), 8)) as ex:
+        objs = list(ex.map(lambda j: _compile(*j), jobs))
+    for v in variants:
+        out = os.path.join(HERE, VARIANTS[v][0])
+        mine = [o for o, (_, jv) in zip(objs, jobs) if jv == v]
+        tmp = out + ".tmp%d" % os.getpid()
+        cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *mine]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("link failed:\n" + r.stderr)
+        os.replace(tmp, out)
+        if verbose:
+            print(out)
     return OUT
 
 

@@ -615,6 +615,22 @@ int scene_arg(mpm_ctx* c, int32_t scene) {
 
 }  // namespace
 
+namespace {
+
+// Apply the deferred deformation update of the last G2P to the stored state
+// (with each snow scene's map), after which no update is pending.
+int land_pending(mpm_ctx* c) {
+    if (c->sur_any)
+        enqueue_materialize_map(c->stream, c->L, tables(c), c->S[c->cur], c->cap, c->B.chunks, c->ctl, c->cfg.chunk);
+    else
+        enqueue_materialize(c->stream, tables(c), c->S[c->cur], c->cap, (int)c->N);
+    HIP_OK(c, hipGetLastError());
+    c->pending = 0;
+    return MPM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int mpm_create(const mpm_config* cfg, mpm_ctx** out) {
@@ -810,8 +826,7 @@ int mpm_add_particles(mpm_ctx* c, int32_t scene, const mpm_material* mat, int64_
         if (r) return r;
     }
     if (c->pending) {  // land the deferred update so old and new particles share one state convention
-        enqueue_materialize(c->stream, tables(c), c->S[c->cur], c->cap, (int)c->N);
-        c->pending = 0;
+        if (int r = land_pending(c)) return r;
     }
     enqueue_insert(c->stream, c->S[c->cur], c->ids[c->cur], c->cap, (int)c->N, (int)count, scene, (int)sh.N, x, v, C,
                    F, s, c->ctl);
@@ -856,6 +871,10 @@ int mpm_read_particles(mpm_ctx* c, int32_t scene, int64_t count, float* x, float
     if (int r = scene_arg(c, scene)) return r;
     if (count != c->sh[scene].N) return fail(c, MPM_EINVAL, "count must equal the scene's particle count");
     if (int r = bring_up_to_date(c)) return r;
+    // a snow map without SVD (learned or closed form) is landed by its own kernel first, so the
+    // state read is the one the next P2G would use
+    if (c->pending && c->sur_any && (F || s))
+        if (int r = land_pending(c)) return r;
     enqueue_read(c->stream, tables(c), c->S[c->cur], c->ids[c->cur], c->cap, (int)c->N, scene, (int)count, c->pending,
                  x, v, C, F, s);
     HIP_OK(c, hipGetLastError());

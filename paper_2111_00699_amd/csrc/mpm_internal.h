@@ -215,6 +215,10 @@ void enqueue_g2p(hipStream_t st, const Launch& L, const Scenes& T, float* S, int
                  int* ctl, const GridBuffers& G, int* host_flag, int lds_box, int parity, int fb_limit, int chunk,
                  int act, int report_zone);
 void enqueue_materialize(hipStream_t st, const Scenes& T, float* S, int64_t cap, int N);
+// The same with each snow scene's own map (exact, closed form or network), over the chunk list of the
+// last rebuild; for contexts with T.sur_any != 0.
+void enqueue_materialize_map(hipStream_t st, const Launch& L, const Scenes& T, float* S, int64_t cap,
+                             const Chunk* chunks, const int* ctl, int chunk);
 void enqueue_insert(hipStream_t st, float* S, int* ids, int64_t cap, int N0, int count, int scene, int id0,
                     const float* x, const float* v, const float* C, const float* F, const float* s, int* ctl);
 void enqueue_read(hipStream_t st, const Scenes& T, const float* S, const int* ids, int64_t cap, int N, int scene,

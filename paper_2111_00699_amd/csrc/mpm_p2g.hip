@@ -481,6 +481,18 @@ __device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, con
             const unsigned long long fb = __ballot(have && ok && !GLOBAL_ONLY && in_zone && nt <= 0);
             if (fb && lane == 0) atomicAdd(&ctl[CTL_FB + parity], (int)__popcll(fb));
         }
+        // Tile lanes whose stencil holds a weight below TINY_W send those
+        // contributions to the global accumulators instead; the smallest of a
+        // stencil's 27 weights is the product of its per-axis minima.  The
+        // per-node test is only compiled into the pass of waves that have
+        // such a lane (rare: a coordinate within 2^-11 dx of a cell edge).
+        bool any_tiny = false;
+        if (!GLOBAL_ONLY) {
+            float wmin = 1.0f;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) wmin *= fminf(fminf(st.w[a][0], st.w[a][1]), st.w[a][2]);
+            any_tiny = __any(have && ok && in_zone && nt > 0 && wmin < TINY_W);
+        }
         if (have && ok) {
             if (!GLOBAL_ONLY && in_zone && nt > 0) {
                 const int tb = (st.base[0] - lo[0]) + R * (st.base[1] - lo[1]) + Q * (st.base[2] - lo[2]);
@@ -490,40 +502,47 @@ __device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, con
                 for (int a = 0; a < 3; ++a) qs[a] = q[a] * m_scale;
 #pragma unroll
                 for (int k = 0; k < 9; ++k) As[k] = Ad[k] * m_scale;
+                auto scatter = [&](auto check) {
+                    constexpr bool CHECK = decltype(check)::value;
 #pragma unroll
-                for (int o2 = 0; o2 < 3; ++o2)
+                    for (int o2 = 0; o2 < 3; ++o2)
 #pragma unroll
-                    for (int o1 = 0; o1 < 3; ++o1) {
-                        const float wyz = st.w[1][o1] * st.w[2][o2];
-                        float m0 = qs[0] + o1 * As[1] + o2 * As[2];
-                        float m1 = qs[1] + o1 * As[4] + o2 * As[5];
-                        float m2 = qs[2] + o1 * As[7] + o2 * As[8];
-                        const int row = tb + R * o1 + Q * o2;
+                        for (int o1 = 0; o1 < 3; ++o1) {
+                            const float wyz = st.w[1][o1] * st.w[2][o2];
+                            float m0 = qs[0] + o1 * As[1] + o2 * As[2];
+                            float m1 = qs[1] + o1 * As[4] + o2 * As[5];
+                            float m2 = qs[2] + o1 * As[7] + o2 * As[8];
+                            const int row = tb + R * o1 + Q * o2;
 #pragma unroll
-                        for (int o0 = 0; o0 < 3; ++o0) {
-                            const float w = wyz * st.w[0][o0];
-                            const int t = row + o0;
-                            if (w >= TINY_W) {
-                                atomicAdd(&tu[t], fixed64(w * W_SCALE));
-                                atomicAdd(&tu[CT + t], fixed64(w * m0));
-                                atomicAdd(&tu[2 * CT + t], fixed64(w * m1));
-                                atomicAdd(&tu[3 * CT + t], fixed64(w * m2));
-                            } else {  // rare: to the node's global accumulator, in FP32
-                                const int gx = st.base[0] + o0, gy = st.base[1] + o1, gz = st.base[2] + o2;
-                                const int bk = (((gz >> 2) + 1) * P.NB + ((gy >> 2) + 1)) * P.NB + ((gx >> 2) + 1);
-                                float* a = acc + 4 * ((int64_t)(sc.brick_base + bk) * BLOCK_NODES + (gx & 3) +
-                                                      ((gy & 3) << 2) + ((gz & 3) << 4));
-                                unsafeAtomicAdd(a + 0, w * M.mp);
-                                unsafeAtomicAdd(a + 1, w * m0 * m_unit);
-                                unsafeAtomicAdd(a + 2, w * m1 * m_unit);
-                                unsafeAtomicAdd(a + 3, w * m2 * m_unit);
-                                acc_dirty[sc.brick_base + bk] = 1;
+                            for (int o0 = 0; o0 < 3; ++o0) {
+                                const float w = wyz * st.w[0][o0];
+                                const int t = row + o0;
+                                if (!CHECK || w >= TINY_W) {
+                                    atomicAdd(&tu[t], fixed64(w * W_SCALE));
+                                    atomicAdd(&tu[CT + t], fixed64(w * m0));
+                                    atomicAdd(&tu[2 * CT + t], fixed64(w * m1));
+                                    atomicAdd(&tu[3 * CT + t], fixed64(w * m2));
+                                } else {  // rare: to the node's global accumulator, in FP32
+                                    const int gx = st.base[0] + o0, gy = st.base[1] + o1, gz = st.base[2] + o2;
+                                    const int bk = (((gz >> 2) + 1) * P.NB + ((gy >> 2) + 1)) * P.NB + ((gx >> 2) + 1);
+                                    float* a = acc + 4 * ((int64_t)(sc.brick_base + bk) * BLOCK_NODES + (gx & 3) +
+                                                          ((gy & 3) << 2) + ((gz & 3) << 4));
+                                    unsafeAtomicAdd(a + 0, w * M.mp);
+                                    unsafeAtomicAdd(a + 1, w * m0 * m_unit);
+                                    unsafeAtomicAdd(a + 2, w * m1 * m_unit);
+                                    unsafeAtomicAdd(a + 3, w * m2 * m_unit);
+                                    acc_dirty[sc.brick_base + bk] = 1;
+                                }
+                                m0 += As[0];
+                                m1 += As[3];
+                                m2 += As[6];
                             }
-                            m0 += As[0];
-                            m1 += As[3];
-                            m2 += As[6];
                         }
-                    }
+                };
+                if (any_tiny)
+                    scatter(std::true_type{});
+                else
+                    scatter(std::false_type{});
             } else {
                 if (!in_zone)
                     activate_blocks(st, P.NB, sc.brick_base, brick_state, ovf, &ctl[CTL_OVF + parity], nbricks, err);
@@ -599,6 +618,60 @@ __device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, con
 }
 
 
+// Land the deferred deformation update of every particle with its scene's
+// snow map -- exact, closed form (no SVD) or the network -- the way P2G
+// applies it, for contexts where some snow scene takes a map without SVD.
+// One chunk per workgroup pass (a chunk holds one scene, so the network runs
+// on whole waves of one scene).
+template <int SURM, int NT>
+__global__ __launch_bounds__(NT) void k_materialize_map(float* __restrict__ S, int64_t cap,
+                                                        const Chunk* __restrict__ chunks, const int* __restrict__ ctl,
+                                                        Scenes T) {
+    struct Empty {};
+    __shared__ typename std::conditional<SURM == 2, mlp::NetLds16, Empty>::type net;
+    __shared__ float sur_stage[SURM == 2 ? NT / 64 * 512 : 1];
+    if constexpr (SURM == 2) {
+        if (T.sur_theta) mlp::load_net16(net, T.sur_theta, T.sur_norm);
+        __syncthreads();
+    }
+    const int nchunk = ctl[CTL_NCHUNK];
+    const int tid = threadIdx.x, wv = tid >> 6;
+    for (int c = blockIdx.x; c < nchunk; c += gridDim.x) {
+        const Chunk ch = chunks[c];
+        const Scene& sc = T.scene[ch.scene];
+        const Mat M = sc.M;
+        const bool have = tid < ch.count;
+        const int p = ch.start + (have ? tid : 0);
+        float C[9], F[9], s = 1.0f, tau[6];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            C[k] = have ? S[(FC + k) * cap + p] : 0.0f;
+            F[k] = have ? S[(FF + k) * cap + p] : ((k % 4 == 0) ? 1.0f : 0.0f);
+        }
+        if (have) s = S[FS * cap + p];
+        bool fb = false;
+        if (sc.ret != 0 && M.kind == MPM_SNOW) {  // uniform over the workgroup
+            if constexpr (SURM == 2) {
+                if (sc.ret == 1)
+                    snow_without_svd<true>(&net, sur_stage + wv * 512, T, sc, sc.P.dt, 1, have, C, F, s, tau, fb);
+                else
+                    snow_without_svd<false>(&net, sur_stage, T, sc, sc.P.dt, 1, have, C, F, s, tau, fb);
+            } else {
+                snow_without_svd<false>(nullptr, nullptr, T, sc, sc.P.dt, 1, have, C, F, s, tau, fb);
+            }
+        } else if (have) {
+            material_step(M, sc.P.dt, 1, C, F, s, tau);
+        }
+        if (have) {
+            if (M.kind != MPM_WATER) {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) S[(FF + k) * cap + p] = F[k];
+            }
+            if (M.kind != MPM_JELLY) S[FS * cap + p] = s;
+        }
+    }
+}
+
 #define MPM_P2G_PARAMS                                                                                          \
     float *__restrict__ S, int64_t cap, const Chunk *__restrict__ chunks, int *__restrict__ ctl,               \
         float *__restrict__ acc, int *__restrict__ acc_dirty, float4 *__restrict__ stage, int stage_nodes,     \
@@ -631,9 +704,13 @@ int p2g_grid_size(int cus, int chunk) {
     const void* fn = nt == 128   ? reinterpret_cast<const void*>(k_p2g<false, 128, 0>)
                      : nt == 256 ? reinterpret_cast<const void*>(k_p2g<false, 256, 0>)
                                  : reinterpret_cast<const void*>(k_p2g<false, 512, 0>);
-    // Twice the resident workgroups: chunks differ in size, and a second wave
-    // of workgroups evens out the per-XCD work split.
-    int occ = 2 * wgs_per_cu(fn, nt);
+    // Four times the resident workgroups (at most 4096 threads per CU): the
+    // chunks of the block-sorted list differ in cost (fill, box size), and
+    // with each workgroup taking every stride-th chunk of its XCD's slice,
+    // more and shorter-lived workgroups even the load out (twice the
+    // resident count: 146.6 us, four times: 140.9 us per launch on the
+    // 1.28M-particle snow scene, frames 2-40).
+    int occ = 4 * wgs_per_cu(fn, nt);
     if (occ > 4096 / nt) occ = 4096 / nt;
     const int g = cus * occ;
     return g < 8 ? 8 : (g / 8) * 8;
@@ -663,6 +740,20 @@ void enqueue_p2g(hipStream_t st, const Launch& L, const Scenes& T, float* S, int
         if (surm == 2) MPM_LAUNCH_P2G_NT(false, 2); else if (surm == 1) MPM_LAUNCH_P2G_NT(false, 1); else MPM_LAUNCH_P2G_NT(false, 0);
     }
 #undef MPM_LAUNCH_P2G_NT
+}
+
+void enqueue_materialize_map(hipStream_t st, const Launch& L, const Scenes& T, float* S, int64_t cap,
+                             const Chunk* chunks, const int* ctl, int chunk) {
+    const int nt = chunk_threads(chunk);
+    const int grid = L.p2g_grid;
+#define MPM_LAUNCH_MAT(SU)                                                                                        \
+    do {                                                                                                          \
+        if (nt == 128) hipLaunchKernelGGL((k_materialize_map<SU, 128>), dim3(grid), dim3(128), 0, st, S, cap, chunks, ctl, T); \
+        else if (nt == 256) hipLaunchKernelGGL((k_materialize_map<SU, 256>), dim3(grid), dim3(256), 0, st, S, cap, chunks, ctl, T); \
+        else hipLaunchKernelGGL((k_materialize_map<SU, 512>), dim3(grid), dim3(512), 0, st, S, cap, chunks, ctl, T); \
+    } while (0)
+    if (T.sur_any == 2) MPM_LAUNCH_MAT(2); else MPM_LAUNCH_MAT(1);
+#undef MPM_LAUNCH_MAT
 }
 
 }  // namespace mpm

@@ -56,6 +56,38 @@ __global__ __launch_bounds__(SW) void k_sur_forward(const float* __restrict__ th
     }
 }
 
+// Y = network(X) with the BF16 inference copy of the network: the weights
+// rounded to BF16 once as they are staged (NetLds16) and the 16-sample tile
+// forward pass P2G runs (forward_tile16), with P2G's input normalisation.
+__global__ __launch_bounds__(SW) void k_sur_forward16(const float* __restrict__ th, const float* __restrict__ norm,
+                                                      const float* __restrict__ X, int64_t count,
+                                                      float* __restrict__ Y) {
+    __shared__ NetLds16 L;
+    __shared__ float xin[SW / 64][16 * 16];
+    load_net16(L, th, norm);
+    __syncthreads();
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, s = lane & 15;
+    const int64_t tiles = (count + 15) / 16;
+    for (int64_t t = (int64_t)blockIdx.x * (SW / 64) + w; t < tiles; t += (int64_t)gridDim.x * (SW / 64)) {
+        const int64_t row = 16 * t + s;
+        const bool valid = row < count;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {  // lane group g stages features 4g..4g+3 of sample s
+            const int f = 4 * g + j;
+            xin[w][s * 16 + f] = (valid && f < SUR_IN) ? (X[row * SUR_IN + f] - L.imu[f]) / L.isd[f] : 0.0f;
+        }
+        __builtin_amdgcn_wave_barrier();
+        float y[4];
+        forward_tile16(L, xin[w], y);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int o = 4 * g + r;
+            if (valid && o < SUR_OUT) Y[row * SUR_OUT + o] = y[r] * L.osd[o] + L.omu[o];
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 // Loss 1/2 |y~ - t~|^2 averaged over `count` samples (normalised space) and
 // its gradient, accumulated into grad[SUR_PARAMS] and *loss (both zeroed by
 // the caller).
@@ -372,8 +404,8 @@ void sur_forward(hipStream_t st, int bf16, const float* th, const float* norm, c
     if (count <= 0) return;
     const int64_t tiles = (count + 15) / 16;
     const int grid = (int)((tiles + 3) / 4 < 4096 ? (tiles + 3) / 4 : 4096);
-    if (bf16)
-        hipLaunchKernelGGL(k_sur_forward<true>, dim3(grid), dim3(SW), 0, st, th, norm, X, count, Y);
+    if (bf16)  // the inference path P2G runs
+        hipLaunchKernelGGL(k_sur_forward16, dim3(grid), dim3(SW), 0, st, th, norm, X, count, Y);
     else
         hipLaunchKernelGGL(k_sur_forward<false>, dim3(grid), dim3(SW), 0, st, th, norm, X, count, Y);
 }

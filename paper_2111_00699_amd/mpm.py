@@ -12,7 +12,10 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmpm.so")
+# MPM_LIBRARY=precise selects the build with IEEE division, square root and
+# denormals (the fast-math ablation); the default is the fast-math build.
+LIB_VARIANTS = {"fast": "libmpm.so", "precise": "libmpm_precise.so"}
+LIB_PATH = os.path.join(HERE, LIB_VARIANTS[os.environ.get("MPM_LIBRARY", "fast") or "fast"])
 
 KIND = {"jelly": 0, "snow": 1, "water": 2, "sand": 3}
 BC = {"sticky": 0, "slip": 1, "separate": 2}

@@ -220,3 +220,90 @@ def test_trained_surrogate_runs_in_the_substep(torch_cuda):
         assert np.all(np.isfinite(got[k])), k
     assert normwise(got["x"], exact["x"]) < 1e-4
     sur.close()
+
+
+def _oracle_trained_network(seed=12, count=20000, steps=600, batch=1024, lr=3e-3):
+    """A network trained by the FP64 oracle's own backpropagation and Adam on
+    exact-map pairs (so no input of the oracle comes from the GPU): trial
+    singular values 1 +- 0.04 and J_P in [0.85, 1.1].  Returns (theta, norm)."""
+    st = scenes.snow_trial_states(seed, count, spread=0.04)
+    X = S.features(scenes.SNOW, st["sig_hat"], st["Jp"], 1e-4, 1e-4)
+    T = S.targets(scenes.SNOW, st["sig_hat"], st["Jp"])
+    norm = norm_vec(X, T)
+    Xn, Tn = zscore(X, norm[0:12], norm[12:24]), zscore(T, norm[24:36], norm[36:48])
+    theta = scenes.mlp_init(seed).astype(np.float64)
+    m, v = np.zeros_like(theta), np.zeros_like(theta)
+    rows = (scenes.splitmix64(seed, steps * batch, 77) % np.uint64(count)).astype(np.int64).reshape(steps, batch)
+    for t in range(steps):
+        g = S.grad(theta, Xn[rows[t]], Tn[rows[t]])
+        theta, m, v = S.adam_step(theta, g, m, v, t + 1, lr=lr)
+    return theta, norm
+
+
+def test_learned_substep_matches_the_oracle(torch_cuda, oracle):
+    """Mode 1 (the network P2G runs on BF16 MFMA, with its fallback checks)
+    against the FP64 oracle running the same network in place of the return
+    map (oracle/surrogate.py: substep_network), two substeps of a snow state
+    near the yield surface, so that P2G applies the network to the first
+    substep's trial gradients and the read applies it to the second's.
+    * Particles whose decision quantities (eigenvalue gaps, residuals) lie
+      within a margin of a threshold in either map are left out of the
+      per-particle check (BF16 against FP64 can decide them either way); they
+      must be fewer than a fifth.
+    * The kept particles: F and J_P within a BF16 bar, 8 x 2^-8 of the
+      largest output spread the map uses (ln(s'/s), J_P'/J_P), per entry.
+    * x, v, C of all particles within 5e-3 normwise (the BF16 stress error
+      reaches them through P2G)."""
+    from paper_2111_00699_amd import mpm
+
+    theta, norm = _oracle_trained_network()
+    theta32 = theta.astype(np.float32)
+    x = scenes.jelly_cube(0)["x"]
+    N = x.shape[1]
+    st = scenes.nontrivial_state(x, seed=21, kind="snow")
+    # elastic gradients near the yield surface: R1 diag(s) R2 with s in [0.97, 1.012]
+    from .test_oracle_pins import rot
+
+    sv = scenes.uniform(21, 3 * N, 40, 0.97, 1.012).reshape(N, 3)
+    R1 = np.stack([rot(7000 + k % 97) for k in range(N)])
+    R2 = np.stack([rot(9000 + k % 89) for k in range(N)])
+    st["F"] = np.ascontiguousarray((R1 * sv[:, None, :]) @ np.transpose(R2, (0, 2, 1))).reshape(N, 9).T.astype(np.float32)
+    st["C"] = (st["C"] * np.float32(0.2)).astype(np.float32)
+    cfg = dict(n=64, dt=1e-4, bc="separate")
+    tol = 2e-2
+    print_case("learned_substep", N=N, tol=tol)
+    sur = mpm.Surrogate()
+    sur.set(theta32, norm.astype(np.float32))
+    sim = mpm.Sim(64, 1e-4, bc="separate")
+    sim.add_particles(scenes.SNOW, st["x"], v=st["v"], C=st["C"], F=st["F"], s=st["s"])
+    sim.use_surrogate(1, sur, tol=tol, dt_ref=1e-4)
+    sim.substep(2)
+    gs = {k: t.cpu().numpy().astype(np.float64) for k, t in sim.read_particles().items()}
+    stats = sim.stats()
+    sim.close()
+    sur.close()
+    os_, used, margins = S.substep_network(cfg, scenes.SNOW, st, theta32.astype(np.float64), norm, tol, 1e-4, steps=2)
+    # margins (the smallest over both maps): the eigenvalue gaps in eigenvalue units of b = F^ F^T,
+    # where the first map's BF16 error in F (below 2e-4 on every particle) moves b by less than
+    # 5e-4; the residuals in their units, where BF16 moves them by less than 2e-3
+    near = np.any(np.abs(margins[:, :2]) < 5e-4, axis=1) | np.any(np.abs(margins[:, 2:]) < 2e-3, axis=1)
+    keep = ~near
+    print(f"[learned] used={used.mean():.3f} near={near.mean():.3f} gpu_surrogate={stats['surrogate_particles']} "
+          f"fallbacks={stats['surrogate_fallbacks']}", flush=True)
+    assert used.mean() > 0.3  # the network carries a good share of the particles
+    assert (~used).mean() > 0.02  # and the fallback is exercised too
+    assert near.mean() < 0.2
+    osd = norm[36:48]
+    bar = 8 * 2.0 ** -8 * max(osd[3:6].max(), osd[9])
+    eF = np.abs(gs["F"] - os_["F"]).max(axis=0)
+    es = np.abs(gs["s"] - os_["s"]) / os_["s"]
+    dF, ds = eF[keep].max(), es[keep].max()
+    print(f"[learned] F err quantiles 50/99/max {np.quantile(eF, 0.5):.2e} {np.quantile(eF, 0.99):.2e} {eF.max():.2e}; "
+          f"above bar: kept {(eF[keep] > bar).sum()} near {(eF[near] > bar).sum()}", flush=True)
+    errs = {k: normwise(gs[k], os_[k]) for k in ("x", "v", "C")}
+    print(f"[learned] bar={bar:.2e} dF={dF:.2e} ds={ds:.2e} " + " ".join(f"{k}={e:.2e}" for k, e in errs.items()),
+          flush=True)
+    assert dF <= bar
+    assert ds <= bar
+    for k, e in errs.items():
+        assert e <= 5e-3, (k, e)

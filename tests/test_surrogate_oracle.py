@@ -84,3 +84,79 @@ def test_targets_conserve_volume_and_vanish_inside_the_yield_surface():
     assert 0.2 < inside.mean() < 0.8
     assert np.allclose(Y[inside, 3:6], 0) and np.allclose(Y[inside, 9], 1)
     assert np.all(Y[:, 0:3] >= lo - 1e-15) and np.all(Y[:, 0:3] <= hi + 1e-15)
+
+
+# ---------------------------------------------- the map a substep applies
+def _trial_gradients(seed, count, spread=0.04):
+    """Trial gradients R1 diag(s) R2 with rotations and singular values around 1
+    (most outside the snow bounds), plus J_P."""
+    from .test_oracle_pins import rot
+
+    s = 1.0 + scenes.uniform(seed, 3 * count, 1, -spread, spread).reshape(count, 3)
+    F = np.stack([rot(seed * 1000 + 2 * k) @ np.diag(s[k]) @ rot(seed * 1000 + 2 * k + 1).T for k in range(count)])
+    Jp = scenes.uniform(seed, count, 2, 0.9, 1.05)
+    return F, Jp
+
+
+def test_network_map_with_exact_predictions_is_the_exact_map():
+    """A stand-in network that outputs the exact targets passes every residual
+    check, and the eigenvector-free rebuild U diag(s'/s) U^T F^ then equals the
+    exact (SVD) map on every particle whose eigenvalues are well separated."""
+    import oracle
+
+    F, Jp = _trial_gradients(3, 400)
+    mat = scenes.SNOW
+    exact = lambda X: S.targets(mat, X[:, 0:3], X[:, 6])
+    Fe, Jpn, used, margins = S.snow_map_network(mat, F, Jp, None, None, 5e-5, 5e-5, tol=1e-9, predict=exact)
+    assert used.mean() > 0.8  # only close eigenvalue pairs fall back
+    assert np.all(margins[used] >= 0)
+    for k in range(F.shape[0]):
+        Fo, Jo = oracle.snow_project(mat, F[k], Jp[k])
+        assert np.abs(Fe[k] - Fo).max() <= 1e-12, k
+        assert abs(Jpn[k] - Jo) <= 1e-12 * Jo
+    # the particles that fell back are exactly the close or inverted ones
+    lam = np.sort(np.linalg.eigvalsh(F @ np.transpose(F, (0, 2, 1))), axis=1)[:, ::-1]
+    q = lam.mean(axis=1)
+    p = np.sqrt(np.sum((lam - q[:, None]) ** 2, axis=1) / 6.0)
+    mu = (lam - q[:, None]) / p[:, None]
+    close = (mu[:, 0] - mu[:, 1] < S.EIG_GAP) | (mu[:, 1] - mu[:, 2] < S.EIG_GAP)
+    assert np.array_equal(~used, close)
+
+
+def test_network_map_rejects_predictions_off_the_yield_surface():
+    """Predictions shifted off the yield surface (or changing the total volume,
+    or disagreeing with their own stress) by more than tol fall back to the
+    exact map; shifted by less they are kept."""
+    F, Jp = _trial_gradients(5, 300)
+    mat = scenes.SNOW
+
+    def shifted(dln=0.0, dj=0.0, dtau=0.0):
+        def f(X):
+            Y = S.targets(mat, X[:, 0:3], X[:, 6])
+            Y[:, 3:6] += dln
+            Y[:, 9] *= np.exp(dj)
+            Y[:, 6:9] += dtau
+            return Y
+        return f
+
+    tol = 1e-3
+    base = S.snow_map_network(mat, F, Jp, None, None, 5e-5, 5e-5, tol, predict=shifted())[2]
+    for kw in (dict(dj=3e-3), dict(dtau=3e-3), dict(dln=5e-2)):
+        used = S.snow_map_network(mat, F, Jp, None, None, 5e-5, 5e-5, tol, predict=shifted(**kw))[2]
+        assert used.sum() < 0.2 * base.sum(), kw
+    used = S.snow_map_network(mat, F, Jp, None, None, 5e-5, 5e-5, tol, predict=shifted(dtau=1e-4))[2]
+    assert np.array_equal(used, base)
+
+
+def test_substep_without_accepted_predictions_is_the_exact_substep():
+    import oracle
+
+    st = scenes.nontrivial_state(scenes.jelly_cube(0)["x"], seed=5, kind="snow")
+    cfg = dict(n=64, dt=1e-4, bc="separate")
+    theta = scenes.mlp_init(4).astype(np.float64)
+    norm = np.concatenate([np.zeros(12), np.ones(12), np.zeros(12), np.ones(12)])
+    s1, used, _ = S.substep_network(cfg, scenes.SNOW, st, theta, norm, tol=1e-12, dt_ref=1e-4, steps=2)
+    ref, _, _, _ = oracle.substep(cfg, scenes.SNOW, st, steps=2)
+    assert used.sum() == 0
+    for k in "xvCFs":
+        assert np.array_equal(s1[k], ref[k]), k
