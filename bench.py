@@ -223,13 +223,19 @@ def bench_batched(args):
 
 
 FOUNTAIN_MAX = 143500
+# The fountain's ASFLIP transfer (flip ratio, beta_min, beta_max) and automatic
+# step (CFL number, largest step): the paper runs its fountain with ASFLIP
+# and automatically deduced steps but gives neither's parameters.
+ASFLIP = (0.95, 0.0, 1.0)
+AUTO_DT = (0.3, 1e-3)
 
 
 def bench_fountain(args):
     """The fountain: water emitted from the inlet once per 1/60 s frame until
-    143,500 particles, on a 128^3 grid, frames of 167 substeps.  Reports ms per
-    frame against the particle count, once with G2P fused into the next P2G
-    (the default below 1,000,000 particles) and once with G2P kept separate."""
+    143,500 particles, on a 128^3 grid.  Reports ms per frame against the
+    particle count: APIC with the fixed step (167 substeps per frame), G2P
+    fused into the next P2G (the default) and kept separate; and ASFLIP with
+    the automatic step (the paper's fountain integrator)."""
     import torch
 
     from paper_2111_00699_amd import mpm, scenes
@@ -250,39 +256,56 @@ def bench_fountain(args):
     log(f"[bench] fountain: {len(emissions)} emitting frames, {total} particles, {frames} frames of {nsub} substeps")
     stream = torch.cuda.current_stream()
     runs = {}
-    for name, flags in (("default_fused", 0), ("separate_g2p", mpm.FLAG_SEPARATE_G2P)):
+    def setup(sim, name):
+        if name == "asflip_auto_dt":  # the paper's fountain integrator and automatic steps
+            sim.set_transfer(ASFLIP[0], ASFLIP[1], ASFLIP[2])
+            sim.set_auto_dt(AUTO_DT[0], AUTO_DT[1])
+
+    for name, flags in (("default_fused", 0), ("separate_g2p", mpm.FLAG_SEPARATE_G2P), ("asflip_auto_dt", 0)):
+        auto = name == "asflip_auto_dt"
         sim = mpm.Sim(cfg["n"], cfg["dt"], bc=cfg["bc"], bc_cells=cfg["bc_cells"], gravity=cfg["gravity"],
                       capacity=2 * total + 256, flags=flags | args.flags, chunk=args.chunk)
         # warmup: one frame of a throwaway emission, then a fresh context
         sim.add_particles(scenes.WATER, emissions[0]["x"], v=emissions[0]["v"])
-        sim.substep(nsub)
+        setup(sim, name)
+        sim.frame(scenes.FRAME)
         sim.synchronize()
         sim.close()
         sim = mpm.Sim(cfg["n"], cfg["dt"], bc=cfg["bc"], bc_cells=cfg["bc_cells"], gravity=cfg["gravity"],
                       capacity=2 * total + 256, flags=flags | args.flags, chunk=args.chunk)
         torch.cuda.synchronize()
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(frames + 1)]
-        counts = []
+        counts, subs = [], []
         n = 0
+        done = 0
         w0 = time.perf_counter()
         ev[0].record(stream)
         for f in range(frames):
             if f < len(emissions):
                 sim.add_particles(scenes.WATER if f == 0 else None, emissions[f]["x"], v=emissions[f]["v"])
                 n += emissions[f]["x"].shape[1]
-            sim.substep(nsub)
+                if f == 0:
+                    setup(sim, name)
+            sim.frame(scenes.FRAME)
             ev[f + 1].record(stream)
             counts.append(n)
+            if auto:  # the frame's step count (the automatic step synchronizes every frame anyway)
+                k = sim.scene_stats()["substeps"]
+                subs.append(k - done)
+                done = k
+            else:
+                subs.append(nsub)
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
         ms = [ev[f].elapsed_time(ev[f + 1]) for f in range(frames)]
         st = sim.stats()
         sim.close()
         gpu_ms = sum(ms)
-        work = nsub * sum(counts)
+        work = sum(c * k for c, k in zip(counts, subs))
         runs[name] = {"ms_total": max(gpu_ms, wall * 1e3), "gpu_event_ms": gpu_ms, "wall_ms": wall * 1e3,
                       "value": work / (max(gpu_ms, wall * 1e3) * 1e-3), "rebuilds": st["rebuilds"],
-                      "frames": [[f + 1, counts[f], round(ms[f], 3)] for f in range(frames)]}
+                      "substeps": sum(subs),
+                      "frames": [[f + 1, counts[f], subs[f], round(ms[f], 3)] for f in range(frames)]}
         log(f"[bench] fountain {name}: {runs[name]['ms_total'] / frames:.2f} ms per frame on average")
     r = runs["default_fused"]
     out = {
@@ -299,6 +322,11 @@ def bench_fountain(args):
                    "substeps_per_frame": nsub, "fuse_below": 1000000},
         "runs": runs,
         "fused_vs_separate": runs["separate_g2p"]["ms_total"] / r["ms_total"],
+        "asflip_auto_dt": {"flip": ASFLIP[0], "beta_min": ASFLIP[1], "beta_max": ASFLIP[2], "cfl": AUTO_DT[0],
+                           "dt_max": AUTO_DT[1],
+                           "ms_per_frame": runs["asflip_auto_dt"]["ms_total"] / frames,
+                           "substeps_per_frame": runs["asflip_auto_dt"]["substeps"] / frames,
+                           "speedup_vs_fixed_step": r["ms_total"] / runs["asflip_auto_dt"]["ms_total"]},
     }
     print(json.dumps(out), flush=True)
 

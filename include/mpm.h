@@ -305,6 +305,35 @@ int mpm_profile_read(mpm_ctx* ctx, mpm_profile_data* out);
  * NULL).  Owned by the library; valid until the next call on that context. */
 const char* mpm_last_error(const mpm_ctx* ctx);
 
+/* ASFLIP transfer for `scene` (the integrator the paper's fountain uses,
+ * "Fountain" in its Results section, after Fei et al. 2021; the formulas are
+ * not in the paper, this is the library's reading of them).  With v the
+ * particle's velocity before the substep, v^ = sum w v_i' the interpolated
+ * new grid velocity, v- = sum w v~_i the interpolated grid velocity the
+ * particles transferred (v~_i = p_i / m_i, before gravity and walls):
+ *   v' = v^ + flip (v - v-)                     (flip = 1: FLIP, 0: APIC)
+ *   x' = x + dt (v^ + beta flip (v - v-))       (beta = 0: positions by PIC)
+ * with beta = beta_max unless the particle's volume is being compressed
+ * (J' < 1, J' = J det(I + dt C') for water and det(I + dt C') otherwise),
+ * where beta = beta_min.  C' stays the APIC gradient of the new grid
+ * velocity.  flip = 0 restores APIC.  Needs 0 <= flip <= 1 and 0 <= beta_min
+ * <= beta_max <= 1 (else MPM_EINVAL).  The first call with flip > 0
+ * allocates one float4 per node of the context's block grids; scenes with
+ * flip > 0 run G2P as its own launch (no G2P2G fusion).                    */
+int mpm_set_transfer(mpm_ctx* ctx, int32_t scene, float flip, float beta_min, float beta_max);
+
+/* Automatic time step (single-scene contexts; the paper's fountain and snow
+ * runs deduce their steps automatically, after Fang et al. 2018; this is the
+ * library's reading): at the start of every mpm_frame the step becomes
+ *   dt = min(dt_max, cfl dx / (max_p |v_p| + |g| frame_dt + c))
+ * with c the material's pressure-wave speed (sqrt(bulk/rho) for water,
+ * sqrt((lambda + 2 mu)/rho) otherwise), then frame_dt / ceil(frame_dt / dt),
+ * so the frame's substeps tile it.  The largest speed is read back from the
+ * device (one synchronization per frame).  cfl = 0 turns it off (the step
+ * stays where it is); otherwise 0 < cfl <= 1 and dt_max > 0.  mpm_substep
+ * keeps the current step.  MPM_EINVAL for a batched context.               */
+int mpm_set_auto_dt(mpm_ctx* ctx, float cfl, float dt_max);
+
 /* ------------------------------------------------ learned snow surrogate
  * An MLP 12 -> 64 -> 64 -> 12 (tanh hidden layers, linear output) standing
  * in for the snow return map and stress in principal space.  Inputs, for

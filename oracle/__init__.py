@@ -75,6 +75,8 @@ def lib():
             "om_g2p_trial": (L, [ct.POINTER(_Cfg), ct.POINTER(_Mat), L, D, D, D, D, D, D]),
             "om_substep": (L, [ct.POINTER(_Cfg), ct.POINTER(_Mat), L, D, D, D, D, D, D, D]),
             "om_substep_omp": (L, [ct.POINTER(_Cfg), ct.POINTER(_Mat), L, D, D, D, D, D, D, D, ct.c_int]),
+            "om_substep_asflip": (L, [ct.POINTER(_Cfg), ct.POINTER(_Mat), L, D, D, D, D, D, D, D, ct.c_double,
+                                      ct.c_double, ct.c_double]),
             "om_keys": (L, [L, F32, ct.c_int, U32, I32]),
             "om_stable_sort": (None, [L, U32, I32, U32]),
             "om_gblocks": (L, [L, U32, U32, I32, I32]),
@@ -220,6 +222,45 @@ def g2p(cfg: dict, mat: dict, st: dict, gv: np.ndarray):
     bad = lib().om_g2p(ct.byref(c), ct.byref(m), N, *(_p(s[k], ct.c_double) for k in "xvCFs"),
                        _p(gv, ct.c_double))
     return s, bad
+
+
+def substep_asflip(cfg: dict, mat: dict, st: dict, flip: float, beta_min: float, beta_max: float,
+                   steps: int = 1):
+    """`steps` substeps with the ASFLIP transfer (om_substep_asflip).  Returns
+    (state, grid mass, grid velocity of the last substep, skipped count)."""
+    s = _state(st)
+    n = int(cfg["n"])
+    NN = num_nodes(n)
+    gm, gv = np.zeros(NN), np.zeros((3, NN))
+    c, m = _cfg(cfg), _mat(mat)
+    N = s["x"].shape[1]
+    bad = 0
+    for _ in range(steps):
+        bad += lib().om_substep_asflip(ct.byref(c), ct.byref(m), N, *(_p(s[k], ct.c_double) for k in "xvCFs"),
+                                       _p(gm, ct.c_double), _p(gv, ct.c_double), float(flip), float(beta_min),
+                                       float(beta_max))
+    return s, gm, gv, bad
+
+
+def frame_time_step(mat: dict, n: int, vmax: float, gravity, cfl: float, dt_max: float, frame: float):
+    """The automatic step of a frame (a reading of the paper's automatically
+    deduced steps): dt = min(dt_max, cfl dx / (vmax + |g| frame + c)) with c
+    the pressure-wave speed (sqrt(bulk/rho) for water, sqrt((lambda + 2 mu)/rho)
+    otherwise), then the frame cut into the fewest whole substeps no longer
+    than that.  Returns (substeps, dt)."""
+    import math
+
+    kind = mat["kind"] if isinstance(mat["kind"], str) else {v: k for k, v in KIND.items()}[mat["kind"]]
+    if kind == "water":
+        c = math.sqrt(mat["bulk"] / mat["rho"])
+    else:
+        mu = mat["E"] / (2 * (1 + mat["nu"]))
+        la = mat["E"] * mat["nu"] / ((1 + mat["nu"]) * (1 - 2 * mat["nu"]))
+        c = math.sqrt((la + 2 * mu) / mat["rho"])
+    g = math.sqrt(sum(float(a) ** 2 for a in gravity))
+    dt = min(dt_max, cfl / n / (vmax + g * frame + c))
+    ns = max(1, math.ceil(frame / dt - 1e-9))
+    return ns, frame / ns
 
 
 def g2p_trial(cfg: dict, mat: dict, st: dict, gv: np.ndarray):

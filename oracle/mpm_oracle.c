@@ -424,8 +424,13 @@ void om_grid_update(const om_config* cfg, const double* gm, double* gv) {
  * then the material update with the new C'.  In-place on x, v, C, F, s.
  * One particle; returns 1 (and leaves it unchanged) if its stencil leaves
  * the grid.                                                                 */
+typedef struct {     /* the ASFLIP transfer (flip = 0: APIC)                          */
+    const double* vt; /* [3][(n+1)^3] grid velocity the particles transferred, p_i/m_i  */
+    double flip, bmin, bmax;
+} om_flip;
+
 static int g2p_particle_map(const om_config* cfg, const om_material* mat, long N, long p, double* x, double* v,
-                            double* C, double* F, double* s, const double* gv, int apply_map) {
+                            double* C, double* F, double* s, const double* gv, int apply_map, const om_flip* fl) {
     const int n = cfg->n;
     const double dx = 1.0 / n, dt = cfg->dt;
     const long NN = (long)(n + 1) * (n + 1) * (n + 1);
@@ -438,7 +443,7 @@ static int g2p_particle_map(const om_config* cfg, const om_material* mat, long N
         if (base[a] < 0 || base[a] + 2 > n) out = 1;
     }
     if (out) return 1;
-    double vn[3] = {0, 0, 0}, Cn[9] = {0};
+    double vn[3] = {0, 0, 0}, Cn[9] = {0}, vbar[3] = {0, 0, 0};
     for (int o0 = 0; o0 < 3; ++o0)
         for (int o1 = 0; o1 < 3; ++o1)
             for (int o2 = 0; o2 < 3; ++o2) {
@@ -449,15 +454,29 @@ static int g2p_particle_map(const om_config* cfg, const om_material* mat, long N
                     double vi = gv[a * NN + id];
                     vn[a] += wt * vi;
                     for (int b = 0; b < 3; ++b) Cn[a * 3 + b] += 4.0 / (dx * dx) * wt * vi * d[b];
+                    if (fl && fl->flip > 0.0) vbar[a] += wt * fl->vt[a * NN + id];
                 }
             }
-    for (int a = 0; a < 3; ++a) {
-        v[a * N + p] = vn[a];
-        x[a * N + p] += dt * vn[a];
-    }
-    for (int c = 0; c < 9; ++c) C[c * N + p] = Cn[c];
     double G[9]; /* I + dt C' */
     for (int c = 0; c < 9; ++c) G[c] = dt * Cn[c] + (c % 4 == 0 ? 1.0 : 0.0);
+    if (fl && fl->flip > 0.0) {
+        /* ASFLIP: v' = v^ + flip (v - v-), x' = x + dt (v^ + beta flip (v - v-)), beta = bmin
+         * where the particle's volume is being compressed (J' < 1), bmax elsewhere */
+        double J = mat_det(G);
+        if (mat->kind == OM_WATER) J *= s[p];
+        double beta = J < 1.0 ? fl->bmin : fl->bmax;
+        for (int a = 0; a < 3; ++a) {
+            double corr = v[a * N + p] - vbar[a];
+            x[a * N + p] += dt * (vn[a] + beta * fl->flip * corr);
+            v[a * N + p] = vn[a] + fl->flip * corr;
+        }
+    } else {
+        for (int a = 0; a < 3; ++a) {
+            v[a * N + p] = vn[a];
+            x[a * N + p] += dt * vn[a];
+        }
+    }
+    for (int c = 0; c < 9; ++c) C[c * N + p] = Cn[c];
     if (mat->kind == OM_WATER) {
         s[p] *= mat_det(G);
     } else {
@@ -484,7 +503,7 @@ static int g2p_particle_map(const om_config* cfg, const om_material* mat, long N
 
 static int g2p_particle(const om_config* cfg, const om_material* mat, long N, long p, double* x, double* v,
                         double* C, double* F, double* s, const double* gv) {
-    return g2p_particle_map(cfg, mat, N, p, x, v, C, F, s, gv, 1);
+    return g2p_particle_map(cfg, mat, N, p, x, v, C, F, s, gv, 1, NULL);
 }
 
 long om_g2p(const om_config* cfg, const om_material* mat, long N, double* x, double* v, double* C, double* F,
@@ -499,7 +518,7 @@ long om_g2p(const om_config* cfg, const om_material* mat, long N, double* x, dou
 long om_g2p_trial(const om_config* cfg, const om_material* mat, long N, double* x, double* v, double* C, double* F,
                   double* s, const double* gv) {
     long bad = 0;
-    for (long p = 0; p < N; ++p) bad += g2p_particle_map(cfg, mat, N, p, x, v, C, F, s, gv, 0);
+    for (long p = 0; p < N; ++p) bad += g2p_particle_map(cfg, mat, N, p, x, v, C, F, s, gv, 0, NULL);
     return bad;
 }
 
@@ -510,6 +529,31 @@ long om_substep(const om_config* cfg, const om_material* mat, long N, double* x,
     long bad = om_p2g(cfg, mat, N, x, v, C, F, s, gm, gv);
     om_grid_update(cfg, gm, gv);
     bad += om_g2p(cfg, mat, N, x, v, C, F, s, gv);
+    return bad;
+}
+
+/* ------------------------------------------------------------- ASFLIP
+ * One substep with the ASFLIP transfer, the integrator the paper's fountain
+ * uses (Results, "Fountain"; Fei et al. 2021).  The paper names it without
+ * its formulas; the reading here: with v the particle's velocity before the
+ * substep, v^ the interpolated new grid velocity and v- the interpolated grid
+ * velocity the particles transferred (p_i / m_i, before gravity and walls),
+ *   v' = v^ + flip (v - v-),   x' = x + dt (v^ + beta flip (v - v-)),
+ * beta = bmin where the particle's volume is being compressed (J' < 1: J
+ * det(I + dt C') for water, det(I + dt C') otherwise) and bmax elsewhere; C'
+ * and the material update are APIC's.  flip = 0 is the APIC substep.        */
+long om_substep_asflip(const om_config* cfg, const om_material* mat, long N, double* x, double* v, double* C,
+                       double* F, double* s, double* gm, double* gv, double flip, double bmin, double bmax) {
+    const int n = cfg->n;
+    const long NN = (long)(n + 1) * (n + 1) * (n + 1);
+    long bad = om_p2g(cfg, mat, N, x, v, C, F, s, gm, gv);
+    double* vt = malloc(sizeof(double) * 3 * NN);
+    for (long i = 0; i < NN; ++i)
+        for (int a = 0; a < 3; ++a) vt[a * NN + i] = gm[i] > 0.0 ? gv[a * NN + i] / gm[i] : 0.0;
+    om_grid_update(cfg, gm, gv);
+    om_flip fl = {vt, flip, bmin, bmax};
+    for (long p = 0; p < N; ++p) bad += g2p_particle_map(cfg, mat, N, p, x, v, C, F, s, gv, 1, &fl);
+    free(vt);
     return bad;
 }
 

@@ -26,6 +26,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -105,6 +106,10 @@ struct mpm_ctx {
     const float* sur_norm = nullptr;
     float sur_tol = 1e-3f, sur_dt_ref = 1.0f;
     int sur_any = 0;
+    // ASFLIP (mpm_set_transfer) and the automatic frame time step (mpm_set_auto_dt)
+    bool any_flip = false;
+    float auto_cfl = 0.0f, auto_dt_max = 0.0f;
+    float* speed_dev = nullptr;  // one word: the largest particle speed, by mpm_frame with auto_cfl > 0
 
     // profiling
     uint32_t prof_mask = 0;
@@ -469,9 +474,20 @@ int check_error_word(mpm_ctx* c) {
 // the default at every size.
 bool fusion_allowed(const mpm_ctx* c) {
     const bool wanted = (c->cfg.flags & MPM_FLAG_FUSED_G2P) || !(c->cfg.flags & MPM_FLAG_SEPARATE_G2P);
-    return wanted && !c->sur_any &&
+    return wanted && !c->sur_any && !c->any_flip &&
            !(c->cfg.flags & (MPM_FLAG_P2G_GLOBAL_ATOMICS | MPM_FLAG_REBUILD_EVERY_STEP |
                              MPM_FLAG_G2P_GLOBAL_GATHER | MPM_FLAG_FRAME_GRAPHS));
+}
+
+// P2G's launch for the current particle count: workgroups for every chunk at
+// half fill (2 N / chunk), at most the machine-filling count of query_launch,
+// a multiple of 8 (one share per XCD).  Small scenes then launch no
+// workgroups that would find no chunk.
+Launch p2g_launch(const mpm_ctx* c) {
+    Launch L = c->L;
+    const int64_t want = (2 * c->N / std::max(c->cfg.chunk, 64) + 8 + 7) / 8 * 8;
+    if (want < L.p2g_grid) L.p2g_grid = (int)want;
+    return L;
 }
 
 // Run the G2P that the last substep left to its successor (see g2p_due_act).
@@ -512,7 +528,7 @@ int substep_one(mpm_ctx* c, int act) {
     const int parity = (int)(c->parity_ctr & 1);
     const Scenes T = tables(c);
     if ((r = prof_begin(c, 1, &slot))) return r;
-    enqueue_p2g(c->stream, c->L, T, c->S[c->cur], c->cap, c->B.chunks, c->ctl, c->G, c->B.brick_state,
+    enqueue_p2g(c->stream, p2g_launch(c), T, c->S[c->cur], c->cap, c->B.chunks, c->ctl, c->G, c->B.brick_state,
                 fused ? 1 : c->pending, parity, (c->cfg.flags & MPM_FLAG_P2G_GLOBAL_ATOMICS) ? 1 : 0, c->nbricks,
                 c->cfg.chunk, act, fused ? 1 : 0, c->ring_dev + rs, fb_limit(c));
     if ((r = prof_end(c, slot))) return r;
@@ -549,7 +565,7 @@ int graph_frame(mpm_ctx* c, float frame_dt, const std::vector<int>& ns) {
         for (int k = 0; k < ns[0]; ++k) {
             const int act = active_ranks(ns, k);
             const int parity = k & 1;  // the rebuild cleared both overflow slots
-            enqueue_p2g(c->stream, c->L, T, c->S[other], c->cap, c->B.chunks, c->ctl, c->G, c->B.brick_state, 1,
+            enqueue_p2g(c->stream, p2g_launch(c), T, c->S[other], c->cap, c->B.chunks, c->ctl, c->G, c->B.brick_state, 1,
                         parity, (c->cfg.flags & MPM_FLAG_P2G_GLOBAL_ATOMICS) ? 1 : 0, c->nbricks, c->cfg.chunk,
                         act, 0, nullptr, 0);
             enqueue_grid(c->stream, c->L, T, c->B, c->ctl, c->G, parity, c->nbricks, act);
@@ -579,8 +595,42 @@ int graph_frame(mpm_ctx* c, float frame_dt, const std::vector<int>& ns) {
     return MPM_OK;
 }
 
+// The automatic time step of a single-scene context for the frame about to
+// run: dt = min(dt_max, cfl dx / (max |v_p| + |g| T + c)) with c the speed of
+// the material's pressure wave, then the smallest whole number of substeps
+// that covers the frame (dt = T / n_s).  The largest particle speed is read
+// back from the device (the frame starts from a synchronized stream).
+int update_auto_dt(mpm_ctx* c, float frame_dt) {
+    if (int r = bring_up_to_date(c)) return r;
+    HIP_OK(c, hipMemsetAsync(c->speed_dev, 0, sizeof(float), c->stream));
+    enqueue_max_speed(c->stream, c->S[c->cur], c->cap, (int)c->N, c->speed_dev);
+    float vmax = 0.0f;
+    HIP_OK(c, hipMemcpyAsync(&vmax, c->speed_dev, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    SceneHost& sh = c->sh[0];
+    const mpm_material& m = sh.mat;
+    const double mu = m.E / (2.0 * (1.0 + m.nu)), la = m.E * m.nu / ((1.0 + m.nu) * (1.0 - 2.0 * m.nu));
+    const double wave = m.kind == MPM_WATER ? std::sqrt((double)m.bulk / m.rho) : std::sqrt((la + 2.0 * mu) / m.rho);
+    const double g = std::sqrt((double)sh.desc.gravity[0] * sh.desc.gravity[0] +
+                               (double)sh.desc.gravity[1] * sh.desc.gravity[1] +
+                               (double)sh.desc.gravity[2] * sh.desc.gravity[2]);
+    const double dt = std::min((double)c->auto_dt_max,
+                               (double)c->auto_cfl / sh.desc.n / ((double)vmax + g * frame_dt + wave));
+    const int n = (int)std::ceil((double)frame_dt / dt - 1e-9);
+    const float dt_new = (float)((double)frame_dt / (n < 1 ? 1 : n));
+    if (dt_new != sh.desc.dt) {
+        sh.desc.dt = dt_new;
+        c->table[0].P.dt = dt_new;
+        if (sh.has_mat) c->table[0].M = derive_material(sh.mat, c->table[0].P);
+        HIP_OK(c, hipMemcpyAsync(c->scene_dev, &c->table[0], sizeof(Scene), hipMemcpyHostToDevice, c->stream));
+    }
+    return MPM_OK;
+}
+
 int run_frame(mpm_ctx* c, float frame_dt) {
     if (c->N == 0) return MPM_OK;
+    if (c->auto_cfl > 0.0f)
+        if (int r = update_auto_dt(c, frame_dt)) return r;
     const std::vector<int> ns = frame_substeps(c, frame_dt);
     if ((c->cfg.flags & MPM_FLAG_FRAME_GRAPHS) && c->pending && !(c->cfg.flags & MPM_FLAG_REBUILD_EVERY_STEP)) {
         int r = poll_flags(c, c->step);  // the ring is idle across a graph frame
@@ -714,6 +764,7 @@ int mpm_create(const mpm_config* cfg, mpm_ctx** out) {
               hipMalloc(&c->G.reg_n, sizeof(int) * nb) == hipSuccess &&
               hipMalloc(&c->G.reg, sizeof(int) * REG_MAX * nb) == hipSuccess &&
               hipMalloc(&c->ctl, sizeof(int) * CTL_ALLOC_WORDS) == hipSuccess &&
+              hipMalloc(&c->speed_dev, sizeof(float)) == hipSuccess &&
               hipMalloc(&c->scene_dev, sizeof(Scene) * S) == hipSuccess &&
               hipMalloc(&c->rank_scene_dev, sizeof(int) * S) == hipSuccess &&
               hipMalloc(&c->rank_brick_dev, sizeof(int) * (S + 1)) == hipSuccess &&
@@ -769,6 +820,8 @@ int mpm_destroy(mpm_ctx* c) {
     (void)hipFree(c->G.acc);
     (void)hipFree(c->G.acc_dirty);
     (void)hipFree(c->G.vel);
+    (void)hipFree(c->G.dvel);
+    (void)hipFree(c->speed_dev);
     (void)hipFree(c->G.stamp);
     (void)hipFree(c->G.ovf[0]);
     (void)hipFree(c->G.ovf[1]);
@@ -1387,6 +1440,39 @@ int mpm_use_surrogate(mpm_ctx* c, int32_t scene, const mpm_surrogate* s, int32_t
     if (!c->sur_any) c->sur_theta = c->sur_norm = nullptr;
     if (c->sur_any && !c->sur_theta && mode == 1) return fail(c, MPM_EINVAL, "no surrogate attached");
     drop_graphs(c);  // recorded kernels carry the old choice
+    return MPM_OK;
+}
+
+int mpm_set_transfer(mpm_ctx* c, int32_t scene, float flip, float beta_min, float beta_max) {
+    if (!c) return MPM_EINVAL;
+    if (int r = scene_arg(c, scene)) return r;
+    if (!(flip >= 0.0f && flip <= 1.0f) || !(beta_min >= 0.0f && beta_min <= beta_max && beta_max <= 1.0f))
+        return fail(c, MPM_EINVAL, "need 0 <= flip <= 1 and 0 <= beta_min <= beta_max <= 1");
+    if (int r = bring_up_to_date(c)) return r;  // an outstanding fused G2P ran with the old transfer
+    if (flip > 0.0f && !c->G.dvel) {
+        const int64_t nodes = (int64_t)c->nbricks * 64;
+        HIP_OK(c, hipMalloc(&c->G.dvel, sizeof(float4) * nodes));
+        HIP_OK(c, hipMemsetAsync(c->G.dvel, 0, sizeof(float4) * nodes, c->stream));
+    }
+    Step& P = c->table[scene].P;
+    P.flip = flip;
+    P.bmin = beta_min;
+    P.bmax = beta_max;
+    HIP_OK(c, hipMemcpyAsync(c->scene_dev + scene, &c->table[scene], sizeof(Scene), hipMemcpyHostToDevice, c->stream));
+    c->any_flip = false;
+    for (int k = 0; k < c->nsc; ++k) c->any_flip = c->any_flip || c->table[k].P.flip > 0.0f;
+    drop_graphs(c);
+    return MPM_OK;
+}
+
+int mpm_set_auto_dt(mpm_ctx* c, float cfl, float dt_max) {
+    if (!c) return MPM_EINVAL;
+    if (c->nsc != 1) return fail(c, MPM_EINVAL, "the automatic time step needs a single-scene context");
+    if (!(cfl >= 0.0f && cfl <= 1.0f) || (cfl > 0.0f && !(dt_max > 0.0f)))
+        return fail(c, MPM_EINVAL, "need 0 <= cfl <= 1 and dt_max > 0");
+    c->auto_cfl = cfl;
+    c->auto_dt_max = dt_max;
+    drop_graphs(c);
     return MPM_OK;
 }
 

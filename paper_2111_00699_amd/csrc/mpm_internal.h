@@ -76,6 +76,11 @@ struct Step {
     float dx, dt;
     float g0, g1, g2;
     int bc, bc_cells;
+    // ASFLIP transfer (flip = 0: APIC): the particle velocity blends the
+    // interpolated new grid velocity with its own FLIP update by `flip`, and
+    // the position moves with a share beta of that FLIP correction (bmax
+    // where the particle's volume is not compressed, bmin elsewhere)
+    float flip, bmin, bmax;
 };
 
 // A run of at most `chunk` sorted particles: a piece of one particle block,
@@ -175,6 +180,8 @@ struct GridBuffers {
     int* acc_dirty; // [NB^3] 1 where P2G's global atomics wrote the block's accumulators this
                     // substep; the grid update reads and clears only those blocks' accumulators
     float4* vel;    // [NB^3 * 64] (vx, vy, vz, m) after the grid update
+    float4* dvel;   // [NB^3 * 64] (v - p/m, 0): the grid velocity change of the update, for ASFLIP
+                    // scenes (allocated when a scene first takes ASFLIP; NULL before)
     int* stamp;     // [NB^3] substep index of the last update of each block
     int* ovf[2];    // overflow block lists, by substep parity
     float4* stage;  // [stage_nodes] P2G tiles, (m, px, py, pz) per node; each P2G workgroup owns an
@@ -215,6 +222,7 @@ void enqueue_g2p(hipStream_t st, const Launch& L, const Scenes& T, float* S, int
                  int* ctl, const GridBuffers& G, int* host_flag, int lds_box, int parity, int fb_limit, int chunk,
                  int act, int report_zone);
 void enqueue_materialize(hipStream_t st, const Scenes& T, float* S, int64_t cap, int N);
+void enqueue_max_speed(hipStream_t st, const float* S, int64_t cap, int N, float* out);
 // The same with each snow scene's own map (exact, closed form or network), over the chunk list of the
 // last rebuild; for contexts with T.sur_any != 0.
 void enqueue_materialize_map(hipStream_t st, const Launch& L, const Scenes& T, float* S, int64_t cap,

@@ -267,17 +267,19 @@ __device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, con
         if (T.sur_theta) mlp::load_net16(net, T.sur_theta, T.sur_norm);
         __syncthreads();
     }
-    if constexpr (!GLOBAL_ONLY) {
-        for (int t = threadIdx.x; t < 4 * CT; t += NT) tq[t] = 0.0;
-        __syncthreads();
+    int begin, end, stride;
+    xcd_split(rank_limit(T, ctl, act, RE_CHUNK, CTL_NCHUNK), begin, end, stride);
+    if constexpr (!GLOBAL_ONLY) {  // (workgroup-uniform: skipped by a workgroup without chunks)
+        if (begin < end) {
+            for (int t = threadIdx.x; t < 4 * CT; t += NT) tq[t] = 0.0;
+            __syncthreads();
+        }
     }
     unsigned err = 0;
     unsigned n_sur = 0, n_fb = 0;
     // fused G2P: the free-zone request, as the G2P kernel makes it (the
     // previous substep's P2G counted its tile fallbacks in the other slot)
     bool left = FUSED && blockIdx.x == 0 && threadIdx.x == 0 && ctl[CTL_FB + (parity ^ 1)] > fb_limit;
-    int begin, end, stride;
-    xcd_split(rank_limit(T, ctl, act, RE_CHUNK, CTL_NCHUNK), begin, end, stride);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     // this workgroup's slice of the staging buffer, filled front to back
     const int slice = (int)((int64_t)stage_nodes / gridDim.x);

@@ -33,7 +33,7 @@ namespace {
 // v = p/m + dt g where m > 0 (else 0) and the wall condition; writes (v, m),
 // clears the accumulator, and stamps the block.
 __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, int* __restrict__ acc_dirty,
-                                             float4* __restrict__ vel,
+                                             float4* __restrict__ vel, float4* __restrict__ dvel,
                                              const int* __restrict__ active, int* __restrict__ ctl,
                                              const int* __restrict__ ovf, int* __restrict__ brick_state,
                                              int* __restrict__ stamp, const int* __restrict__ reg_n,
@@ -131,6 +131,14 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, int* __res
             }
         }
         vel[(int64_t)b * 64 + lane] = make_float4(v[0], v[1], v[2], a.x);
+        if (P.flip > 0.0f) {  // ASFLIP: the change from the transferred velocity p/m
+            float4 d = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (a.x > 0.0f) {
+                const float inv = __frcp_rn(a.x);
+                d = make_float4(v[0] - a.y * inv, v[1] - a.z * inv, v[2] - a.w * inv, 0.0f);
+            }
+            dvel[(int64_t)b * 64 + lane] = d;
+        }
         if (dirty) acc4[(int64_t)b * 64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (lane == 0) {
             stamp[b] = step;
@@ -158,7 +166,8 @@ template <bool LDS_BOX, int NT>
 __global__ __launch_bounds__(NT) void k_g2p(float* __restrict__ S, int64_t cap, const Chunk* __restrict__ chunks,
                                             int* __restrict__ ctl, const float4* __restrict__ vel,
                                             const int4* __restrict__ box, int* __restrict__ host_flag, int parity,
-                                            int fb_limit, int report_zone, Scenes T, int act) {
+                                            int fb_limit, int report_zone, Scenes T, int act,
+                                            const float4* __restrict__ dvel) {
     __shared__ float4 tv[LDS_BOX ? G2P_BOX : 1];
     unsigned err = 0;
     bool left = report_zone && blockIdx.x == 0 && threadIdx.x == 0 && ctl[CTL_FB + parity] > fb_limit;
@@ -210,11 +219,52 @@ __global__ __launch_bounds__(NT) void k_g2p(float* __restrict__ S, int64_t cap, 
             g2p_gather(st, tv, vels, NB, lo, e, nt, R, Q, c4, vp, Cn);
 #pragma unroll
             for (int k = 0; k < 9; ++k) S[(FC + k) * cap + p] = Cn[k];
+            // APIC: x' = x + dt v', v' the interpolated new grid velocity
+            float xv[3] = {vp[0], vp[1], vp[2]};
+            if (P.flip > 0.0f) {
+                // ASFLIP: the particle's FLIP velocity v + sum w (v_i' - v~_i) (its own
+                // velocity plus the interpolated grid change), blended in by `flip`; the
+                // position takes a share beta of the FLIP correction, bmax unless the
+                // particle's volume is being compressed (J' < 1; J' = J det(I + dt C') for
+                // water, det(I + dt C') otherwise)
+                const float4* dv = dvel + (int64_t)sc.brick_base * BLOCK_NODES;
+                int xo[3], yo[3], zo[3];
+                axis_offsets(st.base[0], 1, 0, xo);
+                axis_offsets(st.base[1], NB, 2, yo);
+                axis_offsets(st.base[2], NB * NB, 4, zo);
+                float ds[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+                for (int o2 = 0; o2 < 3; ++o2)
+#pragma unroll
+                    for (int o1 = 0; o1 < 3; ++o1) {
+                        const float wyz = st.w[1][o1] * st.w[2][o2];
+#pragma unroll
+                        for (int o0 = 0; o0 < 3; ++o0) {
+                            const float4 d = dv[xo[o0] + yo[o1] + zo[o2]];
+                            const float w = wyz * st.w[0][o0];
+                            ds[0] += w * d.x;
+                            ds[1] += w * d.y;
+                            ds[2] += w * d.z;
+                        }
+                    }
+                float G[9];
+#pragma unroll
+                for (int k = 0; k < 9; ++k) G[k] = P.dt * Cn[k] + ((k % 4 == 0) ? 1.0f : 0.0f);
+                float J = det3(G);
+                if (sc.M.kind == MPM_WATER) J *= S[FS * cap + p];
+                const float beta = J < 1.0f ? P.bmin : P.bmax;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const float corr = S[(FV + a) * cap + p] + ds[a] - vp[a];  // v_FLIP - v_PIC
+                    xv[a] = vp[a] + beta * P.flip * corr;
+                    vp[a] += P.flip * corr;
+                }
+            }
             bool fin = true;
             float xn[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                xn[a] = x[a] + P.dt * vp[a];
+                xn[a] = x[a] + P.dt * xv[a];
                 S[(FV + a) * cap + p] = vp[a];
                 S[(FX + a) * cap + p] = xn[a];
                 fin = fin && (fabsf(xn[a]) < 1e30f) && (fabsf(vp[a]) < 1e30f);
@@ -387,7 +437,7 @@ void query_launch(Launch& L, int chunk) {
 
 void enqueue_grid(hipStream_t st, const Launch& L, const Scenes& T, const BinBuffers& B, int* ctl, GridBuffers& G,
                   int parity, int nbricks, int act) {
-    hipLaunchKernelGGL(k_grid, dim3(L.grid_grid), dim3(WG), 0, st, G.acc, G.acc_dirty, G.vel, B.active, ctl,
+    hipLaunchKernelGGL(k_grid, dim3(L.grid_grid), dim3(WG), 0, st, G.acc, G.acc_dirty, G.vel, G.dvel, B.active, ctl,
                        G.ovf[parity],
                        B.brick_state, G.stamp, G.reg_n, G.reg, G.stage, G.box, parity, nbricks, T, act);
 }
@@ -397,7 +447,7 @@ void enqueue_g2p(hipStream_t st, const Launch& L, const Scenes& T, float* S, int
                  int act, int report_zone) {
 #define MPM_LAUNCH_G2P(LB, NT)                                                                                    \
     hipLaunchKernelGGL((k_g2p<LB, NT>), dim3(L.g2p_grid), dim3(NT), 0, st, S, cap, chunks, ctl, G.vel, G.box, \
-                       host_flag, parity, fb_limit, report_zone, T, act)
+                       host_flag, parity, fb_limit, report_zone, T, act, G.dvel)
     const int nt = chunk_threads(chunk);
     if (lds_box) {
         if (nt == 128) MPM_LAUNCH_G2P(true, 128); else if (nt == 256) MPM_LAUNCH_G2P(true, 256); else MPM_LAUNCH_G2P(true, 512);
@@ -405,6 +455,26 @@ void enqueue_g2p(hipStream_t st, const Launch& L, const Scenes& T, float* S, int
         if (nt == 128) MPM_LAUNCH_G2P(false, 128); else if (nt == 256) MPM_LAUNCH_G2P(false, 256); else MPM_LAUNCH_G2P(false, 512);
     }
 #undef MPM_LAUNCH_G2P
+}
+
+// The largest particle speed |v| into *out (zeroed by the caller): a wave
+// maximum, then one atomic per wave on the float's bits (non-negative floats
+// order like their bit patterns).
+__global__ __launch_bounds__(WG) void k_max_speed(const float* __restrict__ S, int64_t cap, int N,
+                                                  float* __restrict__ out) {
+    float m = 0.0f;
+    for (int p = blockIdx.x * WG + threadIdx.x; p < N; p += gridDim.x * WG) {
+        const float a = S[FV * cap + p], b = S[(FV + 1) * cap + p], c = S[(FV + 2) * cap + p];
+        m = fmaxf(m, sqrtf(a * a + b * b + c * c));
+    }
+    m = wave_maxf(m);
+    if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<int*>(out), __float_as_int(m));
+}
+
+void enqueue_max_speed(hipStream_t st, const float* S, int64_t cap, int N, float* out) {
+    if (N <= 0) return;
+    const int grid = cdiv(N, WG) < 1024 ? cdiv(N, WG) : 1024;
+    hipLaunchKernelGGL(k_max_speed, dim3(grid), dim3(WG), 0, st, S, cap, N, out);
 }
 
 void enqueue_materialize(hipStream_t st, const Scenes& T, float* S, int64_t cap, int N) {

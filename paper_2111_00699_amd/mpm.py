@@ -108,6 +108,8 @@ SIGNATURES = {
                                                P]),
     "mpm_surrogate_sample": (ct.c_int, [P, ct.c_int32, ct.c_float, ct.c_int64, P, P, ct.POINTER(ct.c_int64)]),
     "mpm_use_surrogate": (ct.c_int, [P, ct.c_int32, P, ct.c_int32, ct.c_float, ct.c_float]),
+    "mpm_set_transfer": (ct.c_int, [P, ct.c_int32, ct.c_float, ct.c_float, ct.c_float]),
+    "mpm_set_auto_dt": (ct.c_int, [P, ct.c_float, ct.c_float]),
 }
 
 _lib = None
@@ -283,6 +285,14 @@ class Sim:
         h = surrogate.h if surrogate is not None else None
         self._sur = surrogate  # keep it alive while the context uses it
         self._check(self.lib.mpm_use_surrogate(self.h, scene, h, int(mode), float(tol), float(dt_ref)))
+
+    def set_transfer(self, flip: float, beta_min: float = 0.0, beta_max: float = 1.0, scene: int = 0):
+        """ASFLIP with flip ratio `flip` and position-correction shares (0 restores APIC)."""
+        self._check(self.lib.mpm_set_transfer(self.h, scene, float(flip), float(beta_min), float(beta_max)))
+
+    def set_auto_dt(self, cfl: float, dt_max: float):
+        """Per-frame automatic time step (0 turns it off)."""
+        self._check(self.lib.mpm_set_auto_dt(self.h, float(cfl), float(dt_max)))
 
     def profile(self, mask: int):
         self._check(self.lib.mpm_profile(self.h, int(mask)))
