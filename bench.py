@@ -417,79 +417,232 @@ ABLATIONS = (  # (name, library flags, chunk size); the baseline first
     ("g2p_global_gather", 0x10, 0),    # G2P gathers from the dense grid, no LDS node box
     ("g2p_always_fused", 0x40, 0),     # G2P inside the next P2G at any size
     ("g2p_always_separate", 0x80, 0),  # G2P as its own launch at any size
+    ("separate_walls", 0x100, 0),      # the wall condition as a launch of its own
+    ("separate_clear", 0x200, 0),      # the accumulator clearing as a launch of its own
+    ("alloc_exact", 0x400, 0),         # buffers grown to exactly what is needed (the fountain emits)
     ("frame_graphs", 0x20, 0),         # frames replayed as HIP graphs
     ("chunk_128", 0, 128),
     ("chunk_512", 0, 512),
 )
+# Library builds measured as ablations (each in a process of its own):
+# IEEE arithmetic instead of fast math, the grouped particle layout instead
+# of one array per field, and P2G's stencil weights parked in LDS.
+ABLATION_LIBRARIES = ("precise", "aosoa", "lds_weights")
 
 
-def bench_ablations(args):
-    """The paper's single-GPU ablations, on this library: each design choice
-    switched off by a flag (or a chunk size), ms per frame and the extra cost
-    against the default build.  Scenes: Sand Blocks (4 boxes of 12^3 and of
-    23^3 cells at 8 ppc, 55,296 and 389,344 particles, Drucker-Prager sand)
-    in a 128^3 grid with slip walls, frames of 1/48 s in 36 substeps as in
-    the paper, timed from the second frame; and the snow scene (1.28M
-    particles, 1/60 s frames of 334 substeps)."""
+def ablation_cases():
+    from paper_2111_00699_amd import scenes
+
+    snow = scenes.snow_config()
+    sand = scenes.sand_config()
+    fountain = scenes.fountain_config()
+    cases = []
+    for l, frames in ((12, 10), (23, 10)):
+        x = scenes.sand_blocks(l=l, boxes=4, n=128)["x"]
+        cases.append((f"sand_blocks_4x{l}^3", {"x": x}, scenes.SAND,
+                      dict(n=sand["n"], dt=sand["dt"], bc=sand["bc"], bc_cells=sand["bc_cells"],
+                           gravity=sand["gravity"]), frames, sand["frame"]))
+    cases.append(("snow", {"x": scenes.snow_spheres(1)["x"]}, scenes.SNOW,
+                  dict(n=snow["n"], dt=snow["dt"], bc=snow["bc"], bc_cells=snow["bc_cells"],
+                       gravity=snow["gravity"]), 2, scenes.FRAME))
+    # the fountain emits every frame: frames 1-24 (emission until 143,500 particles)
+    cases.append(("fountain", {"emit": 24}, scenes.WATER,
+                  dict(n=fountain["n"], dt=fountain["dt"], bc=fountain["bc"], bc_cells=fountain["bc_cells"],
+                       gravity=fountain["gravity"]), 24, scenes.FRAME))
+    return cases
+
+
+def run_ablation_case(case, flags, chunk, stream):
+    """ms per frame of one ablation case with the given flags and chunk size."""
+    import torch
+
+    from paper_2111_00699_amd import mpm, scenes
+
+    name, data, mat, cfg, frames, frame = case
+    emit = data.get("emit", 0)
+    N = data["x"].shape[1] if "x" in data else FOUNTAIN_MAX
+    sim = mpm.Sim(cfg["n"], cfg["dt"], bc=cfg["bc"], bc_cells=cfg["bc_cells"], gravity=cfg["gravity"],
+                  capacity=(2 * N + 256) if not emit else 256, flags=flags, chunk=chunk, stream=stream)
+    total = 0
+    if emit:  # warm the kernels up on a throwaway context
+        e = scenes.fountain_emission(0)
+        warm = mpm.Sim(cfg["n"], cfg["dt"], bc=cfg["bc"], bc_cells=cfg["bc_cells"], gravity=cfg["gravity"],
+                       flags=flags, chunk=chunk, stream=stream)
+        warm.add_particles(mat, e["x"], v=e["v"])
+        warm.frame(frame)
+        warm.synchronize()
+        warm.close()
+    else:
+        sim.add_particles(mat, data["x"])
+        sim.frame(frame)  # warmup
+    sim.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    e0.record(stream)
+    for f in range(frames):
+        if emit and f < emit and total < FOUNTAIN_MAX:
+            e = scenes.fountain_emission(f)
+            k = min(e["x"].shape[1], FOUNTAIN_MAX - total)
+            sim.add_particles(mat if f == 0 else None, np.ascontiguousarray(e["x"][:, :k]),
+                              v=np.ascontiguousarray(e["v"][:, :k]))
+            total += k
+        sim.frame(frame)
+    e1.record(stream)
+    stream.synchronize()
+    ms = max(e0.elapsed_time(e1), (time.perf_counter() - w0) * 1e3) / frames
+    st = sim.stats()
+    sim.close()
+    return {"ms_per_frame": round(ms, 3), "rebuilds": st["rebuilds"], "particles": N}
+
+
+def bench_ablation_rows(args):
+    """(in a process whose MPM_LIBRARY names a library build) the baseline
+    configuration of every ablation case, one JSON line."""
+    import torch
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    out = {}
+    with torch.cuda.stream(stream):
+        for case in ablation_cases():
+            out[case[0]] = run_ablation_case(case, 0, 0, stream)
+            log(f"[bench] ablation rows {os.environ.get('MPM_LIBRARY')} {case[0]}: {out[case[0]]['ms_per_frame']} ms")
+    print(json.dumps(out), flush=True)
+
+
+def fast_math_stress_error():
+    """The paper's fast-math experiment on Sand Blocks (4 boxes of 46^3
+    cells, 3,114,752 particles): one 1/48 s frame from the same initial state
+    with the fast-math build and with the IEEE build, each in a process of its
+    own, ten 1/48 s frames from the same initial state (the boxes land in
+    frames 7-8); the Kirchhoff stress of every particle's state after them
+    (FP64 Hencky of its deformation gradient, numpy's SVD) compared between
+    the two builds."""
+    import subprocess
+    import tempfile
+
+    from paper_2111_00699_amd import scenes
+
+    d = tempfile.mkdtemp(prefix="mpm_fastmath_")
+    res = {}
+    for lib in ("fast", "precise"):
+        env = dict(os.environ, MPM_LIBRARY=lib)
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--workload", "sand-frame-state",
+                            "--out", os.path.join(d, lib + ".npz")], env=env, capture_output=True, text=True,
+                           timeout=600)
+        if r.returncode != 0:
+            raise RuntimeError(f"sand frame with the {lib} build failed: {r.stderr[-2000:]}")
+        res[lib] = json.loads(r.stdout.strip().splitlines()[-1])
+    taus = {}
+    mat = scenes.SAND
+    mu = mat["E"] / (2 * (1 + mat["nu"]))
+    la = mat["E"] * mat["nu"] / ((1 + mat["nu"]) * (1 - 2 * mat["nu"]))
+    for lib in ("fast", "precise"):
+        F = np.load(os.path.join(d, lib + ".npz"))["F"].astype(np.float64)
+        N = F.shape[1]
+        U, sig, _ = np.linalg.svd(F.T.reshape(N, 3, 3))
+        eps = np.log(np.maximum(np.abs(sig), 1e-6))
+        diag = 2 * mu * eps + la * eps.sum(axis=1, keepdims=True)
+        taus[lib] = np.einsum("nik,nk,njk->nij", U, diag, U)
+        os.remove(os.path.join(d, lib + ".npz"))
+    os.rmdir(d)
+    dt = np.abs(taus["fast"] - taus["precise"])
+    return {"particles": int(N), "frames": 10, "max_abs_pa": float(dt.max()), "mean_abs_pa": float(dt.mean()),
+            "p99_abs_pa": float(np.quantile(dt.max(axis=(1, 2)), 0.99)),
+            "max_abs_dyne_per_cm2": float(dt.max() * 10.0), "max_tau_pa": float(np.abs(taus["precise"]).max()),
+            "relative_to_max_tau": float(dt.max() / np.abs(taus["precise"]).max()),
+            "ms_per_frame": {k: v["ms_per_frame"] for k, v in res.items()}}
+
+
+def bench_sand_frame_state(args):
+    """(child of fast_math_stress_error) ten 1/48 s frames of Sand Blocks
+    4 x 46^3 (the boxes land in frames 7-8), the tenth timed; saves F of
+    every particle."""
     import torch
 
     from paper_2111_00699_amd import mpm, scenes
 
     torch.cuda.set_device(0)
+    x = scenes.sand_blocks(l=46, boxes=4, n=128)["x"]
+    c = scenes.sand_config()
+    N = x.shape[1]
+    sim = mpm.Sim(c["n"], c["dt"], bc=c["bc"], bc_cells=c["bc_cells"], gravity=c["gravity"], capacity=2 * N + 256)
+    sim.add_particles(scenes.SAND, x)
+    for _ in range(9):
+        sim.frame(c["frame"])
+    sim.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sim.frame(c["frame"])
+    e1.record()
+    torch.cuda.synchronize()
+    F = sim.read_particles()["F"].cpu().numpy()
+    sim.close()
+    np.savez(args.out, F=F)
+    print(json.dumps({"ms_per_frame": e0.elapsed_time(e1), "library": os.path.basename(mpm.LIB_PATH)}), flush=True)
+
+
+def bench_ablations(args):
+    """The paper's single-GPU ablations, on this library: each design choice
+    switched off by a flag, a chunk size or a library build, ms per frame and
+    the extra cost against the default.  Scenes: Sand Blocks (4 boxes of
+    12^3 and of 23^3 cells at 8 ppc, 55,296 and 389,344 particles,
+    Drucker-Prager sand) in a 128^3 grid with slip walls, frames of 1/48 s in
+    36 substeps as in the paper, timed from the second frame; the snow scene
+    (1.28M particles, 1/60 s frames of 334 substeps); and the fountain's
+    first 24 frames (water emitted every frame).  Library builds run in
+    processes of their own; the fast-math row also gives the Kirchhoff stress
+    difference of the two builds after a Sand Blocks frame (3.1M particles),
+    the paper's fast-math error experiment."""
+    import subprocess
+
+    import torch
+
+    torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
-    snow = scenes.snow_config()
-    sand = scenes.sand_config()
-    cases = []
-    for l, frames in ((12, 10), (23, 10)):
-        x = scenes.sand_blocks(l=l, boxes=4, n=128)["x"]
-        cases.append((f"sand_blocks_4x{l}^3", x, scenes.SAND, dict(n=sand["n"], dt=sand["dt"], bc=sand["bc"],
-                                                                   bc_cells=sand["bc_cells"], gravity=sand["gravity"]),
-                      frames, sand["frame"]))
-    cases.append(("snow", scenes.snow_spheres(1)["x"], scenes.SNOW,
-                  dict(n=snow["n"], dt=snow["dt"], bc=snow["bc"], bc_cells=snow["bc_cells"],
-                       gravity=snow["gravity"]), 2, scenes.FRAME))
-    table = {}
+    cases = ablation_cases()
+    table = {c[0]: {"configs": {}} for c in cases}
     with torch.cuda.stream(stream):
-        for name, x, mat, cfg, frames, frame in cases:
-            N = x.shape[1]
-            rows = {}
+        for case in cases:
             for cname, flags, chunk in ABLATIONS:
-                sim = mpm.Sim(cfg["n"], cfg["dt"], bc=cfg["bc"], bc_cells=cfg["bc_cells"], gravity=cfg["gravity"],
-                              capacity=2 * N + 256, flags=flags, chunk=chunk, stream=stream)
-                sim.add_particles(mat, x)
-                sim.frame(frame)  # warmup
-                sim.synchronize()
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                w0 = time.perf_counter()
-                e0.record(stream)
-                for _ in range(frames):
-                    sim.frame(frame)
-                e1.record(stream)
-                stream.synchronize()
-                ms = max(e0.elapsed_time(e1), (time.perf_counter() - w0) * 1e3) / frames
-                st = sim.stats()
-                sim.close()
-                rows[cname] = {"ms_per_frame": round(ms, 3), "rebuilds": st["rebuilds"]}
-                log(f"[bench] ablation {name} {cname}: {ms:.2f} ms per frame")
-            base = rows["baseline"]["ms_per_frame"]
-            for r in rows.values():
-                r["extra_cost"] = round(r["ms_per_frame"] / base - 1.0, 4)
-            table[name] = {"particles": N, "frames_timed": frames, "configs": rows}
-    snow_base = table["snow"]["configs"]["baseline"]["ms_per_frame"]
-    nsub = snow["substeps_per_frame"]
-    N = table["snow"]["particles"]
+                r = run_ablation_case(case, flags, chunk, stream)
+                table[case[0]]["configs"][cname] = r
+                table[case[0]]["particles"] = r["particles"]
+                table[case[0]]["frames_timed"] = case[4]
+                log(f"[bench] ablation {case[0]} {cname}: {r['ms_per_frame']:.2f} ms per frame")
+    for lib in ABLATION_LIBRARIES:
+        env = dict(os.environ, MPM_LIBRARY=lib)
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--workload", "ablation-rows"], env=env,
+                           capture_output=True, text=True, timeout=900)
+        if r.returncode != 0:
+            raise RuntimeError(f"ablation rows with the {lib} build failed: {r.stderr[-2000:]}")
+        rows = json.loads(r.stdout.strip().splitlines()[-1])
+        for name, row in rows.items():
+            table[name]["configs"]["library_" + lib] = row
+    for t in table.values():
+        base = t["configs"]["baseline"]["ms_per_frame"]
+        for r in t["configs"].values():
+            r["extra_cost"] = round(r["ms_per_frame"] / base - 1.0, 4)
+    log("[bench] fast-math stress error (Sand Blocks 4 x 46^3, one frame)")
+    fm = fast_math_stress_error()
+    snow = table["snow"]
+    snow_base = snow["configs"]["baseline"]["ms_per_frame"]
+    from paper_2111_00699_amd import scenes
+
+    nsub = scenes.snow_config()["substeps_per_frame"]
     out = {
         "metric": "particle-substeps/s",
-        "value": N * nsub / (snow_base * 1e-3),
+        "value": snow["particles"] * nsub / (snow_base * 1e-3),
         "unit": "particle-substeps/s",
-        "n_gpus": 1, "steps": table["snow"]["frames_timed"], "warmup": 1,
+        "n_gpus": 1, "steps": snow["frames_timed"], "warmup": 1,
         "ms_per_step": snow_base, "ms_per_frame": snow_base,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "ablations: each design choice switched off in turn on the Sand Blocks layout "
                                "(4 boxes of 12^3 and 23^3 cells, Drucker-Prager sand, 128^3, 36 substeps per 1/48 s "
-                               "frame) and the snow scene; "
+                               "frame), the snow scene and the fountain's emitting frames; "
                                "value is the snow baseline over its timed frames 2-3"},
         "ablations": table,
+        "fast_math_stress_error": fm,
     }
     print(json.dumps(out), flush=True)
 
@@ -612,18 +765,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--flags", type=int, default=0)
-    ap.add_argument("--workload", choices=("snow", "batched", "surrogate", "fountain", "ablations", "sand"),
+    ap.add_argument("--workload", choices=("snow", "batched", "surrogate", "fountain", "ablations", "sand",
+                                           "ablation-rows", "sand-frame-state"),
                     default="snow")
     ap.add_argument("--train-snapshots", type=int, default=4, help="surrogate: training snapshots per scene")
     ap.add_argument("--train-steps", type=int, default=20000, help="surrogate: Adam steps")
     ap.add_argument("--sur-tol", type=float, default=2e-3, help="surrogate: residual tolerance")
     ap.add_argument("--sur-start-frame", type=int, default=24, help="surrogate: frame the comparison starts at")
+    ap.add_argument("--out", default="", help="sand-frame-state: where the state goes")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 4 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.steps is None:
         args.steps = {"snow": 60, "fountain": 60, "batched": 10, "surrogate": 5, "ablations": 0,
-                      "sand": 60}[args.workload]
+                      "sand": 60}.get(args.workload, 0)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
@@ -651,6 +806,12 @@ def main():
         return
     if args.workload == "ablations":
         bench_ablations(args)
+        return
+    if args.workload == "ablation-rows":
+        bench_ablation_rows(args)
+        return
+    if args.workload == "sand-frame-state":
+        bench_sand_frame_state(args)
         return
     if args.workload == "sand":
         bench_sand(args)

@@ -84,6 +84,12 @@ typedef enum { MPM_BC_STICKY = 0, MPM_BC_SLIP = 1, MPM_BC_SEPARATE = 2 } mpm_bc;
 #define MPM_FLAG_FUSED_G2P 0x40u        /* run each substep's G2P inside the next substep's P2G (the
                                             default; see mpm_substep)                                  */
 #define MPM_FLAG_SEPARATE_G2P 0x80u     /* never: every substep launches its own G2P               */
+/* Ablations of the paper's "Merge Kernels" and "Reduce memory reallocation"
+ * (slower on purpose; results are unchanged):                              */
+#define MPM_FLAG_SEPARATE_WALLS 0x100u  /* the wall condition as a launch of its own after the grid update */
+#define MPM_FLAG_SEPARATE_CLEAR 0x200u  /* clearing the global accumulators as a launch of its own         */
+#define MPM_FLAG_ALLOC_EXACT 0x400u     /* mpm_add_particles grows the particle buffers to exactly what is
+                                           needed instead of 4x when half full (every emission reallocates) */
 
 #define MPM_MAX_SCENES 256
 

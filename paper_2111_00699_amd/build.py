@@ -4,10 +4,11 @@
 
 Each HIP source is compiled with hipcc for gfx950 only; packed-FP32 VALU
 instructions are disabled and float atomics are emitted as the native
-hardware instructions.  Two variants are linked: libmpm.so with the
-fast-math flags (the default) and libmpm_precise.so with IEEE division,
-square root and denormals (the fast-math ablation); the binding loads the
-second when MPM_LIBRARY=precise.
+hardware instructions.  Variants are linked for the ablations:
+libmpm.so (the default, fast-math flags), libmpm_precise.so (IEEE division,
+square root and denormals), libmpm_aosoa.so (grouped particle layout) and
+libmpm_lds_weights.so (P2G weights kept in LDS); the binding loads a variant
+when MPM_LIBRARY names it.
 """
 from __future__ import annotations
 
@@ -34,9 +35,15 @@ BASE_FLAGS = [
 # the state checks still see them.
 FAST_MATH_FLAGS = ["-fgpu-flush-denormals-to-zero", "-fno-signed-zeros", "-freciprocal-math",
                    "-fno-hip-fp32-correctly-rounded-divide-sqrt"]
-# Library variants: the default build and, for the fast-math ablation, one
-# with IEEE division, square root and denormals.
-VARIANTS = {"fast": ("libmpm.so", FAST_MATH_FLAGS), "precise": ("libmpm_precise.so", [])}
+# Library variants: the default build and, for the ablations, one with IEEE
+# division, square root and denormals, one with the grouped particle layout
+# (array of structures of arrays, 64 particles a group) instead of one array
+# per field, and one whose P2G keeps the stencil weights in LDS instead of
+# registers.
+VARIANTS = {"fast": ("libmpm.so", FAST_MATH_FLAGS),
+            "precise": ("libmpm_precise.so", []),
+            "aosoa": ("libmpm_aosoa.so", FAST_MATH_FLAGS + ["-DMPM_AOSOA=1"]),
+            "lds_weights": ("libmpm_lds_weights.so", FAST_MATH_FLAGS + ["-DMPM_WEIGHTS_IN_LDS=1"])}
 
 
 def _compile(src: str, variant: str) -> str:
@@ -52,7 +59,7 @@ def _compile(src: str, variant: str) -> str:
     return obj
 
 
-def build(verbose: bool = False, variants=("fast", "precise")) -> str:
+def build(verbose: bool = False, variants=tuple(VARIANTS)) -> str:
     jobs = [(src, v) for v in variants for src in SOURCES]
     for v in variants:
         os.makedirs(os.path.join(OBJ, v), exist_ok=True)

@@ -251,6 +251,7 @@ void free_particle_buffers(mpm_ctx* c) {
 
 // Allocate particle-sized buffers for `newcap`, keeping the current state.
 int grow(mpm_ctx* c, int64_t newcap) {
+    newcap = (newcap + 255) / 256 * 256;  // whole groups of the grouped layout, aligned arrays
     float* S[2] = {nullptr, nullptr};
     int* ids[2] = {nullptr, nullptr};
     uint32_t *keys[2] = {nullptr, nullptr}, *vals[2] = {nullptr, nullptr};
@@ -301,8 +302,13 @@ int grow(mpm_ctx* c, int64_t newcap) {
         return fail(c, MPM_ENOMEM, "particle buffer allocation failed for capacity " + std::to_string(newcap));
     }
     if (c->N > 0) {
+#if MPM_AOSOA  // the groups of the first N particles do not depend on the capacity
+        HIP_OK(c, hipMemcpyAsync(S[0], c->S[c->cur], sizeof(float) * NF * ((c->N + AOSOA_B - 1) / AOSOA_B * AOSOA_B),
+                                 hipMemcpyDeviceToDevice, c->stream));
+#else
         HIP_OK(c, hipMemcpy2DAsync(S[0], sizeof(float) * newcap, c->S[c->cur], sizeof(float) * c->cap,
                                    sizeof(float) * c->N, NF, hipMemcpyDeviceToDevice, c->stream));
+#endif
         HIP_OK(c, hipMemcpyAsync(ids[0], c->ids[c->cur], sizeof(int) * c->N, hipMemcpyDeviceToDevice, c->stream));
     }
     HIP_OK(c, hipMemsetAsync(box, 0, sizeof(int4) * (newcap + 1), c->stream));
@@ -479,14 +485,22 @@ bool fusion_allowed(const mpm_ctx* c) {
                              MPM_FLAG_G2P_GLOBAL_GATHER | MPM_FLAG_FRAME_GRAPHS));
 }
 
-// P2G's launch for the current particle count: workgroups for every chunk at
-// half fill (2 N / chunk), at most the machine-filling count of query_launch,
-// a multiple of 8 (one share per XCD).  Small scenes then launch no
-// workgroups that would find no chunk.
+// Grid-update passes run as launches of their own (the kernel-merging
+// ablations): bit 0 the wall condition, bit 1 the accumulator clearing.
+int grid_separate(const mpm_ctx* c) {
+    return ((c->cfg.flags & MPM_FLAG_SEPARATE_WALLS) ? 1 : 0) | ((c->cfg.flags & MPM_FLAG_SEPARATE_CLEAR) ? 2 : 0);
+}
+
+// P2G's launch for the current particle count.  query_launch sizes it at
+// four times the resident workgroups, which evens out the chunks' uneven
+// costs when there are several chunks per workgroup; with fewer chunks than
+// half that many workgroups, twice the resident count does better (the
+// workgroups without a chunk cost dispatch time): the fused P2G of 55,296
+// sand particles takes 20.4 us with twice and 22.1 us with four times the
+// resident count, and 30.7 us when the grid is cut to the chunk count.
 Launch p2g_launch(const mpm_ctx* c) {
     Launch L = c->L;
-    const int64_t want = (2 * c->N / std::max(c->cfg.chunk, 64) + 8 + 7) / 8 * 8;
-    if (want < L.p2g_grid) L.p2g_grid = (int)want;
+    if (c->N / std::max(c->cfg.chunk, 64) <= L.p2g_grid / 2) L.p2g_grid = std::max(8, L.p2g_grid / 16 * 8);
     return L;
 }
 
@@ -533,7 +547,7 @@ int substep_one(mpm_ctx* c, int act) {
                 c->cfg.chunk, act, fused ? 1 : 0, c->ring_dev + rs, fb_limit(c));
     if ((r = prof_end(c, slot))) return r;
     if ((r = prof_begin(c, 2, &slot))) return r;
-    enqueue_grid(c->stream, c->L, T, c->B, c->ctl, c->G, parity, c->nbricks, act);
+    enqueue_grid(c->stream, c->L, T, c->B, c->ctl, c->G, parity, c->nbricks, act, grid_separate(c));
     if ((r = prof_end(c, slot))) return r;
     if (fusable) {
         c->g2p_due_act = std::max(c->g2p_due_act, act);
@@ -568,7 +582,7 @@ int graph_frame(mpm_ctx* c, float frame_dt, const std::vector<int>& ns) {
             enqueue_p2g(c->stream, p2g_launch(c), T, c->S[other], c->cap, c->B.chunks, c->ctl, c->G, c->B.brick_state, 1,
                         parity, (c->cfg.flags & MPM_FLAG_P2G_GLOBAL_ATOMICS) ? 1 : 0, c->nbricks, c->cfg.chunk,
                         act, 0, nullptr, 0);
-            enqueue_grid(c->stream, c->L, T, c->B, c->ctl, c->G, parity, c->nbricks, act);
+            enqueue_grid(c->stream, c->L, T, c->B, c->ctl, c->G, parity, c->nbricks, act, grid_separate(c));
             enqueue_g2p(c->stream, c->L, T, c->S[other], c->cap, c->B.chunks, c->ctl, c->G, nullptr,
                         (c->cfg.flags & MPM_FLAG_G2P_GLOBAL_GATHER) ? 0 : 1, parity, fb_limit(c), c->cfg.chunk,
                         act, 1);
@@ -872,9 +886,12 @@ int mpm_add_particles(mpm_ctx* c, int32_t scene, const mpm_material* mat, int64_
     if (count == 0) return MPM_OK;
     // the pending G2P walks the current chunk list, which growing the buffers replaces
     if (int r = bring_up_to_date(c)) return r;
-    if (c->N + count > c->cap / 2) {
+    if ((c->cfg.flags & MPM_FLAG_ALLOC_EXACT) ? c->N + count > c->cap : c->N + count > c->cap / 2) {
         int64_t newcap = c->cap;
-        while (c->N + count > newcap / 2) newcap *= 4;
+        if (c->cfg.flags & MPM_FLAG_ALLOC_EXACT)  // the allocation ablation: just what is needed
+            newcap = c->N + count;
+        else
+            while (c->N + count > newcap / 2) newcap *= 4;
         int r = grow(c, newcap);
         if (r) return r;
     }

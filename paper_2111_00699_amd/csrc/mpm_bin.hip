@@ -69,14 +69,14 @@ __global__ __launch_bounds__(WG) void k_keys(const float* __restrict__ S, int64_
                                              int* __restrict__ ctl) {
     const int j = blockIdx.x * WG + threadIdx.x;
     if (j >= N) return;
-    const Scene& sc = T.scene[fsid_scene(S[FSID * cap + j])];
+    const Scene& sc = T.scene[fsid_scene(S[sidx(FSID, j, cap)])];
     const float fn = sc.P.fn;
     const int n = sc.P.n;
     uint32_t code = (uint32_t)sc.rank << T.shift;
     unsigned err = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const float x = S[(FX + a) * cap + j];
+        const float x = S[sidx(FX + a, j, cap)];
         const float b = floorf(x * fn - 0.5f);
         int c;
         if (!(b == b)) {
@@ -386,10 +386,10 @@ __global__ __launch_bounds__(WG) void k_permute_chunks(const float* __restrict__
             const int k = (int)src[j];  // its position before the sort
             const int dst = ch.start + slot;
 #pragma unroll
-            for (int f = 0; f < FSID; ++f) Sout[f * cap + dst] = Sin[f * cap + k];
+            for (int f = 0; f < FSID; ++f) Sout[sidx(f, dst, cap)] = Sin[sidx(f, k, cap)];
             const uint32_t bcode = (key & mmask) >> 6;
-            const int scene = fsid_scene(Sin[FSID * cap + k]);
-            Sout[FSID * cap + dst] = __int_as_float(scene | (int)(compact3(bcode) << 8) |
+            const int scene = fsid_scene(Sin[sidx(FSID, k, cap)]);
+            Sout[sidx(FSID, dst, cap)] = __int_as_float(scene | (int)(compact3(bcode) << 8) |
                                                     (int)(compact3(bcode >> 1) << 16) |
                                                     (int)(compact3(bcode >> 2) << 24));
             const int id = idin[k];

@@ -10,12 +10,32 @@
 namespace mpm {
 
 // ----------------------------------------------------------------- layout
-// Particle state: one FP32 array per scalar field, field f at S + f * cap.
-// FSID holds integer bits: the particle's scene (bits 0-7) and the block it
-// was binned to at the last rebuild (x, y, z in bits 8-15, 16-23, 24-31),
-// which fixes its free zone; it moves with the particle through the rebuild
-// permutation.
+// Particle state: FP32 scalar fields.  The default build stores them as a
+// structure of arrays, field f of particle j at S[f * cap + j].  Built with
+// MPM_AOSOA=1 (the layout ablation) it stores an array of structures of
+// arrays: particles in groups of AOSOA_B = 64 (one wave), each group holding
+// its fields one after another, 64 values each.  FSID holds integer bits:
+// the particle's scene (bits 0-7) and the block it was binned to at the last
+// rebuild (x, y, z in bits 8-15, 16-23, 24-31), which fixes its free zone; it
+// moves with the particle through the rebuild permutation.
 enum Field : int { FX = 0, FV = 3, FC = 6, FF = 15, FS = 24, FSID = 25, NF = 26 };
+
+#ifndef MPM_AOSOA
+#define MPM_AOSOA 0
+#endif
+constexpr int AOSOA_SHIFT = 6;
+constexpr int AOSOA_B = 1 << AOSOA_SHIFT;
+
+// Index of field f of particle j (cap: the buffer's particle capacity, a
+// multiple of AOSOA_B).
+__host__ __device__ __forceinline__ int64_t sidx(int f, int64_t j, int64_t cap) {
+#if MPM_AOSOA
+    (void)cap;
+    return ((j >> AOSOA_SHIFT) * NF + f) * AOSOA_B + (j & (AOSOA_B - 1));
+#else
+    return (int64_t)f * cap + j;
+#endif
+}
 
 __device__ __forceinline__ int fsid_scene(float f) { return __float_as_int(f) & 255; }
 __device__ __forceinline__ void fsid_block(float f, int B[3]) {
@@ -214,7 +234,7 @@ int p2g_grid_size(int cus, int chunk);
 // 8 waves per SIMD, 4 SIMDs, `lds_per_cu` bytes of LDS).
 int wgs_per_cu(const void* fn, int threads);
 void enqueue_grid(hipStream_t st, const Launch& L, const Scenes& T, const BinBuffers& B, int* ctl, GridBuffers& G,
-                  int parity, int nbricks, int act);
+                  int parity, int nbricks, int act, int separate = 0);
 // host_flag may be NULL (graph-recorded frames read no flag); report_zone 0
 // leaves the free-zone request alone (a G2P that only brings the state up to
 // date before it is read; the next substep's G2P reports the same exits).

@@ -260,6 +260,12 @@ __device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, con
     static_assert(!FUSED || (!GLOBAL_ONLY && SURM == 0), "the fused G2P needs the LDS tile and the exact map");
     __shared__ __align__(16) double tq[GLOBAL_ONLY ? 1 : 4 * CT];
     __shared__ int red_i[7][NT / 64];
+#ifndef MPM_WEIGHTS_IN_LDS
+#define MPM_WEIGHTS_IN_LDS 0
+#endif
+#if MPM_WEIGHTS_IN_LDS
+    __shared__ float wpark[9 * NT];
+#endif
     struct Empty {};
     __shared__ typename std::conditional<SURM == 2, mlp::NetLds16, Empty>::type net;
     __shared__ float sur_stage[SURM == 2 ? NT / 64 * 512 : 1];
@@ -307,21 +313,21 @@ __device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, con
         }
         if (have) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) x[a] = S[(FX + a) * cap + p];
+            for (int a = 0; a < 3; ++a) x[a] = S[sidx(FX + a, p, cap)];
             if (!FUSED) {
 #pragma unroll
-                for (int a = 0; a < 3; ++a) v[a] = S[(FV + a) * cap + p];
+                for (int a = 0; a < 3; ++a) v[a] = S[sidx(FV + a, p, cap)];
 #pragma unroll
-                for (int k = 0; k < 9; ++k) C[k] = S[(FC + k) * cap + p];
+                for (int k = 0; k < 9; ++k) C[k] = S[sidx(FC + k, p, cap)];
             }
-            s = S[FS * cap + p];
+            s = S[sidx(FS, p, cap)];
             if (M.kind != MPM_WATER) {
 #pragma unroll
-                for (int k = 0; k < 9; ++k) F[k] = S[(FF + k) * cap + p];
+                for (int k = 0; k < 9; ++k) F[k] = S[sidx(FF + k, p, cap)];
             }
         }
         int B[3] = {0, 0, 0};  // the particle's block at the last rebuild (its free zone)
-        if (have) fsid_block(S[FSID * cap + p], B);
+        if (have) fsid_block(S[sidx(FSID, p, cap)], B);
         int ng = 0, ngs = 0;  // fused G2P: nodes of the previous box, and the LDS float4 they span
         if constexpr (FUSED) {
             const int4 bb = box[c];  // this chunk's tile box of the previous substep
@@ -342,7 +348,7 @@ __device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, con
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     x[a] += dt * v[a];
-                    S[(FX + a) * cap + p] = x[a];
+                    S[sidx(FX + a, p, cap)] = x[a];
                     fin = fin && (fabsf(x[a]) < 1e30f) && (fabsf(v[a]) < 1e30f);
                 }
                 left = left || left_free_zone(x, P.fn, B);
@@ -371,11 +377,15 @@ __device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, con
             if (pending) {  // the deferred update of the last G2P lands here
                 if (M.kind != MPM_WATER) {
 #pragma unroll
-                    for (int k = 0; k < 9; ++k) S[(FF + k) * cap + p] = F[k];
+                    for (int k = 0; k < 9; ++k) S[sidx(FF + k, p, cap)] = F[k];
                 }
-                if (M.kind != MPM_JELLY) S[FS * cap + p] = s;
+                if (M.kind != MPM_JELLY) S[sidx(FS, p, cap)] = s;
             }
             ok = make_stencil(x, P, st, err);
+#if MPM_WEIGHTS_IN_LDS  // the register-pressure ablation: weights parked in LDS until the scatter
+#pragma unroll
+            for (int k = 0; k < 9; ++k) wpark[k * NT + tid] = st.w[k / 3][k % 3];
+#endif
             // A = m C - (4 dt V0 / dx^2) tau;  Ad = dx A;  q = m v - Ad f, so the
             // momentum sent to stencil node o is w_o (q + Ad o).
             const float Tf[9] = {tau[0], tau[1], tau[2], tau[1], tau[3], tau[4], tau[2], tau[4], tau[5]};
@@ -483,6 +493,12 @@ __device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, con
             const unsigned long long fb = __ballot(have && ok && !GLOBAL_ONLY && in_zone && nt <= 0);
             if (fb && lane == 0) atomicAdd(&ctl[CTL_FB + parity], (int)__popcll(fb));
         }
+#if MPM_WEIGHTS_IN_LDS  // (a barrier separates the store from this load)
+        if (have) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) st.w[k / 3][k % 3] = wpark[k * NT + tid];
+        }
+#endif
         // Tile lanes whose stencil holds a weight below TINY_W send those
         // contributions to the global accumulators instead; the smallest of a
         // stencil's 27 weights is the product of its per-axis minima.  The
@@ -647,10 +663,10 @@ __global__ __launch_bounds__(NT) void k_materialize_map(float* __restrict__ S, i
         float C[9], F[9], s = 1.0f, tau[6];
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            C[k] = have ? S[(FC + k) * cap + p] : 0.0f;
-            F[k] = have ? S[(FF + k) * cap + p] : ((k % 4 == 0) ? 1.0f : 0.0f);
+            C[k] = have ? S[sidx(FC + k, p, cap)] : 0.0f;
+            F[k] = have ? S[sidx(FF + k, p, cap)] : ((k % 4 == 0) ? 1.0f : 0.0f);
         }
-        if (have) s = S[FS * cap + p];
+        if (have) s = S[sidx(FS, p, cap)];
         bool fb = false;
         if (sc.ret != 0 && M.kind == MPM_SNOW) {  // uniform over the workgroup
             if constexpr (SURM == 2) {
@@ -667,9 +683,9 @@ __global__ __launch_bounds__(NT) void k_materialize_map(float* __restrict__ S, i
         if (have) {
             if (M.kind != MPM_WATER) {
 #pragma unroll
-                for (int k = 0; k < 9; ++k) S[(FF + k) * cap + p] = F[k];
+                for (int k = 0; k < 9; ++k) S[sidx(FF + k, p, cap)] = F[k];
             }
-            if (M.kind != MPM_JELLY) S[FS * cap + p] = s;
+            if (M.kind != MPM_JELLY) S[sidx(FS, p, cap)] = s;
         }
     }
 }

@@ -32,6 +32,96 @@ namespace {
 // rebuild whose box (this substep's) holds the node, in chunk order, then
 // v = p/m + dt g where m > 0 (else 0) and the wall condition; writes (v, m),
 // clears the accumulator, and stamps the block.
+// The wall condition on a node's velocity (lowside/highside: the node lies
+// in the low/high wall layer of each axis).
+__device__ __forceinline__ void wall_condition(const Step& P, const bool lowside[3], const bool highside[3],
+                                               float v[3]) {
+    if (P.bc == MPM_BC_STICKY) {
+        v[0] = v[1] = v[2] = 0.0f;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (P.bc == MPM_BC_SLIP) {
+                if (lowside[k] || highside[k]) v[k] = 0.0f;
+            } else {
+                if (lowside[k] && v[k] < 0.0f) v[k] = 0.0f;
+                if (highside[k] && v[k] > 0.0f) v[k] = 0.0f;
+            }
+        }
+    }
+}
+
+// The grid update's block list: the physical blocks of the last rebuild and
+// this substep's overflow blocks; f(b, it, node coordinates, scene) per wave
+// and block.
+template <class Fn>
+__device__ __forceinline__ void for_grid_blocks(const int* active, const int* ctl, const int* ovf, int parity,
+                                                int nbricks, const Scenes& T, int act, Fn f) {
+    const int nact = rank_limit(T, ctl, act, RE_ACTIVE, CTL_NACTIVE);
+    const int total = nact + min(ctl[CTL_OVF + parity], nbricks - ctl[CTL_NACTIVE]);
+    const int lane = threadIdx.x & 63;
+    const int nwaves = gridDim.x * (WG / 64);
+    for (int it = blockIdx.x * (WG / 64) + (threadIdx.x >> 6); it < total; it += nwaves) {
+        const int b = __builtin_amdgcn_readfirstlane(it < nact ? active[it] : ovf[it - nact]);
+        const Scene& sc = T.scene[T.rank_scene[rank_of_brick(T, b)]];
+        const int NB = sc.P.NB, lb = b - sc.brick_base;
+        const int bx = lb % NB, by = (lb / NB) % NB, bz = lb / (NB * NB);
+        const int g[3] = {4 * (bx - 1) + (lane & 3), 4 * (by - 1) + ((lane >> 2) & 3), 4 * (bz - 1) + (lane >> 4)};
+        f(b, it < nact, g, sc);
+    }
+}
+
+// The wall condition as a launch of its own, after k_grid<false, ...>.
+__global__ __launch_bounds__(WG) void k_grid_walls(float4* __restrict__ vel, float4* __restrict__ dvel,
+                                                   const int* __restrict__ active, const int* __restrict__ ctl,
+                                                   const int* __restrict__ ovf, int parity, int nbricks, Scenes T,
+                                                   int act) {
+    const int lane = threadIdx.x & 63;
+    for_grid_blocks(active, ctl, ovf, parity, nbricks, T, act, [&](int b, bool, const int g[3], const Scene& sc) {
+        const Step P = sc.P;
+        bool any = false, lowside[3], highside[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            lowside[k] = g[k] < P.bc_cells;
+            highside[k] = g[k] > P.n - P.bc_cells;
+            any = any || lowside[k] || highside[k];
+        }
+        if (!any) return;
+        float4 u = vel[(int64_t)b * 64 + lane];
+        float v[3] = {u.x, u.y, u.z};
+        wall_condition(P, lowside, highside, v);
+        vel[(int64_t)b * 64 + lane] = make_float4(v[0], v[1], v[2], u.w);
+        if (P.flip > 0.0f) {  // keep the ASFLIP grid change consistent with the walls
+            float4 d = dvel[(int64_t)b * 64 + lane];
+            d.x += v[0] - u.x;
+            d.y += v[1] - u.y;
+            d.z += v[2] - u.z;
+            if (u.w > 0.0f) dvel[(int64_t)b * 64 + lane] = d;
+        }
+    });
+}
+
+// The clearing of the global accumulators as a launch of its own, after
+// k_grid<..., false>.
+__global__ __launch_bounds__(WG) void k_grid_clear(float* __restrict__ acc, int* __restrict__ acc_dirty,
+                                                   const int* __restrict__ active, const int* __restrict__ ctl,
+                                                   const int* __restrict__ ovf, int* __restrict__ brick_state,
+                                                   int parity, int nbricks, Scenes T, int act) {
+    const int lane = threadIdx.x & 63;
+    float4* acc4 = reinterpret_cast<float4*>(acc);
+    for_grid_blocks(active, ctl, ovf, parity, nbricks, T, act, [&](int b, bool physical, const int*, const Scene&) {
+        if (__builtin_amdgcn_readfirstlane(acc_dirty[b]) != 0) {
+            acc4[(int64_t)b * 64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (lane == 0) acc_dirty[b] = 0;
+        }
+        if (lane == 0 && !physical) brick_state[b] = 0;
+    });
+}
+
+// BC and CLEAR false (the kernel-merging ablations): the wall condition, or
+// the clearing of the global accumulators, is left to a launch of its own
+// (k_grid_walls, k_grid_clear).
+template <bool BC, bool CLEAR>
 __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, int* __restrict__ acc_dirty,
                                              float4* __restrict__ vel, float4* __restrict__ dvel,
                                              const int* __restrict__ active, int* __restrict__ ctl,
@@ -115,21 +205,7 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, int* __res
             highside[k] = g[k] > P.n - P.bc_cells;
             any = any || lowside[k] || highside[k];
         }
-        if (any) {
-            if (P.bc == MPM_BC_STICKY) {
-                v[0] = v[1] = v[2] = 0.0f;
-            } else {
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    if (P.bc == MPM_BC_SLIP) {
-                        if (lowside[k] || highside[k]) v[k] = 0.0f;
-                    } else {
-                        if (lowside[k] && v[k] < 0.0f) v[k] = 0.0f;
-                        if (highside[k] && v[k] > 0.0f) v[k] = 0.0f;
-                    }
-                }
-            }
-        }
+        if (BC && any) wall_condition(P, lowside, highside, v);
         vel[(int64_t)b * 64 + lane] = make_float4(v[0], v[1], v[2], a.x);
         if (P.flip > 0.0f) {  // ASFLIP: the change from the transferred velocity p/m
             float4 d = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -139,11 +215,11 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, int* __res
             }
             dvel[(int64_t)b * 64 + lane] = d;
         }
-        if (dirty) acc4[(int64_t)b * 64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (CLEAR && dirty) acc4[(int64_t)b * 64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (lane == 0) {
             stamp[b] = step;
-            if (dirty) acc_dirty[b] = 0;
-            if (it >= nact) brick_state[b] = 0;
+            if (CLEAR && dirty) acc_dirty[b] = 0;
+            if (CLEAR && it >= nact) brick_state[b] = 0;
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -187,8 +263,8 @@ __global__ __launch_bounds__(NT) void k_g2p(float* __restrict__ S, int64_t cap, 
         float x[3] = {0.f, 0.f, 0.f}, fsid = 0.f;
         if (mine) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) x[a] = S[(FX + a) * cap + p];
-            fsid = S[FSID * cap + p];
+            for (int a = 0; a < 3; ++a) x[a] = S[sidx(FX + a, p, cap)];
+            fsid = S[sidx(FSID, p, cap)];
         }
         int lo[3] = {0, 0, 0}, e[3] = {0, 0, 0}, nt = 0, R = 4, Q = 8;
         if (LDS_BOX) {
@@ -218,7 +294,7 @@ __global__ __launch_bounds__(NT) void k_g2p(float* __restrict__ S, int64_t cap, 
             float vp[3], Cn[9];
             g2p_gather(st, tv, vels, NB, lo, e, nt, R, Q, c4, vp, Cn);
 #pragma unroll
-            for (int k = 0; k < 9; ++k) S[(FC + k) * cap + p] = Cn[k];
+            for (int k = 0; k < 9; ++k) S[sidx(FC + k, p, cap)] = Cn[k];
             // APIC: x' = x + dt v', v' the interpolated new grid velocity
             float xv[3] = {vp[0], vp[1], vp[2]};
             if (P.flip > 0.0f) {
@@ -251,11 +327,11 @@ __global__ __launch_bounds__(NT) void k_g2p(float* __restrict__ S, int64_t cap, 
 #pragma unroll
                 for (int k = 0; k < 9; ++k) G[k] = P.dt * Cn[k] + ((k % 4 == 0) ? 1.0f : 0.0f);
                 float J = det3(G);
-                if (sc.M.kind == MPM_WATER) J *= S[FS * cap + p];
+                if (sc.M.kind == MPM_WATER) J *= S[sidx(FS, p, cap)];
                 const float beta = J < 1.0f ? P.bmin : P.bmax;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    const float corr = S[(FV + a) * cap + p] + ds[a] - vp[a];  // v_FLIP - v_PIC
+                    const float corr = S[sidx(FV + a, p, cap)] + ds[a] - vp[a];  // v_FLIP - v_PIC
                     xv[a] = vp[a] + beta * P.flip * corr;
                     vp[a] += P.flip * corr;
                 }
@@ -265,8 +341,8 @@ __global__ __launch_bounds__(NT) void k_g2p(float* __restrict__ S, int64_t cap, 
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 xn[a] = x[a] + P.dt * xv[a];
-                S[(FV + a) * cap + p] = vp[a];
-                S[(FX + a) * cap + p] = xn[a];
+                S[sidx(FV + a, p, cap)] = vp[a];
+                S[sidx(FX + a, p, cap)] = xn[a];
                 fin = fin && (fabsf(xn[a]) < 1e30f) && (fabsf(vp[a]) < 1e30f);
             }
             int B[3];  // the particle's block at the last rebuild (its free zone)
@@ -293,18 +369,18 @@ __global__ __launch_bounds__(NT) void k_g2p(float* __restrict__ S, int64_t cap, 
 __global__ __launch_bounds__(WG) void k_materialize(float* __restrict__ S, int64_t cap, int N, Scenes T) {
     const int p = blockIdx.x * WG + threadIdx.x;
     if (p >= N) return;
-    const Scene& sc = T.scene[fsid_scene(S[FSID * cap + p])];
+    const Scene& sc = T.scene[fsid_scene(S[sidx(FSID, p, cap)])];
     float C[9], F[9], s, tau[6];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        C[k] = S[(FC + k) * cap + p];
-        F[k] = S[(FF + k) * cap + p];
+        C[k] = S[sidx(FC + k, p, cap)];
+        F[k] = S[sidx(FF + k, p, cap)];
     }
-    s = S[FS * cap + p];
+    s = S[sidx(FS, p, cap)];
     material_step(sc.M, sc.P.dt, 1, C, F, s, tau);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) S[(FF + k) * cap + p] = F[k];
-    S[FS * cap + p] = s;
+    for (int k = 0; k < 9; ++k) S[sidx(FF + k, p, cap)] = F[k];
+    S[sidx(FS, p, cap)] = s;
 }
 
 // Append `count` particles of `scene` at storage positions N0.., numbered
@@ -323,16 +399,16 @@ __global__ __launch_bounds__(WG) void k_insert(float* __restrict__ S, int* __res
         const float xa = x[a * (int64_t)count + i];
         if (!(fabsf(xa) < 1e30f)) err |= MPM_ERR_NONFINITE;
         else if (!(xa >= 0.0f && xa <= 1.0f)) err |= MPM_ERR_DOMAIN;
-        S[(FX + a) * cap + j] = xa;
-        S[(FV + a) * cap + j] = v ? v[a * (int64_t)count + i] : 0.0f;
+        S[sidx(FX + a, j, cap)] = xa;
+        S[sidx(FV + a, j, cap)] = v ? v[a * (int64_t)count + i] : 0.0f;
     }
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        S[(FC + k) * cap + j] = C ? C[k * (int64_t)count + i] : 0.0f;
-        S[(FF + k) * cap + j] = F ? F[k * (int64_t)count + i] : ((k % 4 == 0) ? 1.0f : 0.0f);
+        S[sidx(FC + k, j, cap)] = C ? C[k * (int64_t)count + i] : 0.0f;
+        S[sidx(FF + k, j, cap)] = F ? F[k * (int64_t)count + i] : ((k % 4 == 0) ? 1.0f : 0.0f);
     }
-    S[FS * cap + j] = s ? s[i] : 1.0f;
-    S[FSID * cap + j] = __int_as_float(scene);
+    S[sidx(FS, j, cap)] = s ? s[i] : 1.0f;
+    S[sidx(FSID, j, cap)] = __int_as_float(scene);
     ids[j] = id0 + i;
     if (err) atomicOr(&ctl[CTL_ERROR], (int)err);
 }
@@ -343,19 +419,19 @@ __global__ __launch_bounds__(WG) void k_read(const float* __restrict__ S, const 
                                              float* __restrict__ v, float* __restrict__ C, float* __restrict__ F,
                                              float* __restrict__ s) {
     const int j = blockIdx.x * WG + threadIdx.x;
-    if (j >= N || fsid_scene(S[FSID * cap + j]) != scene) return;
+    if (j >= N || fsid_scene(S[sidx(FSID, j, cap)]) != scene) return;
     const Scene& sc = T.scene[scene];
     const int64_t id = ids[j];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (x) x[a * (int64_t)Ns + id] = S[(FX + a) * cap + j];
-        if (v) v[a * (int64_t)Ns + id] = S[(FV + a) * cap + j];
+        if (x) x[a * (int64_t)Ns + id] = S[sidx(FX + a, j, cap)];
+        if (v) v[a * (int64_t)Ns + id] = S[sidx(FV + a, j, cap)];
     }
-    float Cp[9], Fp[9], sp = S[FS * cap + j], tau[6];
+    float Cp[9], Fp[9], sp = S[sidx(FS, j, cap)], tau[6];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        Cp[k] = S[(FC + k) * cap + j];
-        Fp[k] = S[(FF + k) * cap + j];
+        Cp[k] = S[sidx(FC + k, j, cap)];
+        Fp[k] = S[sidx(FF + k, j, cap)];
         if (C) C[k * (int64_t)Ns + id] = Cp[k];
     }
     if (pending && (F || s)) material_step(sc.M, sc.P.dt, 1, Cp, Fp, sp, tau);
@@ -432,14 +508,27 @@ void query_launch(Launch& L, int chunk) {
     const int nt = chunk_threads(chunk);
     L.p2g_grid = p2g_grid_size(L.cus, chunk);
     L.g2p_grid = grid_for(g2p_fn(true, nt), nt, 8 * 256 / nt);
-    L.grid_grid = grid_for(reinterpret_cast<const void*>(k_grid), WG, 8);
+    L.grid_grid = grid_for(reinterpret_cast<const void*>(k_grid<true, true>), WG, 8);
 }
 
 void enqueue_grid(hipStream_t st, const Launch& L, const Scenes& T, const BinBuffers& B, int* ctl, GridBuffers& G,
-                  int parity, int nbricks, int act) {
-    hipLaunchKernelGGL(k_grid, dim3(L.grid_grid), dim3(WG), 0, st, G.acc, G.acc_dirty, G.vel, G.dvel, B.active, ctl,
-                       G.ovf[parity],
-                       B.brick_state, G.stamp, G.reg_n, G.reg, G.stage, G.box, parity, nbricks, T, act);
+                  int parity, int nbricks, int act, int separate) {
+    const bool bc = !(separate & 1), clear = !(separate & 2);
+#define MPM_LAUNCH_GRID(BCV, CLV)                                                                                  \
+    hipLaunchKernelGGL((k_grid<BCV, CLV>), dim3(L.grid_grid), dim3(WG), 0, st, G.acc, G.acc_dirty, G.vel, G.dvel, \
+                       B.active, ctl, G.ovf[parity], B.brick_state, G.stamp, G.reg_n, G.reg, G.stage, G.box, parity,  \
+                       nbricks, T, act)
+    if (bc && clear) MPM_LAUNCH_GRID(true, true);
+    else if (bc) MPM_LAUNCH_GRID(true, false);
+    else if (clear) MPM_LAUNCH_GRID(false, true);
+    else MPM_LAUNCH_GRID(false, false);
+#undef MPM_LAUNCH_GRID
+    if (!bc)
+        hipLaunchKernelGGL(k_grid_walls, dim3(L.grid_grid), dim3(WG), 0, st, G.vel, G.dvel, B.active, ctl,
+                           G.ovf[parity], parity, nbricks, T, act);
+    if (!clear)
+        hipLaunchKernelGGL(k_grid_clear, dim3(L.grid_grid), dim3(WG), 0, st, G.acc, G.acc_dirty, B.active, ctl,
+                           G.ovf[parity], B.brick_state, parity, nbricks, T, act);
 }
 
 void enqueue_g2p(hipStream_t st, const Launch& L, const Scenes& T, float* S, int64_t cap, const Chunk* chunks,
@@ -464,7 +553,7 @@ __global__ __launch_bounds__(WG) void k_max_speed(const float* __restrict__ S, i
                                                   float* __restrict__ out) {
     float m = 0.0f;
     for (int p = blockIdx.x * WG + threadIdx.x; p < N; p += gridDim.x * WG) {
-        const float a = S[FV * cap + p], b = S[(FV + 1) * cap + p], c = S[(FV + 2) * cap + p];
+        const float a = S[sidx(FV, p, cap)], b = S[sidx(FV + 1, p, cap)], c = S[sidx(FV + 2, p, cap)];
         m = fmaxf(m, sqrtf(a * a + b * b + c * c));
     }
     m = wave_maxf(m);

@@ -333,16 +333,16 @@ __global__ __launch_bounds__(SW) void k_sur_sample(const float* __restrict__ S, 
                                                    float* __restrict__ X, float* __restrict__ Y,
                                                    unsigned long long* __restrict__ counter) {
     const int j = blockIdx.x * SW + threadIdx.x;
-    if (j >= N || fsid_scene(S[FSID * cap + j]) != scene) return;
+    if (j >= N || fsid_scene(S[sidx(FSID, j, cap)]) != scene) return;
     const Scene& sc = T.scene[scene];
     const Mat& M = sc.M;
     float C[9], F[9], Fh[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        C[k] = S[(FC + k) * cap + j];
-        F[k] = S[(FF + k) * cap + j];
+        C[k] = S[sidx(FC + k, j, cap)];
+        F[k] = S[sidx(FF + k, j, cap)];
     }
-    const float Jp = S[FS * cap + j];
+    const float Jp = S[sidx(FS, j, cap)];
     if (pending)
         advance_gradient(C, sc.P.dt, F, Fh);
     else

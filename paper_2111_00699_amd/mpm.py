@@ -12,9 +12,12 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# MPM_LIBRARY=precise selects the build with IEEE division, square root and
-# denormals (the fast-math ablation); the default is the fast-math build.
-LIB_VARIANTS = {"fast": "libmpm.so", "precise": "libmpm_precise.so"}
+# MPM_LIBRARY selects a build of the library: "fast" (the default, fast-math
+# flags) or one of the ablation builds: "precise" (IEEE division, square root
+# and denormals), "aosoa" (grouped particle layout), "lds_weights" (P2G
+# stencil weights kept in LDS).
+LIB_VARIANTS = {"fast": "libmpm.so", "precise": "libmpm_precise.so", "aosoa": "libmpm_aosoa.so",
+                "lds_weights": "libmpm_lds_weights.so"}
 LIB_PATH = os.path.join(HERE, LIB_VARIANTS[os.environ.get("MPM_LIBRARY", "fast") or "fast"])
 
 KIND = {"jelly": 0, "snow": 1, "water": 2, "sand": 3}
@@ -24,6 +27,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -1, -2, -3, -4
 ERR_NONFINITE, ERR_DOMAIN, ERR_CAPACITY = 0x1, 0x2, 0x4
 FLAG_REBUILD_EVERY_STEP, FLAG_P2G_GLOBAL_ATOMICS, FLAG_MANUAL_REBUILD, FLAG_P2G_SORTED_LANES = 0x1, 0x2, 0x4, 0x8
 FLAG_G2P_GLOBAL_GATHER, FLAG_FRAME_GRAPHS, FLAG_FUSED_G2P, FLAG_SEPARATE_G2P = 0x10, 0x20, 0x40, 0x80
+FLAG_SEPARATE_WALLS, FLAG_SEPARATE_CLEAR, FLAG_ALLOC_EXACT = 0x100, 0x200, 0x400
 MAX_SCENES = 256
 PHASE_REBUILD, PHASE_P2G, PHASE_GRID, PHASE_G2P = 0x1, 0x2, 0x4, 0x8
 
