@@ -100,7 +100,10 @@ struct mpm_ctx {
     // the next substep's P2G runs it first (fused), or bring_up_to_date()
     // does before the state is read, extended, sampled or rebuilt.
     int g2p_due_act = 0;
-    FrameGraph graphs[2];
+    // frame graphs by particle-buffer parity and by whether the frame starts with a rebuild
+    FrameGraph graphs[2][2];
+    hipEvent_t graph_done = nullptr;  // recorded after the last graph frame
+    bool graph_inflight = false;
     // snow return map without SVD (see mpm_use_surrogate)
     const float* sur_theta = nullptr;
     const float* sur_norm = nullptr;
@@ -403,11 +406,26 @@ int poll_flags(mpm_ctx* c, int64_t must_upto) {
 
 
 void drop_graphs(mpm_ctx* c) {
-    for (auto& g : c->graphs) {
-        if (g.exec) (void)hipGraphExecDestroy(g.exec);
-        if (g.graph) (void)hipGraphDestroy(g.graph);
-        g = FrameGraph{};
+    for (auto& gp : c->graphs)
+        for (auto& g : gp) {
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
+            if (g.graph) (void)hipGraphDestroy(g.graph);
+            g = FrameGraph{};
+        }
+}
+
+// Wait for the last graph frame and take over its rebuild request (the
+// pinned word after the ring slots, which graph frames' kernels set when a
+// particle leaves its free zone).
+int settle_graph_frame(mpm_ctx* c) {
+    if (!c->graph_inflight) return MPM_OK;
+    HIP_OK(c, hipEventSynchronize(c->graph_done));
+    c->graph_inflight = false;
+    if (__atomic_load_n(c->ring + RING, __ATOMIC_ACQUIRE)) {
+        c->need_rebuild = true;
+        __atomic_store_n(c->ring + RING, 0, __ATOMIC_RELEASE);
     }
+    return MPM_OK;
 }
 
 // Substeps each rank takes in a frame of length frame_dt (non-increasing in
@@ -434,11 +452,13 @@ int active_ranks(const std::vector<int>& ns, int k) {
 // MPM_FLAG_MANUAL_REBUILD the request is ignored like the free-zone one.
 int fb_limit(const mpm_ctx* c) { return (int)(c->N >> 8); }
 
-void enqueue_rebuild_into_alt(mpm_ctx* c) {
-    enqueue_rebuild(c->stream, tables(c), c->S[c->cur], c->S[c->cur ^ 1], c->ids[c->cur], c->ids[c->cur ^ 1], c->cap,
+// Rebuild from particle buffer `cur` into the other one.
+void enqueue_rebuild_into_alt(mpm_ctx* c, int cur) {
+    enqueue_rebuild(c->stream, tables(c), c->S[cur], c->S[cur ^ 1], c->ids[cur], c->ids[cur ^ 1], c->cap,
                     (int)c->N, c->cfg.chunk, (c->cfg.flags & MPM_FLAG_P2G_SORTED_LANES) ? 0 : 1, c->B, c->ctl,
                     c->nbricks, c->key_bits, c->G.reg_n, c->G.reg);
 }
+void enqueue_rebuild_into_alt(mpm_ctx* c) { enqueue_rebuild_into_alt(c, c->cur); }
 
 void note_rebuild(mpm_ctx* c) {
     c->cur ^= 1;
@@ -478,11 +498,14 @@ int check_error_word(mpm_ctx* c) {
 // misses beyond that on its GPU); on gfx950 with the fixed-point tile it
 // saves 8-10% of a frame at 6.6K-99K particles and 3% at 1.28M, so it is
 // the default at every size.
-bool fusion_allowed(const mpm_ctx* c) {
+// G2P may run inside the next substep's P2G (in_graph: inside a graph frame,
+// which fuses within the frame).
+bool fusion_allowed(const mpm_ctx* c, bool in_graph = false) {
     const bool wanted = (c->cfg.flags & MPM_FLAG_FUSED_G2P) || !(c->cfg.flags & MPM_FLAG_SEPARATE_G2P);
     return wanted && !c->sur_any && !c->any_flip &&
            !(c->cfg.flags & (MPM_FLAG_P2G_GLOBAL_ATOMICS | MPM_FLAG_REBUILD_EVERY_STEP |
-                             MPM_FLAG_G2P_GLOBAL_GATHER | MPM_FLAG_FRAME_GRAPHS));
+                             MPM_FLAG_G2P_GLOBAL_GATHER)) &&
+           (in_graph || !(c->cfg.flags & MPM_FLAG_FRAME_GRAPHS));
 }
 
 // Grid-update passes run as launches of their own (the kernel-merging
@@ -522,8 +545,9 @@ int bring_up_to_date(mpm_ctx* c) {
 // substep ends after its grid update and its G2P runs at the start of the
 // next substep's P2G.
 int substep_one(mpm_ctx* c, int act) {
-    int r = poll_flags(c, c->step - c->cfg.lag);
+    int r = settle_graph_frame(c);
     if (r) return r;
+    if ((r = poll_flags(c, c->step - c->cfg.lag))) return r;
     int slot;
     const bool rebuild = c->need_rebuild || (c->cfg.flags & MPM_FLAG_REBUILD_EVERY_STEP);
     const bool fusable = fusion_allowed(c);
@@ -563,49 +587,79 @@ int substep_one(mpm_ctx* c, int act) {
     return MPM_OK;
 }
 
-// A frame as a replayed graph: rebuild from buffer `cur` into the other one,
-// then every substep of the frame on it.  Recorded on first use for this
-// parity, particle count, frame length and chunk size.
+// A frame as a replayed graph.  Each particle-buffer parity has two
+// recordings: with a rebuild at the frame start (into the other buffer) and
+// without.  The host picks one from the rebuild request the previous graph
+// frame left (it waits for that frame first), so rebuilds keep the free
+// zone's cadence; a frame without one starts by clearing the overflow
+// counts, as a rebuild does.  Inside the frame each substep's G2P runs within
+// the next substep's P2G when fusion is allowed, and the frame ends with the
+// G2P still due.  A recording holds for one particle count, frame length
+// and chunk size.
+// Record the frame graph of particle buffer `cur`, with or without the
+// rebuild at its start.
+int record_frame_graph(mpm_ctx* c, int cur, bool rebuild, float frame_dt, const std::vector<int>& ns) {
+    FrameGraph& g = c->graphs[cur][rebuild ? 1 : 0];
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g = FrameGraph{};
+    const bool fuse = fusion_allowed(c, true);
+    int* flag = c->ring_dev + RING;
+    HIP_OK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    if (rebuild)
+        enqueue_rebuild_into_alt(c, cur);
+    else
+        enqueue_clear_overflow(c->stream, c->ctl);
+    const int buf = rebuild ? cur ^ 1 : cur;
+    const Scenes T = tables(c);
+    const int lds_box = (c->cfg.flags & MPM_FLAG_G2P_GLOBAL_GATHER) ? 0 : 1;
+    for (int k = 0; k < ns[0]; ++k) {
+        const int act = active_ranks(ns, k);
+        const int parity = k & 1;  // both overflow slots start cleared
+        const bool fused = fuse && k > 0;
+        enqueue_p2g(c->stream, p2g_launch(c), T, c->S[buf], c->cap, c->B.chunks, c->ctl, c->G, c->B.brick_state, 1,
+                    parity, (c->cfg.flags & MPM_FLAG_P2G_GLOBAL_ATOMICS) ? 1 : 0, c->nbricks, c->cfg.chunk, act,
+                    fused ? 1 : 0, flag, fb_limit(c));
+        enqueue_grid(c->stream, c->L, T, c->B, c->ctl, c->G, parity, c->nbricks, act, grid_separate(c));
+        if (!fuse)
+            enqueue_g2p(c->stream, c->L, T, c->S[buf], c->cap, c->B.chunks, c->ctl, c->G, flag, lds_box, parity,
+                        fb_limit(c), c->cfg.chunk, act, 1);
+    }
+    if (fuse)  // every scene's last substep of the frame
+        enqueue_g2p(c->stream, c->L, T, c->S[buf], c->cap, c->B.chunks, c->ctl, c->G, flag, lds_box,
+                    (ns[0] - 1) & 1, fb_limit(c), c->cfg.chunk, active_ranks(ns, 0), 1);
+    hipGraph_t graph = nullptr;
+    const hipError_t e1 = hipGetLastError();
+    const hipError_t e2 = hipStreamEndCapture(c->stream, &graph);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(c, MPM_EDEVICE, std::string("frame graph capture: ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+    }
+    g.graph = graph;
+    HIP_OK(c, hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+    g.N = c->N;
+    g.frame_dt = frame_dt;
+    g.chunk = c->cfg.chunk;
+    return MPM_OK;
+}
+
 int graph_frame(mpm_ctx* c, float frame_dt, const std::vector<int>& ns) {
-    FrameGraph& g = c->graphs[c->cur];
+    if (int r = settle_graph_frame(c)) return r;
+    const bool rebuild = c->need_rebuild || (c->cfg.flags & MPM_FLAG_REBUILD_EVERY_STEP);
+    const FrameGraph& g = c->graphs[c->cur][rebuild ? 1 : 0];
     if (!(g.exec && g.N == c->N && g.frame_dt == frame_dt && g.chunk == c->cfg.chunk)) {
-        if (g.exec) (void)hipGraphExecDestroy(g.exec);
-        if (g.graph) (void)hipGraphDestroy(g.graph);
-        g = FrameGraph{};
-        HIP_OK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-        enqueue_rebuild_into_alt(c);
-        const int other = c->cur ^ 1;
-        const Scenes T = tables(c);
-        for (int k = 0; k < ns[0]; ++k) {
-            const int act = active_ranks(ns, k);
-            const int parity = k & 1;  // the rebuild cleared both overflow slots
-            enqueue_p2g(c->stream, p2g_launch(c), T, c->S[other], c->cap, c->B.chunks, c->ctl, c->G, c->B.brick_state, 1,
-                        parity, (c->cfg.flags & MPM_FLAG_P2G_GLOBAL_ATOMICS) ? 1 : 0, c->nbricks, c->cfg.chunk,
-                        act, 0, nullptr, 0);
-            enqueue_grid(c->stream, c->L, T, c->B, c->ctl, c->G, parity, c->nbricks, act, grid_separate(c));
-            enqueue_g2p(c->stream, c->L, T, c->S[other], c->cap, c->B.chunks, c->ctl, c->G, nullptr,
-                        (c->cfg.flags & MPM_FLAG_G2P_GLOBAL_GATHER) ? 0 : 1, parity, fb_limit(c), c->cfg.chunk,
-                        act, 1);
-        }
-        hipGraph_t graph = nullptr;
-        const hipError_t e1 = hipGetLastError();
-        const hipError_t e2 = hipStreamEndCapture(c->stream, &graph);
-        if (e1 != hipSuccess || e2 != hipSuccess) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return fail(c, MPM_EDEVICE, std::string("frame graph capture: ") +
-                                            hipGetErrorString(e1 != hipSuccess ? e1 : e2));
-        }
-        g.graph = graph;
-        HIP_OK(c, hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
-        g.N = c->N;
-        g.frame_dt = frame_dt;
-        g.chunk = c->cfg.chunk;
+        // all four at once, so that a run does not stop to record mid-way
+        for (int cur = 0; cur < 2; ++cur)
+            for (int rb = 0; rb < 2; ++rb)
+                if (int r = record_frame_graph(c, cur, rb != 0, frame_dt, ns)) return r;
     }
     HIP_OK(c, hipGraphLaunch(g.exec, c->stream));
-    note_rebuild(c);
+    HIP_OK(c, hipEventRecord(c->graph_done, c->stream));
+    c->graph_inflight = true;
+    if (rebuild) note_rebuild(c);
     c->parity_ctr = 0;
     for (int k = 0; k < ns[0]; ++k) note_substep(c, active_ranks(ns, k));
-    c->checked = c->step;  // graph frames leave no host flags to read
+    c->checked = c->step;  // graph frames leave no ring flags to read
     return MPM_OK;
 }
 
@@ -806,18 +860,22 @@ int mpm_create(const mpm_config* cfg, mpm_ctx** out) {
         c->err = "initialisation failed";
         return bail(MPM_EDEVICE);
     }
-    if (hipHostMalloc(&c->ring, sizeof(int) * RING, hipHostMallocDefault) != hipSuccess ||
+    if (hipHostMalloc(&c->ring, sizeof(int) * (RING + 1), hipHostMallocDefault) != hipSuccess ||
         hipHostGetDevicePointer(reinterpret_cast<void**>(&c->ring_dev), c->ring, 0) != hipSuccess) {
         (void)hipGetLastError();
         c->err = "pinned ring allocation failed";
         return bail(MPM_ENOMEM);
     }
-    memset(c->ring, 0, sizeof(int) * RING);
+    memset(c->ring, 0, sizeof(int) * (RING + 1));
     for (int i = 0; i < RING; ++i)
         if (hipEventCreateWithFlags(&c->ev[i], hipEventDisableTiming) != hipSuccess) {
             c->err = "event creation failed";
             return bail(MPM_EDEVICE);
         }
+    if (hipEventCreateWithFlags(&c->graph_done, hipEventDisableTiming) != hipSuccess) {
+        c->err = "event creation failed";
+        return bail(MPM_EDEVICE);
+    }
     int64_t cap0 = cfg->capacity > 0 ? cfg->capacity : 4096;
     cap0 = (cap0 + 255) / 256 * 256;
     int r = grow(c, cap0);
@@ -851,6 +909,7 @@ int mpm_destroy(mpm_ctx* c) {
     if (c->ring) (void)hipHostFree(c->ring);
     for (int i = 0; i < RING; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    if (c->graph_done) (void)hipEventDestroy(c->graph_done);
     for (auto& p : c->prof) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);

@@ -551,6 +551,18 @@ __global__ void k_finish_rebuild(int* ctl) {
 
 }  // namespace
 
+// The overflow-block and tile-fallback counts of both substep parities
+// cleared between substeps, as a rebuild leaves them (a graph frame without
+// a rebuild starts with this).
+__global__ void k_clear_overflow(int* ctl) {
+    ctl[CTL_OVF] = ctl[CTL_OVF + 1] = 0;
+    ctl[CTL_FB] = ctl[CTL_FB + 1] = 0;
+}
+
+void enqueue_clear_overflow(hipStream_t st, int* ctl) {
+    hipLaunchKernelGGL(k_clear_overflow, dim3(1), dim3(1), 0, st, ctl);
+}
+
 void enqueue_copy_codes(hipStream_t st, uint32_t* dst, const uint32_t* src, int count, uint32_t mask) {
     if (count <= 0) return;
     hipLaunchKernelGGL(k_copy_codes, dim3(cdiv(count, WG)), dim3(WG), 0, st, dst, src, count, mask);

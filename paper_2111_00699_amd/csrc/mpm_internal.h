@@ -243,6 +243,7 @@ void enqueue_g2p(hipStream_t st, const Launch& L, const Scenes& T, float* S, int
                  int act, int report_zone);
 void enqueue_materialize(hipStream_t st, const Scenes& T, float* S, int64_t cap, int N);
 void enqueue_max_speed(hipStream_t st, const float* S, int64_t cap, int N, float* out);
+void enqueue_clear_overflow(hipStream_t st, int* ctl);
 // The same with each snow scene's own map (exact, closed form or network), over the chunk list of the
 // last rebuild; for contexts with T.sur_any != 0.
 void enqueue_materialize_map(hipStream_t st, const Launch& L, const Scenes& T, float* S, int64_t cap,
