@@ -27,13 +27,16 @@ constexpr int AOSOA_SHIFT = 6;
 constexpr int AOSOA_B = 1 << AOSOA_SHIFT;
 
 // Index of field f of particle j (cap: the buffer's particle capacity, a
-// multiple of AOSOA_B).
+// multiple of AOSOA_B), as a part common to all particles (the field's
+// start) plus a 32-bit part per particle, so that loads address a uniform
+// base plus a 32-bit offset.
 __host__ __device__ __forceinline__ int64_t sidx(int f, int64_t j, int64_t cap) {
 #if MPM_AOSOA
     (void)cap;
-    return ((j >> AOSOA_SHIFT) * NF + f) * AOSOA_B + (j & (AOSOA_B - 1));
+    const uint32_t jj = (uint32_t)j;
+    return (int64_t)f * AOSOA_B + (int64_t)((jj >> AOSOA_SHIFT) * (uint32_t)(NF * AOSOA_B) + (jj & (AOSOA_B - 1)));
 #else
-    return (int64_t)f * cap + j;
+    return (int64_t)f * cap + (int64_t)(uint32_t)j;
 #endif
 }
 

@@ -82,6 +82,12 @@ __device__ __forceinline__ int pitch_plane(int R, int e1) {
     return q + ((8 - (q & 15)) & 15);
 }
 
+// floor(u / d) for 0 <= u < 2^20 and d >= 1, from rcp = 1/d in FP32 (1 ulp):
+// (u + 1/2) rcp lies within (u + 1/2) 2^-22 / d of (u + 1/2) / d, which is at
+// least 1/(2d) away from every integer, so the truncation is exact while
+// (u + 1/2) 2^-22 < 1/2.  Three instructions instead of an integer division.
+__device__ __forceinline__ int div_small(int u, float rcp) { return (int)(((float)u + 0.5f) * rcp); }
+
 // ------------------------------------------------------------ G2P pieces
 // A chunk's node box (origin lo, extent e per axis, from its P2G tile) as a
 // float4 array tv[x + R y + Q z] of grid velocities (R, Q: the row and plane
@@ -89,8 +95,10 @@ __device__ __forceinline__ int pitch_plane(int R, int e1) {
 // velocities; nt = e0 e1 e2 nodes).
 __device__ __forceinline__ void load_node_box(float4* tv, const float4* vels, int NB, const int lo[3],
                                               const int e[3], int nt, int R, int Q, int tid, int nthreads) {
+    const float r0 = 1.0f / (float)e[0], r01 = 1.0f / (float)(e[0] * e[1]);
     for (int t = tid; t < nt; t += nthreads) {
-        const int x = t % e[0], y = (t / e[0]) % e[1], z = t / (e[0] * e[1]);
+        const int z = div_small(t, r01), t01 = t - z * e[0] * e[1];
+        const int y = div_small(t01, r0), x = t01 - y * e[0];
         const int gx = lo[0] + x, gy = lo[1] + y, gz = lo[2] + z;
         tv[x + R * y + Q * z] = vels[((((gz >> 2) + 1) * NB + ((gy >> 2) + 1)) * NB + ((gx >> 2) + 1)) * 64 +
                                      (gx & 3) + ((gy & 3) << 2) + ((gz & 3) << 4)];

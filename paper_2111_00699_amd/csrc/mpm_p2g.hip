@@ -607,8 +607,10 @@ __device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, con
             __syncthreads();
             float4* slot = stage + off;
             const int e01 = ext[0] * ext[1];
+            const float r01 = 1.0f / (float)(e01 > 0 ? e01 : 1), r0 = 1.0f / (float)(ext[0] > 0 ? ext[0] : 1);
             for (int u = tid; u < nt; u += NT) {  // staged in the tight box layout
-                const int z = u / e01, y = (u - z * e01) / ext[0], xx = u - z * e01 - y * ext[0];
+                const int z = div_small(u, r01), u01 = u - z * e01;
+                const int y = div_small(u01, r0), xx = u01 - y * ext[0];
                 const int t = xx + R * y + Q * z;
                 const long long* ti = reinterpret_cast<const long long*>(tq);
                 const double mu = (double)m_unit;
