@@ -720,7 +720,7 @@ def bench_surrogate(args):
         st1 = sim.stats()
         p2g = sim.profile_read()["p2g"]
         p2g_us = 1e3 * p2g["ms"] / max(p2g["launches"], 1)
-        finals[name] = sim.read_particles()["x"]
+        finals[name] = sim.read_particles()
         done = st1["surrogate_particles"] - st0["surrogate_particles"]
         fb = st1["surrogate_fallbacks"] - st0["surrogate_fallbacks"]
         results[name] = {"ms_per_frame": e0.elapsed_time(e1) / args.steps, "p2g_avg_launch_us": p2g_us,
@@ -732,9 +732,33 @@ def bench_surrogate(args):
         sim.close()
         log(f"[bench] {name}: {results[name]}")
     dx = 1.0 / cfg["n"]
+
+    def kirchhoff(st):
+        """Snow Kirchhoff stress of each particle (FP64): fixed-corotated of F_E with
+        Lame parameters scaled by exp(xi (1 - J_P))."""
+        m = scenes.SNOW
+        F = st["F"].double().cpu().numpy().T.reshape(-1, 3, 3)
+        Jp = st["s"].double().cpu().numpy()
+        U, sig, Vt = np.linalg.svd(F)
+        det = np.linalg.det(F)
+        sig[:, 2] *= np.sign(det)
+        h = np.exp(m["xi"] * (1.0 - Jp))
+        mu0 = m["E"] / (2 * (1 + m["nu"]))
+        la0 = m["E"] * m["nu"] / ((1 + m["nu"]) * (1 - 2 * m["nu"]))
+        J = np.prod(sig, axis=1)
+        d = 2 * (mu0 * h)[:, None] * (sig - 1) * sig + ((la0 * h) * (J - 1) * J)[:, None]
+        U[:, :, 2] *= np.sign(det)[:, None]
+        return np.einsum("nik,nk,njk->nij", U, d, U)
+
+    tau_exact = kirchhoff(finals["exact"])
+    tscale = np.abs(tau_exact).max()
     for name in ("surrogate", "closed_form"):
-        d = (finals[name] - finals["exact"]).norm(dim=0) / dx
+        d = (finals[name]["x"] - finals["exact"]["x"]).norm(dim=0) / dx
         results[name]["position_error_dx"] = {"mean": float(d.mean()), "max": float(d.max())}
+        dt_ = np.abs(kirchhoff(finals[name]) - tau_exact).max(axis=(1, 2))
+        results[name]["stress_error"] = {"max_pa": float(dt_.max()), "p99_pa": float(np.quantile(dt_, 0.99)),
+                                         "mean_pa": float(dt_.mean()), "max_tau_pa": float(tscale),
+                                         "max_rel": float(dt_.max() / tscale)}
     ex = results["exact"]["ms_per_frame"]
     train_tflops = MLP_TRAIN_FLOPS * 16384 * args.train_steps / t_train / 1e12
     out = {
