@@ -225,7 +225,9 @@ double om_sand_alpha(const om_material* m, double q) {
  *   t > 0 (expansion): all elastic strain is released (eps' = 0) and the
  *     hardening state grows by |eps|;
  *   else, with dg = |d| + (3 la + 2 mu)/(2 mu) t alpha(q):
- *     dg <= 0: the state is inside the cone and unchanged;
+ *     dg <= 0: the state is inside the cone and unchanged (Fe = Fhat, so an
+ *       inverted gradient stays inverted: only the two plastic branches
+ *       rebuild the gradient from its singular values);
  *     dg > 0: the deviator shrinks along itself by dg (eps' = eps - dg d/|d|,
  *       the trace, i.e. the volume, is kept) and q grows by dg.
  * Fe = U diag(exp eps') V^T; q_out the new hardening state.                */
@@ -250,7 +252,9 @@ void om_sand_project(const om_material* m, const double Fhat[9], double q, doubl
     } else {
         double dg = nd + (3.0 * la + 2.0 * mu) / (2.0 * mu) * t * om_sand_alpha(m, q);
         if (dg <= 0.0) {
-            for (int k = 0; k < 3; ++k) en[k] = e[k];
+            for (int i = 0; i < 9; ++i) Fe[i] = Fhat[i];
+            *q_out = q;
+            return;
         } else {
             for (int k = 0; k < 3; ++k) en[k] = e[k] - dg * d[k] / nd;
             dq = dg;

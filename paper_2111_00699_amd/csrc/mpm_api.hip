@@ -1088,8 +1088,12 @@ int mpm_get_stats(mpm_ctx* c, mpm_stats* o) {
     o->overflow_blocks = c->step > 0 ? h[CTL_OVF + ((c->parity_ctr - 1) & 1)] : 0;
     o->error = (uint32_t)h[CTL_ERROR];
     o->pending_update = (uint32_t)c->pending;
-    unsigned long long c64[CTL64_WORDS];
-    memcpy(c64, h + CTL_WORDS, sizeof c64);
+    unsigned long long c64[CTL64_WORDS] = {};
+    for (int st = 0; st < CTL64_STRIPES; ++st) {
+        unsigned long long w[CTL64_WORDS];
+        memcpy(w, h + CTL64_BASE + 2 * CTL64_STRIDE * st, sizeof w);
+        for (int k = 0; k < CTL64_WORDS; ++k) c64[k] += w[k];
+    }
     o->p2g_fallback_chunks = (int64_t)c64[CTL64_FALLBACK_CHUNKS];
     o->p2g_global_particles = (int64_t)c64[CTL64_GLOBAL_PARTICLES];
     o->surrogate_particles = (int64_t)c64[CTL64_SUR_PARTICLES];

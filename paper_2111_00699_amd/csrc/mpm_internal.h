@@ -66,17 +66,25 @@ enum Ctl : int {
     CTL_STEP = 11,     // substeps completed (advanced by G2P; stamps the blocks the grid update touched)
     CTL_NGROUP = 12,   // merge groups (2x2x1 block slabs) of the last rebuild
     CTL_WORDS = 16,
-    // 64-bit running counters follow the 16 words (byte offset 64):
+    // 64-bit running counters, kept in CTL64_STRIPES copies a 128-byte line
+    // apart (from byte offset 128): device-scope atomics on one address are
+    // executed one after another (about 9 ns each on MI355X), so the many
+    // waves that count spread their adds over the stripes, and a reader sums
+    // the stripes.
     CTL64_FALLBACK_CHUNKS = 0,     // P2G chunks whose node box did not fit the LDS tile
     CTL64_GLOBAL_PARTICLES = 1,    // particles P2G scattered with global atomics
     CTL64_SUR_PARTICLES = 2,       // snow return maps done by the surrogate / closed-form path
     CTL64_SUR_FALLBACKS = 3,       // ... that fell back to the exact path
     CTL64_WORDS = 4,
-    CTL_ALLOC_WORDS = CTL_WORDS + 2 * CTL64_WORDS
+    CTL64_BASE = 32,               // int offset of stripe 0
+    CTL64_STRIDE = 16,             // 64-bit words per stripe (128 bytes)
+    CTL64_STRIPES = 64,
+    CTL_ALLOC_WORDS = CTL64_BASE + 2 * CTL64_STRIDE * CTL64_STRIPES
 };
 
-__host__ __device__ inline unsigned long long* ctl64(int* ctl) {
-    return reinterpret_cast<unsigned long long*>(ctl + CTL_WORDS);
+// Stripe s of the 64-bit counters (s taken modulo the stripe count).
+__host__ __device__ inline unsigned long long* ctl64(int* ctl, int s = 0) {
+    return reinterpret_cast<unsigned long long*>(ctl + CTL64_BASE) + (s & (CTL64_STRIPES - 1)) * CTL64_STRIDE;
 }
 
 // Derived material constants.
@@ -318,6 +326,16 @@ __device__ __forceinline__ void eig_sym3(float b00, float b01, float b02, float 
     U[0] = u00; U[1] = u01; U[2] = u02;
     U[3] = u10; U[4] = u11; U[5] = u12;
     U[6] = u20; U[7] = u21; U[8] = u22;
+}
+
+// a / b refined by one Newton step on the reciprocal quotient: the library
+// divides by hardware reciprocals (1 ulp), and where the quotient feeds a
+// quantity that must be exact (a = b gives exactly 1) the residual
+// a - q b, exact in an FMA, corrects it.
+__device__ __forceinline__ float div_refined(float a, float b) {
+    const float r = 1.0f / b;
+    const float q = a * r;
+    return fmaf(fmaf(-q, b, a), r, q);
 }
 
 __device__ __forceinline__ float det3(const float A[9]) {

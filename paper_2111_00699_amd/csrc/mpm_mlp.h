@@ -161,22 +161,43 @@ __device__ __forceinline__ void stage_input(const NetLds& L, const float* __rest
     }
 }
 
-// Inference copy of the network for P2G: weights already rounded to BF16
-// (so an A fragment is one 8-byte LDS read), biases and normalisation FP32.
-struct NetLds16 {
-    short W1[64 * 16], W2[64 * 64], W3[16 * 64];
+// Inference copy of the network for P2G: the weights rounded to BF16 once
+// as they are staged, biases and normalisation FP32.  The hidden layers run
+// on gfx950's 16x16x32 BF16 MFMA: a K = 32 fragment of lane (i, g) holds the
+// eight k' = 8g..8g+7, and k' is a permutation of the 32 hidden units of the
+// block chosen so that the B fragment is the D output of the previous layer
+// as it lies in the registers (units 4g..4g+3 of two consecutive 16-unit
+// tiles); the weight rows are stored in that k' order, so an A fragment is
+// one 16-byte LDS read.  Rows are padded to W16_LD so the 16 rows one read
+// instruction touches start in different banks.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4h __attribute__((ext_vector_type(4)));
+constexpr int W16_LD = 72;
+
+struct __attribute__((aligned(16))) NetLds16 {
+    __bf16 W1[64 * 16];      // [unit][feature], the K = 16 first layer
+    __bf16 W2[64 * W16_LD];  // [unit][k'] of the two K = 32 blocks
+    __bf16 W3[16 * W16_LD];  // [output][k'] (outputs padded to 16)
     float b1[64], b2[64], b3[16];
     float imu[16], isd[16], omu[16], osd[16];
 };
 
+// Position k' of hidden unit u in its K = 32 block: unit 32 kb + 16 h + 4 g + r
+// sits at 32 kb + 8 g + 4 h + r.
+__device__ __forceinline__ int kperm(int u) {
+    const int w = u & 31;
+    return (u & 32) + 8 * ((w & 15) >> 2) + 4 * (w >> 4) + (w & 3);
+}
+
 __device__ inline void load_net16(NetLds16& L, const float* __restrict__ th, const float* __restrict__ norm) {
     for (int t = threadIdx.x; t < 64 * 16; t += blockDim.x) {
         const int o = t >> 4, i = t & 15;
-        L.W1[t] = to_bf16(i < SUR_IN ? th[SUR_W1 + o * SUR_IN + i] : 0.0f);
-        const int o3 = t >> 6, i3 = t & 63;
-        L.W3[t] = to_bf16(o3 < SUR_OUT ? th[SUR_W3 + o3 * SUR_H + i3] : 0.0f);
+        L.W1[t] = (__bf16)(i < SUR_IN ? th[SUR_W1 + o * SUR_IN + i] : 0.0f);
+        const int o3 = t >> 6, u = t & 63;
+        L.W3[o3 * W16_LD + kperm(u)] = (__bf16)(o3 < SUR_OUT ? th[SUR_W3 + o3 * SUR_H + u] : 0.0f);
     }
-    for (int t = threadIdx.x; t < 64 * 64; t += blockDim.x) L.W2[t] = to_bf16(th[SUR_W2 + t]);
+    for (int t = threadIdx.x; t < 64 * 64; t += blockDim.x)
+        L.W2[(t >> 6) * W16_LD + kperm(t & 63)] = (__bf16)th[SUR_W2 + t];
     for (int t = threadIdx.x; t < 64; t += blockDim.x) {
         L.b1[t] = th[SUR_B1 + t];
         L.b2[t] = th[SUR_B2 + t];
@@ -190,41 +211,84 @@ __device__ inline void load_net16(NetLds16& L, const float* __restrict__ th, con
     }
 }
 
-__device__ __forceinline__ f32x4 mma16(f32x4 acc, const short* W, int ld, int mt, int kt, const float b[4]) {
-    const int lane = threadIdx.x & 63, i = lane & 15, g = lane >> 4;
-    const bf16x4 a = *reinterpret_cast<const bf16x4*>(W + (16 * mt + i) * ld + 16 * kt + 4 * g);
-    bf16x4 bb;
+// tanh of the four accumulators and their BF16 B-fragment halves
+__device__ __forceinline__ void act_pack(f32x4 a0, f32x4 a1, bf16x8& b) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) bb[j] = to_bf16(b[j]);
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc, 0, 0, 0);
+    for (int r = 0; r < 4; ++r) {
+        b[r] = (__bf16)act_tanh(a0[r]);
+        b[4 + r] = (__bf16)act_tanh(a1[r]);
+    }
 }
 
-// The forward pass of forward_tile with the BF16 inference copy (y: normalised outputs).
-__device__ __forceinline__ void forward_tile16(const NetLds16& L, const float* xin, float y[4]) {
-    const int lane = threadIdx.x & 63, g = lane >> 4, s = lane & 15;
-    float xb[4], h1[4][4], h2[4][4];
+// Forward pass of the wave's 64 samples, one per lane: xn the lane's
+// normalised inputs, yn its normalised outputs.  stage: FWD_STAGE floats of
+// LDS owned by the wave, 16-byte aligned (the rows move as 16-byte vectors),
+// the inputs as BF16 rows [64][16] in the first 512
+// and the outputs [64][12] after them.  The four 16-sample tiles run one
+// after the other with no barrier between them (the four output tiles of a
+// layer are independent MFMA chains).
+constexpr int FWD_STAGE = 512 + 64 * SUR_OUT;
+
+__device__ __forceinline__ void forward_wave16(const NetLds16& L, float* stage, const float xn[SUR_IN],
+                                               float yn[SUR_OUT]) {
+    static_assert(SUR_OUT == 12, "the output rows are three float4");
+    const int lane = threadIdx.x & 63, g = lane >> 4, i = lane & 15;
+    __bf16* xs = reinterpret_cast<__bf16*>(stage);
+    float* ys = stage + 512;
+    {
+        bf16x8 r0, r1;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) xb[j] = xin[s * 16 + 4 * g + j];
+        for (int j = 0; j < 8; ++j) r0[j] = (__bf16)xn[j];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mma16(acc, L.W1, 16, mt, 0, xb);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) h1[mt][r] = act_tanh(acc[r] + L.b1[16 * mt + 4 * g + r]);
+        for (int j = 0; j < 8; ++j) r1[j] = (__bf16)(8 + j < SUR_IN ? xn[8 + j] : 0.0f);
+        *reinterpret_cast<bf16x8*>(xs + lane * 16) = r0;
+        *reinterpret_cast<bf16x8*>(xs + lane * 16 + 8) = r1;
     }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll 1
+    for (int t = 0; t < 4; ++t) {
+        // the weights are read again for every tile rather than held in registers
+        // across the four (they would take some 80 VGPRs from the caller)
+        asm volatile("" ::: "memory");
+        // B fragment of the first layer: features 4g..4g+3 of sample 16t + i
+        const bf16x4h xb = *reinterpret_cast<const bf16x4h*>(xs + (16 * t + i) * 16 + 4 * g);
+        f32x4 h[4];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int mt = 0; mt < 4; ++mt) {
+            const bf16x4h a = *reinterpret_cast<const bf16x4h*>(L.W1 + (16 * mt + i) * 16 + 4 * g);
+            h[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(bf16x4, a),
+                                                               __builtin_bit_cast(bf16x4, xb),
+                                                               *reinterpret_cast<const f32x4*>(L.b1 + 16 * mt + 4 * g),
+                                                               0, 0, 0);
+        }
+        bf16x8 hb[2];
+        act_pack(h[0], h[1], hb[0]);
+        act_pack(h[2], h[3], hb[1]);
 #pragma unroll
-        for (int kt = 0; kt < 4; ++kt) acc = mma16(acc, L.W2, 64, mt, kt, h1[kt]);
+        for (int mt = 0; mt < 4; ++mt) {
+            f32x4 acc = *reinterpret_cast<const f32x4*>(L.b2 + 16 * mt + 4 * g);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) h2[mt][r] = act_tanh(acc[r] + L.b2[16 * mt + 4 * g + r]);
+            for (int kb = 0; kb < 2; ++kb) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(L.W2 + (16 * mt + i) * W16_LD + 32 * kb + 8 * g);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, hb[kb], acc, 0, 0, 0);
+            }
+            h[mt] = acc;
+        }
+        act_pack(h[0], h[1], hb[0]);
+        act_pack(h[2], h[3], hb[1]);
+        f32x4 acc = *reinterpret_cast<const f32x4*>(L.b3 + 4 * g);
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(L.W3 + i * W16_LD + 32 * kb + 8 * g);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, hb[kb], acc, 0, 0, 0);
+        }
+        // outputs 4g..4g+3 of sample 16t + i (g = 3 holds the padding outputs)
+        if (g < 3) *reinterpret_cast<f32x4*>(ys + (16 * t + i) * SUR_OUT + 4 * g) = acc;
     }
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int kt = 0; kt < 4; ++kt) acc = mma16(acc, L.W3, 64, 0, kt, h2[kt]);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) y[r] = acc[r] + L.b3[4 * g + r];
+    for (int o = 0; o < SUR_OUT; ++o) yn[o] = ys[lane * SUR_OUT + o];
+    __builtin_amdgcn_wave_barrier();
 }
 
 }  // namespace mlp

@@ -139,30 +139,19 @@ __device__ void snow_without_svd(const mlp::NetLds16* net, float* stage, const S
     for (int k = 0; k < 3; ++k) sh[k] = use ? sqrtf(fmaxf(q + p * mu[k], 1e-30f)) : 1.0f;
     const float Jp = use ? s : 1.0f;
     if (NET && pending && __ballot(use) != 0ull) {  // a wave with no eligible lane skips the network
-        // features [s, ln s, J_P, ln J_P, h, dt/dt_ref, s1 s2 s3, 1], one 16-sample tile at a time
-        float xf[SUR_IN] = {sh[0], sh[1], sh[2], logf(sh[0]), logf(sh[1]), logf(sh[2]), Jp, logf(Jp),
-                            expf(M.xi * (1.0f - Jp)), dt / T.sur_dt_ref, sh[0] * sh[1] * sh[2], 1.0f};
-        const int lane = threadIdx.x & 63, g = lane >> 4, sl = lane & 15;
-        float* xs = stage;        // [16][16]
-        float* ys = stage + 256;  // [16][16]
-        float yv[SUR_OUT];
-        for (int t = 0; t < 4; ++t) {
-            if ((lane >> 4) == t) {
+        // features [s, ln s, J_P, ln J_P, h, dt/dt_ref, s1 s2 s3, 1], the wave's 64 samples at once.
+        // dt/dt_ref is exactly 1 at the training step (a refined division): a feature that was
+        // constant in training has a floored spread (1e-6), so one ulp off would move its
+        // normalised value by 0.06 and the J_P output by about 4e-4.
+        const float dtr = div_refined(dt, T.sur_dt_ref);
+        const float xf[SUR_IN] = {sh[0], sh[1], sh[2], logf(sh[0]), logf(sh[1]), logf(sh[2]), Jp, logf(Jp),
+                                  expf(M.xi * (1.0f - Jp)), dtr, sh[0] * sh[1] * sh[2], 1.0f};
+        float xn[SUR_IN], yv[SUR_OUT];
 #pragma unroll
-                for (int f = 0; f < 16; ++f) xs[sl * 16 + f] = f < SUR_IN ? (xf[f] - net->imu[f]) / net->isd[f] : 0.0f;
-            }
-            __builtin_amdgcn_wave_barrier();
-            float y[4];
-            mlp::forward_tile16(*net, xs, y);
+        for (int f = 0; f < SUR_IN; ++f) xn[f] = (xf[f] - net->imu[f]) / net->isd[f];
+        mlp::forward_wave16(*net, stage, xn, yv);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) ys[sl * 16 + 4 * g + r] = y[r];
-            __builtin_amdgcn_wave_barrier();
-            if ((lane >> 4) == t) {
-#pragma unroll
-                for (int o = 0; o < SUR_OUT; ++o) yv[o] = ys[sl * 16 + o] * net->osd[o] + net->omu[o];
-            }
-            __builtin_amdgcn_wave_barrier();
-        }
+        for (int o = 0; o < SUR_OUT; ++o) yv[o] = yv[o] * net->osd[o] + net->omu[o];
         // outputs [s', ln(s'/s), tau/E, J_P'/J_P, h', s1's2's3']: the projected state comes from
         // ln(s'/s) and J_P'/J_P; the stress is evaluated from that state, and the network's own
         // stress outputs serve as a consistency check
@@ -268,7 +257,7 @@ __device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, con
 #endif
     struct Empty {};
     __shared__ typename std::conditional<SURM == 2, mlp::NetLds16, Empty>::type net;
-    __shared__ float sur_stage[SURM == 2 ? NT / 64 * 512 : 1];
+    __shared__ __attribute__((aligned(16))) float sur_stage[SURM == 2 ? NT / 64 * mlp::FWD_STAGE : 1];
     if constexpr (SURM == 2) {
         if (T.sur_theta) mlp::load_net16(net, T.sur_theta, T.sur_norm);
         __syncthreads();
@@ -362,7 +351,7 @@ __device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, con
                 bool fb = false;
                 if constexpr (SURM == 2) {
                     if (sc.ret == 1)
-                        snow_without_svd<true>(&net, sur_stage + wv * 512, T, sc, dt, pending, have, C, F, s, tau, fb);
+                        snow_without_svd<true>(&net, sur_stage + wv * mlp::FWD_STAGE, T, sc, dt, pending, have, C, F, s, tau, fb);
                     else
                         snow_without_svd<false>(&net, sur_stage, T, sc, dt, pending, have, C, F, s, tau, fb);
                 } else {  // no network in this variant
@@ -474,7 +463,7 @@ __device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, con
             // no room in the tile or in this workgroup's staging slice: the chunk goes to global atomics
             if (Q * ext[2] > CT || used + nt > slice) nt = -1;
             if (!ch.tile) nt = -1;  // a registration list was full at the rebuild
-            if (nt < 0 && tid == 0) atomicAdd(&ctl64(ctl)[CTL64_FALLBACK_CHUNKS], 1ull);
+            if (nt < 0 && tid == 0) atomicAdd(&ctl64(ctl, blockIdx.x)[CTL64_FALLBACK_CHUNKS], 1ull);
             off = slice0 + used;
             if (nt > 0) used += nt;
             // (the tile is all zero here: cleared at the start, and every node a chunk touched is
@@ -488,7 +477,8 @@ __device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, con
         // ---- phase 2: scatter
         {
             const unsigned long long g = __ballot(have && ok && (GLOBAL_ONLY || !in_zone || nt <= 0));
-            if (g && lane == 0) atomicAdd(&ctl64(ctl)[CTL64_GLOBAL_PARTICLES], (unsigned long long)__popcll(g));
+            if (g && lane == 0)
+                atomicAdd(&ctl64(ctl, blockIdx.x * (NT / 64) + wv)[CTL64_GLOBAL_PARTICLES], (unsigned long long)__popcll(g));
             // in-zone particles that lost the tile: a rebuild would shrink their chunk's box again
             const unsigned long long fb = __ballot(have && ok && !GLOBAL_ONLY && in_zone && nt <= 0);
             if (fb && lane == 0) atomicAdd(&ctl[CTL_FB + parity], (int)__popcll(fb));
@@ -632,8 +622,9 @@ __device__ __forceinline__ void p2g_body(float* __restrict__ S, int64_t cap, con
     }
     if (err) atomicOr(&ctl[CTL_ERROR], (int)err);
     if (SURM != 0 && (threadIdx.x & 63) == 0) {
-        if (n_sur) atomicAdd(&ctl64(ctl)[CTL64_SUR_PARTICLES], (unsigned long long)n_sur);
-        if (n_fb) atomicAdd(&ctl64(ctl)[CTL64_SUR_FALLBACKS], (unsigned long long)n_fb);
+        unsigned long long* c64 = ctl64(ctl, blockIdx.x * (NT / 64) + (threadIdx.x >> 6));
+        if (n_sur) atomicAdd(&c64[CTL64_SUR_PARTICLES], (unsigned long long)n_sur);
+        if (n_fb) atomicAdd(&c64[CTL64_SUR_FALLBACKS], (unsigned long long)n_fb);
     }
 }
 
@@ -649,7 +640,7 @@ __global__ __launch_bounds__(NT) void k_materialize_map(float* __restrict__ S, i
                                                         Scenes T) {
     struct Empty {};
     __shared__ typename std::conditional<SURM == 2, mlp::NetLds16, Empty>::type net;
-    __shared__ float sur_stage[SURM == 2 ? NT / 64 * 512 : 1];
+    __shared__ __attribute__((aligned(16))) float sur_stage[SURM == 2 ? NT / 64 * mlp::FWD_STAGE : 1];
     if constexpr (SURM == 2) {
         if (T.sur_theta) mlp::load_net16(net, T.sur_theta, T.sur_norm);
         __syncthreads();
@@ -673,7 +664,7 @@ __global__ __launch_bounds__(NT) void k_materialize_map(float* __restrict__ S, i
         if (sc.ret != 0 && M.kind == MPM_SNOW) {  // uniform over the workgroup
             if constexpr (SURM == 2) {
                 if (sc.ret == 1)
-                    snow_without_svd<true>(&net, sur_stage + wv * 512, T, sc, sc.P.dt, 1, have, C, F, s, tau, fb);
+                    snow_without_svd<true>(&net, sur_stage + wv * mlp::FWD_STAGE, T, sc, sc.P.dt, 1, have, C, F, s, tau, fb);
                 else
                     snow_without_svd<false>(&net, sur_stage, T, sc, sc.P.dt, 1, have, C, F, s, tau, fb);
             } else {

@@ -57,34 +57,29 @@ __global__ __launch_bounds__(SW) void k_sur_forward(const float* __restrict__ th
 }
 
 // Y = network(X) with the BF16 inference copy of the network: the weights
-// rounded to BF16 once as they are staged (NetLds16) and the 16-sample tile
-// forward pass P2G runs (forward_tile16), with P2G's input normalisation.
+// rounded to BF16 once as they are staged (NetLds16) and the wave-wide
+// forward pass P2G runs (forward_wave16, 64 samples a wave), with P2G's
+// input normalisation.
 __global__ __launch_bounds__(SW) void k_sur_forward16(const float* __restrict__ th, const float* __restrict__ norm,
                                                       const float* __restrict__ X, int64_t count,
                                                       float* __restrict__ Y) {
     __shared__ NetLds16 L;
-    __shared__ float xin[SW / 64][16 * 16];
+    __shared__ __attribute__((aligned(16))) float stage[SW / 64][FWD_STAGE];
     load_net16(L, th, norm);
     __syncthreads();
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, s = lane & 15;
-    const int64_t tiles = (count + 15) / 16;
-    for (int64_t t = (int64_t)blockIdx.x * (SW / 64) + w; t < tiles; t += (int64_t)gridDim.x * (SW / 64)) {
-        const int64_t row = 16 * t + s;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t groups = (count + 63) / 64;
+    for (int64_t t = (int64_t)blockIdx.x * (SW / 64) + w; t < groups; t += (int64_t)gridDim.x * (SW / 64)) {
+        const int64_t row = 64 * t + lane;
         const bool valid = row < count;
+        float xn[SUR_IN], yn[SUR_OUT];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {  // lane group g stages features 4g..4g+3 of sample s
-            const int f = 4 * g + j;
-            xin[w][s * 16 + f] = (valid && f < SUR_IN) ? (X[row * SUR_IN + f] - L.imu[f]) / L.isd[f] : 0.0f;
-        }
-        __builtin_amdgcn_wave_barrier();
-        float y[4];
-        forward_tile16(L, xin[w], y);
+        for (int f = 0; f < SUR_IN; ++f) xn[f] = valid ? (X[row * SUR_IN + f] - L.imu[f]) / L.isd[f] : 0.0f;
+        forward_wave16(L, stage[w], xn, yn);
+        if (valid) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int o = 4 * g + r;
-            if (valid && o < SUR_OUT) Y[row * SUR_OUT + o] = y[r] * L.osd[o] + L.omu[o];
+            for (int o = 0; o < SUR_OUT; ++o) Y[row * SUR_OUT + o] = yn[o] * L.osd[o] + L.omu[o];
         }
-        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -326,14 +321,15 @@ __global__ __launch_bounds__(SW) void k_sur_indices(uint64_t seed, int step, int
 
 // Training pairs: the trial state of each particle of `scene` (the deferred
 // update applied when `pending`) through the exact snow return map, written
-// as feature and target rows (compacted with a counter; rows of inverted
-// particles are skipped).
+// as feature and target rows (compacted with a counter, one atomic add per
+// wave for the wave's rows; rows of inverted particles are skipped).
 __global__ __launch_bounds__(SW) void k_sur_sample(const float* __restrict__ S, int64_t cap, int N, Scenes T,
                                                    int scene, int pending, float E, float dt_ref, int64_t max_rows,
                                                    float* __restrict__ X, float* __restrict__ Y,
                                                    unsigned long long* __restrict__ counter) {
-    const int j = blockIdx.x * SW + threadIdx.x;
-    if (j >= N || fsid_scene(S[sidx(FSID, j, cap)]) != scene) return;
+    const int j0 = blockIdx.x * SW + threadIdx.x;
+    bool ok = j0 < N && fsid_scene(S[sidx(FSID, j0 < N ? j0 : 0, cap)]) == scene;
+    const int j = ok ? j0 : 0;
     const Scene& sc = T.scene[scene];
     const Mat& M = sc.M;
     float C[9], F[9], Fh[9];
@@ -355,7 +351,16 @@ __global__ __launch_bounds__(SW) void k_sur_sample(const float* __restrict__ S, 
     if (a < b) { t = a; a = b; b = t; }
     if (b < c) { t = b; b = c; c = t; }
     if (a < b) { t = a; a = b; b = t; }
-    if (!(c > 0.0f) || !(Jp > 0.0f)) return;
+    ok = ok && c > 0.0f && Jp > 0.0f;
+    // the wave's rows take consecutive slots from one add to the counter
+    const unsigned long long m = __ballot(ok);
+    if (m == 0ull) return;
+    const int lane = threadIdx.x & 63, first = __ffsll((long long)m) - 1;
+    unsigned long long base = 0;
+    if (lane == first) base = atomicAdd(counter, (unsigned long long)__popcll(m));
+    base = ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(base >> 32), first) << 32) |
+           (unsigned)__builtin_amdgcn_readlane((int)(unsigned)base, first);
+    if (!ok) return;
     const float s[3] = {a, b, c};
     float sn[3];
 #pragma unroll
@@ -363,7 +368,7 @@ __global__ __launch_bounds__(SW) void k_sur_sample(const float* __restrict__ S, 
     const float Js = s[0] * s[1] * s[2], Jn = sn[0] * sn[1] * sn[2];
     const float Jpn = Jp * Js / Jn;
     const float hn = expf(M.xi * (1.0f - Jpn));
-    const unsigned long long r = atomicAdd(counter, 1ull);
+    const unsigned long long r = base + (unsigned long long)__popcll(m & ((1ull << lane) - 1ull));
     if ((int64_t)r >= max_rows) return;
     float* x = X + r * SUR_IN;
     float* y = Y + r * SUR_OUT;
@@ -378,7 +383,7 @@ __global__ __launch_bounds__(SW) void k_sur_sample(const float* __restrict__ S, 
     x[6] = Jp;
     x[7] = logf(Jp);
     x[8] = expf(M.xi * (1.0f - Jp));
-    x[9] = sc.P.dt / dt_ref;
+    x[9] = div_refined(sc.P.dt, dt_ref);  // as P2G computes it (exactly 1 at dt_ref)
     x[10] = Js;
     x[11] = 1.0f;
     y[9] = Jpn / Jp;
@@ -404,10 +409,13 @@ void sur_forward(hipStream_t st, int bf16, const float* th, const float* norm, c
     if (count <= 0) return;
     const int64_t tiles = (count + 15) / 16;
     const int grid = (int)((tiles + 3) / 4 < 4096 ? (tiles + 3) / 4 : 4096);
-    if (bf16)  // the inference path P2G runs
-        hipLaunchKernelGGL(k_sur_forward16, dim3(grid), dim3(SW), 0, st, th, norm, X, count, Y);
-    else
+    if (bf16) {  // the inference path P2G runs
+        const int64_t groups = (count + 63) / 64;
+        const int g16 = (int)((groups + 3) / 4 < 4096 ? (groups + 3) / 4 : 4096);
+        hipLaunchKernelGGL(k_sur_forward16, dim3(g16), dim3(SW), 0, st, th, norm, X, count, Y);
+    } else {
         hipLaunchKernelGGL(k_sur_forward<false>, dim3(grid), dim3(SW), 0, st, th, norm, X, count, Y);
+    }
 }
 
 void sur_grad(hipStream_t st, int bf16, const float* th, const float* norm, const float* X, const float* T,

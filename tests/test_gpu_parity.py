@@ -291,6 +291,38 @@ def test_sand_return_map_cases_on_gpu(torch_cuda, oracle):
     assert min(tip.sum(), cone.sum(), inside.sum()) > N // 10, (tip.sum(), cone.sum(), inside.sum())
 
 
+def test_sand_inverted_gradients_on_gpu(torch_cuda, oracle):
+    """Sand with every fifth gradient inverted (one column negated): inside
+    the cone the map keeps the trial gradient, inverted, on both sides; on
+    the cone and in expansion both rebuild it from |sig|.  Three substeps, so
+    the kept sign feeds the next substep's map."""
+    sc = scenes.jelly_cube(0)
+    st = scenes.nontrivial_state(sc["x"], seed=31, kind="sand")
+    F = st["F"].astype(np.float64)
+    F = np.eye(3).reshape(9, 1) + 2.0 * (F - np.eye(3).reshape(9, 1))
+    inv = np.arange(F.shape[1]) % 5 == 0
+    for k in (2, 5, 8):
+        F[k, inv] = -F[k, inv]
+    st["F"] = F.astype(np.float32)
+    N = F.shape[1]
+    assert np.all(np.linalg.det(st["F"].astype(np.float64).T.reshape(N, 3, 3))[inv] < 0)
+    cfg = dict(n=64, dt=2e-4, bc="slip")
+    print_case("sand_inverted", N=N, inverted=int(inv.sum()))
+    sim = make_sim(torch_cuda, cfg)
+    sim.add_particles(scenes.SAND, st["x"], v=st["v"], C=st["C"], F=st["F"], s=st["s"])
+    sim.substep(3)
+    gs = gpu_state(sim)
+    sim.close()
+    os_, _, _, bad = oracle.substep(cfg, scenes.SAND, st, steps=3)
+    assert bad == 0
+    compare_state(gs, os_, "sand", n=64)
+    det = np.linalg.det(os_["F"].T.reshape(N, 3, 3))
+    kept = inv & (det < 0)
+    # both branches occur among the inverted particles
+    assert kept.sum() > inv.sum() // 10 and (inv & (det > 0)).sum() > inv.sum() // 10, (kept.sum(), inv.sum())
+    assert np.all(np.sign(np.linalg.det(gs["F"].astype(np.float64).T.reshape(N, 3, 3))) == np.sign(det))
+
+
 def test_sand_blocks_substeps(torch_cuda, oracle):
     """The Sand Blocks layout (4 boxes of 12^3 cells, 55,296 particles) at the
     paper's time step, from a non-trivial state, 6 substeps on the slip box."""

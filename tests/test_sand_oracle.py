@@ -126,18 +126,27 @@ def test_return_map_cases(oracle):
 
 
 def test_inverted_gradient_is_taken_without_its_sign(oracle):
-    """An inverted trial gradient is mapped like its reflection: the result
-    has positive determinant and the stress uses log |sig|."""
+    """An inverted trial gradient: the stress uses log |sig| (that of its
+    reflection); inside the cone the map leaves it as it is (still inverted),
+    and on the cone or in expansion it is rebuilt from |sig| like its
+    reflection, coming out with a positive determinant."""
     P, Q = rot(1500), rot(1501)
-    sig = np.array([1.02, 0.97, 0.9])
-    Fh = P @ np.diag(sig * [1, 1, -1]) @ Q.T
-    Fr = P @ np.diag(sig) @ Q.T
-    Fe, q = oracle.sand_project(SAND, Fh, 0.2)
-    Fer, qr = oracle.sand_project(SAND, Fr, 0.2)
-    assert np.linalg.det(Fh) < 0 and np.linalg.det(Fe) > 0
-    assert np.allclose(Fe, Fer, atol=1e-12) and abs(q - qr) < 1e-12
     mu, la = lame(SAND["E"], SAND["nu"])
-    assert np.allclose(oracle.hencky(Fh, mu, la), oracle.hencky(Fr, mu, la), atol=1e-9)
+    # inside the cone (dg < 0 at q = 0.2), on it, and in expansion
+    for sig, case in (([1.02, 0.97, 0.9], "inside"), ([1.1, 0.93, 0.85], "cone"), ([1.05, 1.02, 1.01], "tip")):
+        sig = np.array(sig)
+        Fh = P @ np.diag(sig * [1, 1, -1]) @ Q.T
+        Fr = P @ np.diag(sig) @ Q.T
+        Fe, q = oracle.sand_project(SAND, Fh, 0.2)
+        Fer, qr = oracle.sand_project(SAND, Fr, 0.2)
+        assert np.linalg.det(Fh) < 0
+        assert abs(q - qr) < 1e-12
+        if case == "inside":
+            assert q == 0.2 and np.array_equal(Fe, Fh) and np.array_equal(Fer, Fr)
+        else:
+            assert q > 0.2 and np.linalg.det(Fe) > 0
+            assert np.allclose(Fe, Fer, atol=1e-12)
+        assert np.allclose(oracle.hencky(Fh, mu, la), oracle.hencky(Fr, mu, la), atol=1e-9)
 
 
 def test_sand_substep_moves_hardening_only_where_plastic(oracle):
