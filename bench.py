@@ -15,9 +15,10 @@ the K timed frames (inputs resident in HBM before timing starts).
 `roofline` covers the P2G kernel, timed with HIP events on the library's
 stream during the timed frames, against the HBM peak (`frac` from the
 algorithmic bytes, `traffic_frac` from the measured HBM bytes);
-`roofline_lds` puts the same launches against the LDS 64-bit atomic rate that
-bounds them; `cpu_baseline` times the FP64 oracle on the host on a bounded
-sample.  The other workloads print their own line: the fountain (ms per
+`roofline_valu` puts them against the VALU issue rate (the kernel's counted
+instructions at full issue: the bound it actually meets), `roofline_lds`
+against the LDS 64-bit atomic rate; `cpu_baseline` times the FP64 oracle on
+the host on a bounded sample.  The other workloads print their own line: the fountain (ms per
 frame against the growing particle count), 256 batched scenes, and the
 learned constitutive map.
 """
@@ -71,21 +72,30 @@ SUBSTEP_BYTES = {m: P2G_BYTES[m] + G2P_BYTES for m in P2G_BYTES}
 # The figure belongs to the P2G sources whose hash is stored beside it: after
 # any change to them the bench reports traffic as null until it is measured
 # again.
-P2G_TRAFFIC = {"kernel": "p2g_fused", "sources_sha256_16": "2546c4e795846aa6", "bytes": 195.75e6}
+P2G_TRAFFIC = {"kernel": "p2g_fused", "sources_sha256_16": "52105fc774076c52", "bytes": 194.42e6,
+               # SQ_INSTS_VALU per launch (wave instructions), same runs and sources
+               "valu_wave_instructions": 51.12e6}
+# VALU issue peak of gfx950: 256 CUs x 4 SIMDs, a wave64 VALU instruction
+# every 4 cycles per SIMD, at 2.4 GHz.
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 P2G_SOURCES = ("paper_2111_00699_amd/csrc/mpm_p2g.hip", "paper_2111_00699_amd/csrc/mpm_internal.h",
                "paper_2111_00699_amd/csrc/mpm_kernels.h", "paper_2111_00699_amd/csrc/mpm_api.hip",
                "paper_2111_00699_amd/build.py")
 
 
-def p2g_traffic_bytes(kernel):
+def p2g_counters_valid(kernel):
+    """Whether the stored P2G counter figures belong to these sources and kernel."""
     import hashlib
 
     h = hashlib.sha256()
     for f in P2G_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    ok = h.hexdigest()[:16] == P2G_TRAFFIC["sources_sha256_16"] and kernel == P2G_TRAFFIC["kernel"]
-    return P2G_TRAFFIC["bytes"] if ok else None
+    return h.hexdigest()[:16] == P2G_TRAFFIC["sources_sha256_16"] and kernel == P2G_TRAFFIC["kernel"]
+
+
+def p2g_traffic_bytes(kernel):
+    return P2G_TRAFFIC["bytes"] if p2g_counters_valid(kernel) else None
 
 
 def log(msg):
@@ -99,7 +109,7 @@ def oracle_threads():
     return int(env) if env.isdigit() and int(env) > 0 else len(os.sched_getaffinity(0))
 
 
-def cpu_baseline(sc, cfg, serial_steps=3, threaded_steps=5):
+def cpu_baseline(sc, cfg, serial_steps=5, threaded_steps=40):
     """The FP64 oracle on the host cores, on bounded samples of the snow
     scene: the serial oracle on one thread and its multi-threaded form on
     every host thread this process may use, each from the frame-0 state (at
@@ -923,7 +933,14 @@ def main():
                      "bytes_basis": "per particle-substep state traffic of P2G + G2P (snow: 212 B)",
                      "kernel_bytes_per_particle": kernel_bytes,
                      "kernel_bytes_frac": kernel_bytes * N / (p2g_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
-        # the bound P2G actually meets: its LDS atomics against their measured peak rate
+        # the VALU issue bound: the launch's counted wave instructions at full issue against the
+        # live launch time (null once the sources differ from the counted ones)
+        "roofline_valu": ({"kernel": "p2g_fused", "bound": "valu_issue",
+                           "wave_instructions_per_launch": P2G_TRAFFIC["valu_wave_instructions"],
+                           "floor_us": P2G_TRAFFIC["valu_wave_instructions"] / VALU_ISSUE_PEAK * 1e6,
+                           "frac": P2G_TRAFFIC["valu_wave_instructions"] / VALU_ISSUE_PEAK / (p2g_avg_ms * 1e-3)}
+                          if fused and p2g_counters_valid("p2g_fused") else None),
+        # the LDS 64-bit atomics of the same launches against their measured peak rate
         "roofline_lds": {"kernel": "p2g_fused" if fused else "p2g", "bound": "lds_u64_atomics",
                          "achieved": P2G_LDS_ATOMICS_PER_PARTICLE * N / (p2g_avg_ms * 1e-3),
                          "peak": LDS_U64_ATOMIC_PEAK, "unit": "lane-ops/s",
