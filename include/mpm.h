@@ -75,12 +75,19 @@ typedef enum { MPM_BC_STICKY = 0, MPM_BC_SLIP = 1, MPM_BC_SEPARATE = 2 } mpm_bc;
                                             copy of the chunk's node box */
 #define MPM_FLAG_P2G_SORTED_LANES 0x8u   /* store each chunk in plain sorted order instead of the
                                             order that deals it over the LDS passes by bank */
-#define MPM_FLAG_FRAME_GRAPHS 0x20u      /* mpm_frame records a whole frame (one rebuild at its start, then
-                                            every scene's substeps) as a HIP graph per particle-buffer
-                                            parity and replays it; within a frame the free-zone flag is not
-                                            read (particles that leave their zone transfer through global
-                                            atomics).  Needs config.stream != 0.  A graph is recorded again
-                                            after mpm_add_particles, a new frame_dt or a new chunk size. */
+#define MPM_FLAG_FRAME_GRAPHS 0x20u      /* mpm_frame replays a whole frame (every scene's substeps, G2P
+                                            inside the next P2G) as a HIP graph: four recordings, by
+                                            particle-buffer parity and with or without a rebuild at the
+                                            frame's start, picked from the rebuild request the previous
+                                            frame left and from the exit horizon: the substeps before a
+                                            particle could move 3 cells at the mean particle speed and
+                                            the gravity (reduced at the end of each graph frame).  Within
+                                            a graph frame the free-zone flag is not acted on (a particle that leaves its
+                                            zone transfers through global atomics until the next frame);
+                                            when the horizon is shorter than the frame, the frame runs
+                                            directly instead.  Needs config.stream != 0.  The graphs are
+                                            recorded again after mpm_add_particles, a new frame_dt or a
+                                            new chunk size.                                            */
 #define MPM_FLAG_FUSED_G2P 0x40u        /* run each substep's G2P inside the next substep's P2G (the
                                             default; see mpm_substep)                                  */
 #define MPM_FLAG_SEPARATE_G2P 0x80u     /* never: every substep launches its own G2P               */
@@ -205,8 +212,8 @@ int mpm_add_particles(mpm_ctx* ctx, int32_t scene, const mpm_material* mat, int6
  * per phase for all scenes.  A substep's G2P runs inside the next substep's
  * P2G launch (paper, "Merge Kernels": G2P2G) unless MPM_FLAG_SEPARATE_G2P,
  * MPM_FLAG_P2G_GLOBAL_ATOMICS,
- * MPM_FLAG_REBUILD_EVERY_STEP, MPM_FLAG_G2P_GLOBAL_GATHER,
- * MPM_FLAG_FRAME_GRAPHS or a learned / closed-form return map is in use.
+ * MPM_FLAG_REBUILD_EVERY_STEP, MPM_FLAG_G2P_GLOBAL_GATHER, ASFLIP or a
+ * learned / closed-form return map is in use.
  * Calls that read, extend, sample or rebuild the state run the outstanding
  * G2P first, so what they see does not change.  The host waits for the
  * device only to keep at most `lag` substeps in flight, so that it can read

@@ -112,7 +112,9 @@ struct mpm_ctx {
     // ASFLIP (mpm_set_transfer) and the automatic frame time step (mpm_set_auto_dt)
     bool any_flip = false;
     float auto_cfl = 0.0f, auto_dt_max = 0.0f;
-    float* speed_dev = nullptr;  // one word: the largest particle speed, by mpm_frame with auto_cfl > 0
+    float* speed_dev = nullptr;  // [0..1]: the largest particle speed and the sum of speeds (auto dt,
+                                 // exit horizon); [2..3]: the same, reduced at the end of each graph frame
+    bool graph_speed = false;    // ring[RING + 1 ..] holds the speeds at the end of the last frame
 
     // profiling
     uint32_t prof_mask = 0;
@@ -498,14 +500,13 @@ int check_error_word(mpm_ctx* c) {
 // misses beyond that on its GPU); on gfx950 with the fixed-point tile it
 // saves 8-10% of a frame at 6.6K-99K particles and 3% at 1.28M, so it is
 // the default at every size.
-// G2P may run inside the next substep's P2G (in_graph: inside a graph frame,
-// which fuses within the frame).
-bool fusion_allowed(const mpm_ctx* c, bool in_graph = false) {
+// G2P may run inside the next substep's P2G (graph frames fuse within the
+// frame and end with the G2P done).
+bool fusion_allowed(const mpm_ctx* c) {
     const bool wanted = (c->cfg.flags & MPM_FLAG_FUSED_G2P) || !(c->cfg.flags & MPM_FLAG_SEPARATE_G2P);
     return wanted && !c->sur_any && !c->any_flip &&
            !(c->cfg.flags & (MPM_FLAG_P2G_GLOBAL_ATOMICS | MPM_FLAG_REBUILD_EVERY_STEP |
-                             MPM_FLAG_G2P_GLOBAL_GATHER)) &&
-           (in_graph || !(c->cfg.flags & MPM_FLAG_FRAME_GRAPHS));
+                             MPM_FLAG_G2P_GLOBAL_GATHER));
 }
 
 // Grid-update passes run as launches of their own (the kernel-merging
@@ -547,6 +548,7 @@ int bring_up_to_date(mpm_ctx* c) {
 int substep_one(mpm_ctx* c, int act) {
     int r = settle_graph_frame(c);
     if (r) return r;
+    c->graph_speed = false;  // the state moves on from the last graph frame's end
     if ((r = poll_flags(c, c->step - c->cfg.lag))) return r;
     int slot;
     const bool rebuild = c->need_rebuild || (c->cfg.flags & MPM_FLAG_REBUILD_EVERY_STEP);
@@ -603,7 +605,7 @@ int record_frame_graph(mpm_ctx* c, int cur, bool rebuild, float frame_dt, const 
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (g.graph) (void)hipGraphDestroy(g.graph);
     g = FrameGraph{};
-    const bool fuse = fusion_allowed(c, true);
+    const bool fuse = fusion_allowed(c);
     int* flag = c->ring_dev + RING;
     HIP_OK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     if (rebuild)
@@ -628,6 +630,8 @@ int record_frame_graph(mpm_ctx* c, int cur, bool rebuild, float frame_dt, const 
     if (fuse)  // every scene's last substep of the frame
         enqueue_g2p(c->stream, c->L, T, c->S[buf], c->cap, c->B.chunks, c->ctl, c->G, flag, lds_box,
                     (ns[0] - 1) & 1, fb_limit(c), c->cfg.chunk, active_ranks(ns, 0), 1);
+    // the speeds the next frame's exit horizon starts from
+    enqueue_speeds_to_host(c->stream, c->S[buf], c->cap, (int)c->N, c->speed_dev + 2, c->ring_dev + RING + 1);
     hipGraph_t graph = nullptr;
     const hipError_t e1 = hipGetLastError();
     const hipError_t e2 = hipStreamEndCapture(c->stream, &graph);
@@ -643,9 +647,54 @@ int record_frame_graph(mpm_ctx* c, int cur, bool rebuild, float frame_dt, const 
     return MPM_OK;
 }
 
-int graph_frame(mpm_ctx* c, float frame_dt, const std::vector<int>& ns) {
+// Substeps after which a particle moving at speed v could first leave its
+// free zone: it must move more than 3 cells, so with the gravity g not before
+// 3 dx = v t + g t^2 / 2; the smallest such t over the scenes, in each
+// scene's steps.
+double exit_horizon(const mpm_ctx* c, double v) {
+    double out = 1e30;
+    for (const SceneHost& s : c->sh) {
+        if (s.N == 0) continue;
+        const double dx = 1.0 / s.desc.n;
+        const double g = std::sqrt((double)s.desc.gravity[0] * s.desc.gravity[0] +
+                                   (double)s.desc.gravity[1] * s.desc.gravity[1] +
+                                   (double)s.desc.gravity[2] * s.desc.gravity[2]);
+        const double t = g > 0.0 ? (std::sqrt(v * v + 6.0 * g * dx) - v) / g : (v > 0.0 ? 3.0 * dx / v : 1e30);
+        out = std::min(out, t / (double)s.desc.dt);
+    }
+    return out;
+}
+
+// The mean particle speed now: from the last graph frame's end when that is
+// current (published to pinned memory inside the frame), else one reduction
+// read back.
+int current_mean_speed(mpm_ctx* c, double& v) {
+    float w[2] = {0.0f, 0.0f};
+    if (c->graph_speed) {
+        for (int k = 0; k < 2; ++k) {
+            const int bits = __atomic_load_n(c->ring + RING + 1 + k, __ATOMIC_ACQUIRE);
+            memcpy(&w[k], &bits, sizeof(float));
+        }
+    } else {
+        if (int r = bring_up_to_date(c)) return r;
+        HIP_OK(c, hipMemsetAsync(c->speed_dev, 0, 2 * sizeof(float), c->stream));
+        enqueue_speeds(c->stream, c->S[c->cur], c->cap, (int)c->N, c->speed_dev);
+        HIP_OK(c, hipMemcpyAsync(w, c->speed_dev, 2 * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+        HIP_OK(c, hipStreamSynchronize(c->stream));
+    }
+    v = c->N > 0 ? (double)w[1] / (double)c->N : 0.0;
+    return MPM_OK;
+}
+
+// A graph frame can rebuild only at its start, so a particle that leaves its
+// zone mid-frame keeps the global path until the next frame.  Besides the
+// request the previous frame left, the frame therefore also rebuilds when the
+// exit horizon (above) ends within it.
+int graph_frame(mpm_ctx* c, float frame_dt, const std::vector<int>& ns, double horizon) {
     if (int r = settle_graph_frame(c)) return r;
-    const bool rebuild = c->need_rebuild || (c->cfg.flags & MPM_FLAG_REBUILD_EVERY_STEP);
+    const int64_t since = c->step - c->last_rebuild;
+    const bool due = c->last_rebuild >= 0 && (double)(since + ns[0]) > horizon;
+    const bool rebuild = c->need_rebuild || due || (c->cfg.flags & MPM_FLAG_REBUILD_EVERY_STEP);
     const FrameGraph& g = c->graphs[c->cur][rebuild ? 1 : 0];
     if (!(g.exec && g.N == c->N && g.frame_dt == frame_dt && g.chunk == c->cfg.chunk)) {
         // all four at once, so that a run does not stop to record mid-way
@@ -656,6 +705,7 @@ int graph_frame(mpm_ctx* c, float frame_dt, const std::vector<int>& ns) {
     HIP_OK(c, hipGraphLaunch(g.exec, c->stream));
     HIP_OK(c, hipEventRecord(c->graph_done, c->stream));
     c->graph_inflight = true;
+    c->graph_speed = true;
     if (rebuild) note_rebuild(c);
     c->parity_ctr = 0;
     for (int k = 0; k < ns[0]; ++k) note_substep(c, active_ranks(ns, k));
@@ -670,8 +720,8 @@ int graph_frame(mpm_ctx* c, float frame_dt, const std::vector<int>& ns) {
 // back from the device (the frame starts from a synchronized stream).
 int update_auto_dt(mpm_ctx* c, float frame_dt) {
     if (int r = bring_up_to_date(c)) return r;
-    HIP_OK(c, hipMemsetAsync(c->speed_dev, 0, sizeof(float), c->stream));
-    enqueue_max_speed(c->stream, c->S[c->cur], c->cap, (int)c->N, c->speed_dev);
+    HIP_OK(c, hipMemsetAsync(c->speed_dev, 0, 2 * sizeof(float), c->stream));
+    enqueue_speeds(c->stream, c->S[c->cur], c->cap, (int)c->N, c->speed_dev);
     float vmax = 0.0f;
     HIP_OK(c, hipMemcpyAsync(&vmax, c->speed_dev, sizeof(float), hipMemcpyDeviceToHost, c->stream));
     HIP_OK(c, hipStreamSynchronize(c->stream));
@@ -701,10 +751,22 @@ int run_frame(mpm_ctx* c, float frame_dt) {
         if (int r = update_auto_dt(c, frame_dt)) return r;
     const std::vector<int> ns = frame_substeps(c, frame_dt);
     if ((c->cfg.flags & MPM_FLAG_FRAME_GRAPHS) && c->pending && !(c->cfg.flags & MPM_FLAG_REBUILD_EVERY_STEP)) {
-        int r = poll_flags(c, c->step);  // the ring is idle across a graph frame
+        int r = settle_graph_frame(c);
         if (r) return r;
-        if ((r = bring_up_to_date(c))) return r;
-        return graph_frame(c, frame_dt, ns);
+        // A graph frame rebuilds only at its start: while particles could leave their zones
+        // within a frame even right after a rebuild, frames run directly, rebuilding where
+        // needed, and return to graphs once the motion allows a whole frame.
+        // the horizon of the bulk (the mean speed): a few fast particles that leave their
+        // zones cost little on the global path and ask for the next frame's rebuild
+        double vmean;
+        if ((r = current_mean_speed(c, vmean))) return r;
+        const double horizon = exit_horizon(c, vmean);
+        c->graph_speed = false;
+        if (horizon >= (double)ns[0]) {
+            if ((r = poll_flags(c, c->step))) return r;  // the ring is idle across a graph frame
+            if ((r = bring_up_to_date(c))) return r;
+            return graph_frame(c, frame_dt, ns, horizon);
+        }
     }
     for (int k = 0; k < ns[0]; ++k) {
         int r = substep_one(c, active_ranks(ns, k));
@@ -832,7 +894,7 @@ int mpm_create(const mpm_config* cfg, mpm_ctx** out) {
               hipMalloc(&c->G.reg_n, sizeof(int) * nb) == hipSuccess &&
               hipMalloc(&c->G.reg, sizeof(int) * REG_MAX * nb) == hipSuccess &&
               hipMalloc(&c->ctl, sizeof(int) * CTL_ALLOC_WORDS) == hipSuccess &&
-              hipMalloc(&c->speed_dev, sizeof(float)) == hipSuccess &&
+              hipMalloc(&c->speed_dev, 4 * sizeof(float)) == hipSuccess &&
               hipMalloc(&c->scene_dev, sizeof(Scene) * S) == hipSuccess &&
               hipMalloc(&c->rank_scene_dev, sizeof(int) * S) == hipSuccess &&
               hipMalloc(&c->rank_brick_dev, sizeof(int) * (S + 1)) == hipSuccess &&
@@ -849,6 +911,7 @@ int mpm_create(const mpm_config* cfg, mpm_ctx** out) {
         hipMemsetAsync(c->B.brick_state, 0, sizeof(int) * nb, c->stream) != hipSuccess ||
         hipMemsetAsync(c->G.reg_n, 0, sizeof(int) * nb, c->stream) != hipSuccess ||
         hipMemsetAsync(c->ctl, 0, sizeof(int) * CTL_ALLOC_WORDS, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->speed_dev, 0, 4 * sizeof(float), c->stream) != hipSuccess ||
         hipMemsetAsync(c->rank_end_dev, 0, sizeof(int) * 4 * S, c->stream) != hipSuccess ||
         hipMemcpyAsync(c->scene_dev, c->table.data(), sizeof(Scene) * S, hipMemcpyHostToDevice, c->stream) !=
             hipSuccess ||
@@ -860,13 +923,13 @@ int mpm_create(const mpm_config* cfg, mpm_ctx** out) {
         c->err = "initialisation failed";
         return bail(MPM_EDEVICE);
     }
-    if (hipHostMalloc(&c->ring, sizeof(int) * (RING + 1), hipHostMallocDefault) != hipSuccess ||
+    if (hipHostMalloc(&c->ring, sizeof(int) * (RING + 3), hipHostMallocDefault) != hipSuccess ||
         hipHostGetDevicePointer(reinterpret_cast<void**>(&c->ring_dev), c->ring, 0) != hipSuccess) {
         (void)hipGetLastError();
         c->err = "pinned ring allocation failed";
         return bail(MPM_ENOMEM);
     }
-    memset(c->ring, 0, sizeof(int) * (RING + 1));
+    memset(c->ring, 0, sizeof(int) * (RING + 3));
     for (int i = 0; i < RING; ++i)
         if (hipEventCreateWithFlags(&c->ev[i], hipEventDisableTiming) != hipSuccess) {
             c->err = "event creation failed";
@@ -924,6 +987,7 @@ int mpm_add_particles(mpm_ctx* c, int32_t scene, const mpm_material* mat, int64_
     if (int r = scene_arg(c, scene)) return r;
     if (count < 0 || (count > 0 && !x)) return fail(c, MPM_EINVAL, "bad count or null positions");
     if (c->N + count > (int64_t)1 << 30) return fail(c, MPM_EINVAL, "too many particles");
+    c->graph_speed = false;  // new particles bring their own speeds
     SceneHost& sh = c->sh[scene];
     if (mat) {
         if (mat->kind < 0 || mat->kind > 3) return fail(c, MPM_EINVAL, "bad material kind");
@@ -1131,6 +1195,7 @@ int mpm_autotune(mpm_ctx* c, float frame_dt, int32_t frames, int32_t* chunk_out)
     if (!c) return MPM_EINVAL;
     if (!(frame_dt > 0.0f) || frames < 1) return fail(c, MPM_EINVAL, "frame_dt must be positive and frames >= 1");
     const int orig_chunk = c->cfg.chunk;
+    c->graph_speed = false;
     if (c->N == 0) {
         if (chunk_out) *chunk_out = orig_chunk;
         return MPM_OK;
@@ -1159,6 +1224,7 @@ int mpm_autotune(mpm_ctx* c, float frame_dt, int32_t frames, int32_t* chunk_out)
         dst->pending = s.pending;
         dst->g2p_due_act = 0;  // the snapshot holds the state brought up to date
         dst->sh = s.sh;
+        dst->graph_speed = false;
     };
     mpm_ctx saved;  // host counters only
     saved.step = c->step;

@@ -253,7 +253,11 @@ void enqueue_g2p(hipStream_t st, const Launch& L, const Scenes& T, float* S, int
                  int* ctl, const GridBuffers& G, int* host_flag, int lds_box, int parity, int fb_limit, int chunk,
                  int act, int report_zone);
 void enqueue_materialize(hipStream_t st, const Scenes& T, float* S, int64_t cap, int N);
-void enqueue_max_speed(hipStream_t st, const float* S, int64_t cap, int N, float* out);
+// Particle speeds of the whole state: out[0] the largest, out[1] the sum (out zeroed by the caller).
+void enqueue_speeds(hipStream_t st, const float* S, int64_t cap, int N, float* out);
+// ... reduced into word[0..1] (zero on entry), published to pinned host[0..1] as float bits, and
+// word cleared again (graph frames)
+void enqueue_speeds_to_host(hipStream_t st, const float* S, int64_t cap, int N, float* word, int* host);
 void enqueue_clear_overflow(hipStream_t st, int* ctl);
 // The same with each snow scene's own map (exact, closed form or network), over the chunk list of the
 // last rebuild; for contexts with T.sur_any != 0.

@@ -239,4 +239,10 @@ __device__ __forceinline__ float wave_maxf(float v) {
     return v;
 }
 
+__device__ __forceinline__ float wave_sumf(float v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
 }  // namespace mpm

@@ -549,21 +549,55 @@ void enqueue_g2p(hipStream_t st, const Launch& L, const Scenes& T, float* S, int
 // The largest particle speed |v| into *out (zeroed by the caller): a wave
 // maximum, then one atomic per wave on the float's bits (non-negative floats
 // order like their bit patterns).
-__global__ __launch_bounds__(WG) void k_max_speed(const float* __restrict__ S, int64_t cap, int N,
-                                                  float* __restrict__ out) {
-    float m = 0.0f;
+// Particle speeds: out[0] the largest (as ordered int bits), out[1] their sum.
+// One add of each per workgroup (same-address atomics run one at a time).
+__global__ __launch_bounds__(WG) void k_speeds(const float* __restrict__ S, int64_t cap, int N,
+                                               float* __restrict__ out) {
+    float m = 0.0f, sum = 0.0f;
     for (int p = blockIdx.x * WG + threadIdx.x; p < N; p += gridDim.x * WG) {
         const float a = S[sidx(FV, p, cap)], b = S[sidx(FV + 1, p, cap)], c = S[sidx(FV + 2, p, cap)];
-        m = fmaxf(m, sqrtf(a * a + b * b + c * c));
+        const float v = sqrtf(a * a + b * b + c * c);
+        m = fmaxf(m, v);
+        sum += v;
     }
     m = wave_maxf(m);
-    if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<int*>(out), __float_as_int(m));
+    sum = wave_sumf(sum);
+    __shared__ float wm[WG / 64], ws[WG / 64];
+    if ((threadIdx.x & 63) == 0) {
+        wm[threadIdx.x >> 6] = m;
+        ws[threadIdx.x >> 6] = sum;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < WG / 64; ++w) {
+            m = fmaxf(m, wm[w]);
+            sum += ws[w];
+        }
+        atomicMax(reinterpret_cast<int*>(out), __float_as_int(m));
+        atomicAdd(out + 1, sum);
+    }
 }
 
-void enqueue_max_speed(hipStream_t st, const float* S, int64_t cap, int N, float* out) {
+// The speeds reduced into word[0..1] (cleared first), published to pinned
+// host memory as float bits (host[0] largest, host[1] sum), word cleared again.
+__global__ void k_publish_speeds(float* __restrict__ word, int* __restrict__ host) {
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(host, __float_as_int(word[0]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(host + 1, __float_as_int(word[1]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        word[0] = 0.0f;
+        word[1] = 0.0f;
+    }
+}
+
+void enqueue_speeds(hipStream_t st, const float* S, int64_t cap, int N, float* out) {
     if (N <= 0) return;
-    const int grid = cdiv(N, WG) < 1024 ? cdiv(N, WG) : 1024;
-    hipLaunchKernelGGL(k_max_speed, dim3(grid), dim3(WG), 0, st, S, cap, N, out);
+    const int grid = cdiv(N, WG) < 256 ? cdiv(N, WG) : 256;
+    hipLaunchKernelGGL(k_speeds, dim3(grid), dim3(WG), 0, st, S, cap, N, out);
+}
+
+void enqueue_speeds_to_host(hipStream_t st, const float* S, int64_t cap, int N, float* word, int* host) {
+    enqueue_speeds(st, S, cap, N, word);
+    hipLaunchKernelGGL(k_publish_speeds, dim3(1), dim3(64), 0, st, word, host);
 }
 
 void enqueue_materialize(hipStream_t st, const Scenes& T, float* S, int64_t cap, int N) {

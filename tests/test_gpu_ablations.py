@@ -122,10 +122,12 @@ def test_library_builds_match_the_oracle(torch_cuda, library):
 def test_graph_frames_keep_the_free_zone_cadence(torch_cuda):
     """Sand Blocks (4 boxes of 12^3 cells) falling and landing over 12 frames
     of 36 substeps, replayed as graph frames: a frame starts with a rebuild
-    only when the previous one asked for it (about every other frame here,
-    not every frame), G2P runs inside P2G within the frame, and the frames
-    agree with the same frames run directly (1e-4 normwise: rebuilds at other
-    substeps change the order of the grid sums)."""
+    when the previous one asked for it or the exit horizon of the bulk ends
+    within it, so the rebuilds follow the free zone's cadence (within a few
+    of the direct frames' count, not one per substep), G2P runs inside P2G
+    within the frame, and the frames agree with the same frames run directly
+    (1e-4 normwise: rebuilds at other substeps change the order of the grid
+    sums)."""
     from paper_2111_00699_amd import mpm
 
     from .test_gpu_parity import normwise
@@ -146,7 +148,7 @@ def test_graph_frames_keep_the_free_zone_cadence(torch_cuda):
             assert sim.stats()["error"] == 0
             sim.close()
     print(f"[graphs] rebuilds graph={rebuilds[0]} direct={rebuilds[1]}", flush=True)
-    assert rebuilds[0] <= 8  # 12 frames, the first one eager (nothing pending yet)
+    assert abs(rebuilds[0] - rebuilds[1]) <= 4, rebuilds
     assert rebuilds[0] >= 2  # the boxes fall several cells, so rebuilds do happen
     for k in ("x", "v", "F", "s"):
         e = normwise(out[0][k], out[1][k])
