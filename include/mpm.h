@@ -37,6 +37,11 @@
  *     leaving the grid, capacity exceeded) set a sticky error word; the next
  *     mpm_read_* or mpm_get_stats call returns MPM_ESTATE, and the word stays
  *     set until mpm_clear_error().
+ *   - Statistics are read with mpm_get_stats (the counters a "stats" call
+ *     returns).  A trained network is loaded in two calls: mpm_surrogate_set
+ *     puts parameters and normalisation into a surrogate object, and
+ *     mpm_use_surrogate lets a scene take it, so one network can serve
+ *     several contexts.
  */
 #ifndef MPM_H
 #define MPM_H
