@@ -16,7 +16,7 @@ the K timed frames (inputs resident in HBM before timing starts).
 stream during the timed frames, against the HBM peak (`frac` from the
 algorithmic bytes, `traffic_frac` from the measured HBM bytes);
 `roofline_valu` puts them against the VALU issue rate (the kernel's counted
-instructions at full issue: the bound it actually meets), `roofline_lds`
+instructions at full issue: a floor under its time), `roofline_lds`
 against the LDS 64-bit atomic rate; `cpu_baseline` times the FP64 oracle on
 the host on a bounded sample.  The other workloads print their own line: the fountain (ms per
 frame against the growing particle count), 256 batched scenes, and the
@@ -933,7 +933,7 @@ def main():
                      "bytes_basis": "per particle-substep state traffic of P2G + G2P (snow: 212 B)",
                      "kernel_bytes_per_particle": kernel_bytes,
                      "kernel_bytes_frac": kernel_bytes * N / (p2g_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
-        # the VALU issue bound: the launch's counted wave instructions at full issue against the
+        # the VALU issue floor: the launch's counted wave instructions at full issue against the
         # live launch time (null once the sources differ from the counted ones)
         "roofline_valu": ({"kernel": "p2g_fused", "bound": "valu_issue",
                            "wave_instructions_per_launch": P2G_TRAFFIC["valu_wave_instructions"],
