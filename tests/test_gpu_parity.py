@@ -250,6 +250,40 @@ def test_single_substep_matches_oracle(torch_cuda, oracle, kind, mode):
     sim.close()
 
 
+def test_empty_context_then_particles(torch_cuda, oracle):
+    """A context that holds no particles: substeps and frames are no-ops,
+    reads return zero-length arrays and an all-zero grid, and no rebuild
+    runs; particles added afterwards take their first substep as in a fresh
+    context, within the single-substep bars."""
+    mat, bc = MATS["snow"]
+    sc = scenes.jelly_cube(0)
+    st = scenes.nontrivial_state(sc["x"], seed=9, kind="snow")
+    cfg = dict(n=64, dt=1e-4, bc=bc)
+    print_case("empty_context", N=0)
+    sim = make_sim(torch_cuda, cfg)
+    sim.substep(3)
+    sim.frame(1.0 / 60.0)
+    empty = gpu_state(sim)
+    assert all(a.shape[-1] == 0 for a in empty.values())
+    gm, gv = (t.cpu().numpy() for t in sim.read_grid())
+    assert not gm.any() and not gv.any()
+    stats = sim.stats()
+    assert stats["error"] == 0 and stats["rebuilds"] == 0
+    print_case("empty_context_then_particles", N=st["x"].shape[1])
+    sim.add_particles(mat, st["x"], v=st["v"], C=st["C"], F=st["F"], s=st["s"])
+    sim.substep(1)
+    gs = gpu_state(sim)
+    gm, gv = (t.cpu().numpy() for t in sim.read_grid())
+    stats = sim.stats()
+    sim.close()
+    os_, om, ov, bad = oracle.substep(cfg, mat, st)
+    assert bad == 0
+    compare_state(gs, os_, "snow")
+    assert normwise(gm, om) <= TOL
+    assert normwise(gv, ov) <= TOL
+    assert stats["error"] == 0 and stats["rebuilds"] == 1
+
+
 def test_ragged_multi_block_substep(torch_cuda, oracle):
     """30001 particles over many blocks at n=128, small chunks: many partial
     chunks and tiles, snow with the return map active."""
