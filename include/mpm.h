@@ -102,6 +102,9 @@ typedef enum { MPM_BC_STICKY = 0, MPM_BC_SLIP = 1, MPM_BC_SEPARATE = 2 } mpm_bc;
 #define MPM_FLAG_SEPARATE_CLEAR 0x200u  /* clearing the global accumulators as a launch of its own         */
 #define MPM_FLAG_ALLOC_EXACT 0x400u     /* mpm_add_particles grows the particle buffers to exactly what is
                                            needed instead of 4x when half full (every emission reallocates) */
+#define MPM_FLAG_CHUNK_PER_BLOCK 0x800u /* each work chunk holds the particles of one block only, instead of
+                                           consecutive blocks packed up to the chunk size (the paper's
+                                           "virtual blocks" of Gao et al.: more, emptier workgroups) */
 
 #define MPM_MAX_SCENES 256
 
@@ -260,8 +263,9 @@ int mpm_read_grid(mpm_ctx* ctx, int32_t scene, float* m_dev, float* v_dev);
  * rebuild).  Storage layout after a rebuild: scenes in order of increasing dt
  * (ties by scene index), inside a scene geometric blocks in code order;
  * chunks of at most config.chunk particles: consecutive blocks of one
- * 2x2x1 slab of blocks (equal block code >> 2) share a chunk while they fit,
- * a larger block is cut into runs of config.chunk; inside a chunk of
+ * 2x2x1 slab of blocks (equal block code >> 2) share a chunk while they fit
+ * (each block a chunk of its own with MPM_FLAG_CHUNK_PER_BLOCK), a larger
+ * block is cut into runs of config.chunk; inside a chunk of
  * `count` particles the particles are ranked by the bank pair
  * (x + 12 y + 8 z) mod 16 of their cell (x, y, z), then by block and cell
  * code, ties in sorted order, and rank r is stored at slot 16 p + q of the

@@ -457,8 +457,9 @@ int fb_limit(const mpm_ctx* c) { return (int)(c->N >> 8); }
 // Rebuild from particle buffer `cur` into the other one.
 void enqueue_rebuild_into_alt(mpm_ctx* c, int cur) {
     enqueue_rebuild(c->stream, tables(c), c->S[cur], c->S[cur ^ 1], c->ids[cur], c->ids[cur ^ 1], c->cap,
-                    (int)c->N, c->cfg.chunk, (c->cfg.flags & MPM_FLAG_P2G_SORTED_LANES) ? 0 : 1, c->B, c->ctl,
-                    c->nbricks, c->key_bits, c->G.reg_n, c->G.reg);
+                    (int)c->N, c->cfg.chunk, (c->cfg.flags & MPM_FLAG_P2G_SORTED_LANES) ? 0 : 1,
+                    (c->cfg.flags & MPM_FLAG_CHUNK_PER_BLOCK) ? 0 : 1, c->B, c->ctl, c->nbricks, c->key_bits,
+                    c->G.reg_n, c->G.reg);
 }
 void enqueue_rebuild_into_alt(mpm_ctx* c) { enqueue_rebuild_into_alt(c, c->cur); }
 

@@ -238,9 +238,10 @@ struct OpGroups {
     const uint32_t* gcode;
     int* group_start;
     const int* ctl;
+    int pack;  // 0: every block is a group of its own (one block per chunk)
     __device__ int count(int g) const {
         if (g >= ctl[CTL_NGB]) return 0;
-        return (g == 0 || (gcode[g] >> 2) != (gcode[g - 1] >> 2)) ? 1 : 0;
+        return (g == 0 || !pack || (gcode[g] >> 2) != (gcode[g - 1] >> 2)) ? 1 : 0;
     }
     __device__ void emit(int g, int off, int) const { group_start[off] = g; }
 };
@@ -569,7 +570,8 @@ void enqueue_copy_codes(hipStream_t st, uint32_t* dst, const uint32_t* src, int 
 }
 
 void enqueue_rebuild(hipStream_t st, const Scenes& T, float* S_cur, float* S_alt, int* id_cur, int* id_alt,
-                     int64_t cap, int N, int chunk, int spread, BinBuffers& B, int* ctl, int nbricks, int key_bits,
+                     int64_t cap, int N, int chunk, int spread, int pack, BinBuffers& B, int* ctl, int nbricks,
+                     int key_bits,
                      int* reg_n, int* reg) {
     const int nb = cdiv(N > 0 ? N : 1, WG);
     // 1. particle codes
@@ -588,7 +590,7 @@ void enqueue_rebuild(hipStream_t st, const Scenes& T, float* S_cur, float* S_alt
     B.sorted = cur;  // slot holding the sorted codes and their source positions
     // 3. geometric blocks and work chunks
     device_scan(st, OpGBlocks{B.keys[cur], N, B.gstart, B.gcode}, N, B.scan_tiles, ctl + CTL_NGB);
-    device_scan(st, OpGroups{B.gcode, B.group_start, ctl}, N, B.scan_tiles, ctl + CTL_NGROUP);
+    device_scan(st, OpGroups{B.gcode, B.group_start, ctl, pack}, N, B.scan_tiles, ctl + CTL_NGROUP);
     device_scan(st, OpChunks{B.gstart, B.gcode, B.group_start, ctl, N, chunk, B.chunks, T}, N, B.scan_tiles,
                 ctl + CTL_NCHUNK);
     // 4. gather the whole particle state into (chunk-spread) sorted order

@@ -200,7 +200,8 @@ struct BinBuffers {
 // Codes, stable radix sort, blocks, chunks and the gather into sorted order
 // for all scenes at once; `key_bits` is the width of the particle codes.
 void enqueue_rebuild(hipStream_t st, const Scenes& T, float* S_cur, float* S_alt, int* id_cur, int* id_alt,
-                     int64_t cap, int N, int chunk, int spread, BinBuffers& B, int* ctl, int nbricks, int key_bits,
+                     int64_t cap, int N, int chunk, int spread, int pack, BinBuffers& B, int* ctl, int nbricks,
+                     int key_bits,
                      int* reg_n, int* reg);
 // dst[i] = src[i] & mask (particle codes without the rank bits).
 void enqueue_copy_codes(hipStream_t st, uint32_t* dst, const uint32_t* src, int count, uint32_t mask);

@@ -27,7 +27,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -1, -2, -3, -4
 ERR_NONFINITE, ERR_DOMAIN, ERR_CAPACITY = 0x1, 0x2, 0x4
 FLAG_REBUILD_EVERY_STEP, FLAG_P2G_GLOBAL_ATOMICS, FLAG_MANUAL_REBUILD, FLAG_P2G_SORTED_LANES = 0x1, 0x2, 0x4, 0x8
 FLAG_G2P_GLOBAL_GATHER, FLAG_FRAME_GRAPHS, FLAG_FUSED_G2P, FLAG_SEPARATE_G2P = 0x10, 0x20, 0x40, 0x80
-FLAG_SEPARATE_WALLS, FLAG_SEPARATE_CLEAR, FLAG_ALLOC_EXACT = 0x100, 0x200, 0x400
+FLAG_SEPARATE_WALLS, FLAG_SEPARATE_CLEAR, FLAG_ALLOC_EXACT, FLAG_CHUNK_PER_BLOCK = 0x100, 0x200, 0x400, 0x800
 MAX_SCENES = 256
 PHASE_REBUILD, PHASE_P2G, PHASE_GRID, PHASE_G2P = 0x1, 0x2, 0x4, 0x8
 

@@ -226,13 +226,14 @@ MATS = {"jelly": (scenes.JELLY, "sticky"), "snow": (scenes.SNOW, "separate"), "w
 
 
 @pytest.mark.parametrize("kind", ["jelly", "snow", "water", "sand"])
-@pytest.mark.parametrize("mode", ["tile", "global", "every_step", "sorted_lanes", "g2p_global", "chunk128", "chunk512"])
+@pytest.mark.parametrize("mode", ["tile", "global", "every_step", "sorted_lanes", "g2p_global", "chunk128", "chunk512",
+                                  "per_block"])
 def test_single_substep_matches_oracle(torch_cuda, oracle, kind, mode):
     mat, bc = MATS[kind]
     sc = scenes.jelly_cube(0)
     st = scenes.nontrivial_state(sc["x"], seed=5, kind=kind)
     cfg = dict(n=64, dt=1e-4, bc=bc)
-    flags = {"global": 0x2, "every_step": 0x1, "sorted_lanes": 0x8, "g2p_global": 0x10}.get(mode, 0)
+    flags = {"global": 0x2, "every_step": 0x1, "sorted_lanes": 0x8, "g2p_global": 0x10, "per_block": 0x800}.get(mode, 0)
     chunk = {"chunk128": 128, "chunk512": 512}.get(mode, 0)
     print_case("substep1", kind=kind, mode=mode, N=st["x"].shape[1])
     sim = make_sim(torch_cuda, cfg, flags=flags, chunk=chunk)
