@@ -285,7 +285,7 @@ int grow(mpm_ctx* c, int64_t newcap) {
     ok = ok && hipMalloc(&chunks, sizeof(Chunk) * (newcap + 1)) == hipSuccess;
     ok = ok && hipMalloc(&group_start, sizeof(int) * (newcap + 2)) == hipSuccess;
     ok = ok && hipMalloc(&sorted_ids, sizeof(int) * newcap) == hipSuccess;
-    ok = ok && hipMalloc(&stage, sizeof(float4) * stage_nodes) == hipSuccess;
+    ok = ok && hipMalloc(&stage, sizeof(float4) * (stage_nodes + 1)) == hipSuccess;
     ok = ok && hipMalloc(&box, sizeof(int4) * (newcap + 1)) == hipSuccess;
     if (!ok) {
         for (int i = 0; i < 2; ++i) {
@@ -317,6 +317,7 @@ int grow(mpm_ctx* c, int64_t newcap) {
         HIP_OK(c, hipMemcpyAsync(ids[0], c->ids[c->cur], sizeof(int) * c->N, hipMemcpyDeviceToDevice, c->stream));
     }
     HIP_OK(c, hipMemsetAsync(box, 0, sizeof(int4) * (newcap + 1), c->stream));
+    HIP_OK(c, hipMemsetAsync(stage + stage_nodes, 0, sizeof(float4), c->stream));  // the zero node
     HIP_OK(c, hipStreamSynchronize(c->stream));
     free_particle_buffers(c);
     for (int i = 0; i < 2; ++i) {

@@ -216,8 +216,9 @@ struct GridBuffers {
                     // scenes (allocated when a scene first takes ASFLIP; NULL before)
     int* stamp;     // [NB^3] substep index of the last update of each block
     int* ovf[2];    // overflow block lists, by substep parity
-    float4* stage;  // [stage_nodes] P2G tiles, (m, px, py, pz) per node; each P2G workgroup owns an
-                    // equal slice and packs the tiles of its chunks there
+    float4* stage;  // [stage_nodes + 1] P2G tiles, (m, px, py, pz) per node; each P2G workgroup owns an
+                    // equal slice of the first stage_nodes and packs the tiles of its chunks there; node
+                    // stage_nodes stays zero (the grid update's loads outside a tile read it)
     int4* box;      // [cap] per chunk: x = tile origin packed 10 bits/axis, y = extent packed 8 bits/axis
                     // (0 = no tile), z = offset of the tile in `stage` (nodes)
     int stage_nodes;

@@ -128,8 +128,8 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, int* __res
                                              const int* __restrict__ ovf, int* __restrict__ brick_state,
                                              int* __restrict__ stamp, const int* __restrict__ reg_n,
                                              const int* __restrict__ reg, const float4* __restrict__ stage,
-                                             const int4* __restrict__ box, int parity, int nbricks, Scenes T,
-                                             int act) {
+                                             int zero_node, const int4* __restrict__ box, int parity, int nbricks,
+                                             Scenes T, int act) {
     const int nact = rank_limit(T, ctl, act, RE_ACTIVE, CTL_NACTIVE);
     const int total = nact + min(ctl[CTL_OVF + parity], nbricks - ctl[CTL_NACTIVE]);
     const int step = ctl[CTL_STEP];
@@ -152,14 +152,31 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, int* __res
         if (it < nact) {  // a physical block: gather the tiles registered with it (at most REG_MAX)
             const int m = min(__builtin_amdgcn_readfirstlane(reg_n[it]), REG_MAX);
             for (int rb = 0; rb < m; rb += 64) {  // 64 registrations a round, one per lane
-                int4 bb = make_int4(0, 0, 0, 0);
+                // Each lane prepares its registration's tile for the whole wave: the lanes of
+                // this block whose node lies in the tile's box (a 64-bit mask, lane = x + 4 y +
+                // 16 z) and the staged index of the block's first node, so that node (x, y, z)
+                // of the block sits at base + x + e0 y + e0 e1 z of the tight box layout.
                 bool ov = false;  // does tile `lane` still exist and reach into this block?
+                uint64_t lm = 0;
+                int base = 0, s1 = 0, s2 = 0;
                 if (rb + lane < m) {
-                    bb = box[reg[(int64_t)it * REG_MAX + rb + lane]];
+                    const int4 bb = box[reg[(int64_t)it * REG_MAX + rb + lane]];
                     const int e0 = bb.y & 255, e1 = (bb.y >> 8) & 255, e2 = bb.y >> 16;
                     const int l0 = bb.x & 1023, l1 = (bb.x >> 10) & 1023, l2 = bb.x >> 20;
-                    ov = e0 > 0 && l0 <= n0 + 3 && l0 + e0 > n0 && l1 <= n1 + 3 && l1 + e1 > n1 &&
-                         l2 <= n2 + 3 && l2 + e2 > n2;
+                    // block-local node range [x0, x1) x [y0, y1) x [z0, z1) inside the box
+                    const int x0 = max(l0 - n0, 0), x1 = min(l0 + e0 - n0, 4);
+                    const int y0 = max(l1 - n1, 0), y1 = min(l1 + e1 - n1, 4);
+                    const int z0 = max(l2 - n2, 0), z1 = min(l2 + e2 - n2, 4);
+                    ov = e0 > 0 && x0 < x1 && y0 < y1 && z0 < z1;
+                    if (ov) {
+                        const unsigned xm = ((1u << x1) - 1u) & ~((1u << x0) - 1u);
+                        const unsigned ry = (0x1111u >> (4 * (4 - (y1 - y0)))) << (4 * y0);
+                        const uint64_t rz = (0x0001000100010001ull >> (16 * (4 - (z1 - z0)))) << (16 * z0);
+                        lm = (uint64_t)(xm * ry) * rz;  // the factors' set bits never overlap: no carries
+                        base = bb.z + (n0 - l0) + e0 * ((n1 - l1) + e1 * (n2 - l2));
+                        s1 = e0;
+                        s2 = e0 * e1;
+                    }
                 }
                 // the overlapping tiles in registration order, eight loads in flight at a time
                 // (summed in the same order as one at a time)
@@ -167,17 +184,20 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, int* __res
                     float4 sv[8];
 #pragma unroll
                     for (int u = 0; u < 8; ++u) {
-                        sv[u] = make_float4(0.f, 0.f, 0.f, 0.f);
                         if (mask) {  // wave-uniform
                             const int i = __builtin_ctzll(mask);
                             mask &= mask - 1;
-                            const int bx_ = __builtin_amdgcn_readlane(bb.x, i), by_ = __builtin_amdgcn_readlane(bb.y, i),
-                                      s_ = __builtin_amdgcn_readlane(bb.z, i);
-                            const int e0 = by_ & 255, e1 = (by_ >> 8) & 255, e2 = by_ >> 16;
-                            const int r0 = g[0] - (bx_ & 1023), r1 = g[1] - ((bx_ >> 10) & 1023),
-                                      r2 = g[2] - (bx_ >> 20);
-                            if (r0 >= 0 && r0 < e0 && r1 >= 0 && r1 < e1 && r2 >= 0 && r2 < e2)
-                                sv[u] = stage[s_ + r0 + e0 * (r1 + e1 * r2)];
+                            const uint64_t lmi =
+                                ((uint64_t)(unsigned)__builtin_amdgcn_readlane((int)(lm >> 32), i) << 32) |
+                                (unsigned)__builtin_amdgcn_readlane((int)(unsigned)lm, i);
+                            const int bi = __builtin_amdgcn_readlane(base, i), s1i = __builtin_amdgcn_readlane(s1, i),
+                                      s2i = __builtin_amdgcn_readlane(s2, i);
+                            // every lane loads: those outside the tile's box read the zero node
+                            const int ri = bi + lx + (int)__umul24(s1i, ly) + (int)__umul24(s2i, lz);
+                            const int idx = ((lmi >> lane) & 1ull) ? ri : zero_node;
+                            sv[u] = stage[idx];
+                        } else {
+                            sv[u] = make_float4(0.f, 0.f, 0.f, 0.f);
                         }
                     }
 #pragma unroll
@@ -516,8 +536,8 @@ void enqueue_grid(hipStream_t st, const Launch& L, const Scenes& T, const BinBuf
     const bool bc = !(separate & 1), clear = !(separate & 2);
 #define MPM_LAUNCH_GRID(BCV, CLV)                                                                                  \
     hipLaunchKernelGGL((k_grid<BCV, CLV>), dim3(L.grid_grid), dim3(WG), 0, st, G.acc, G.acc_dirty, G.vel, G.dvel, \
-                       B.active, ctl, G.ovf[parity], B.brick_state, G.stamp, G.reg_n, G.reg, G.stage, G.box, parity,  \
-                       nbricks, T, act)
+                       B.active, ctl, G.ovf[parity], B.brick_state, G.stamp, G.reg_n, G.reg, G.stage,                 \
+                       G.stage_nodes, G.box, parity, nbricks, T, act)
     if (bc && clear) MPM_LAUNCH_GRID(true, true);
     else if (bc) MPM_LAUNCH_GRID(true, false);
     else if (clear) MPM_LAUNCH_GRID(false, true);
