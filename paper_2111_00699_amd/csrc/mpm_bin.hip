@@ -354,13 +354,18 @@ __global__ __launch_bounds__(WG) void k_permute_chunks(const float* __restrict__
                                                        const uint32_t* __restrict__ keys,
                                                        const Chunk* __restrict__ chunks, const int* __restrict__ ctl,
                                                        int64_t cap, int spread, int shift) {
+    constexpr int NRK = 4096;  // ranking keys: 4-bit bank pair, 8-bit segment and cell
     __shared__ int rk[PERMUTE_MAX];
+    __shared__ int below[NRK];  // per ranking key: how many of the chunk's particles rank lower
     const int nch = ctl[CTL_NCHUNK];
     const uint32_t mmask = (1u << shift) - 1u;
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
         const Chunk ch = chunks[c];
-        const bool deal = spread && ch.count <= PERMUTE_MAX;
+        const bool deal = spread && ch.count <= PERMUTE_MAX;  // workgroup-uniform
         if (deal) {
+            // a counting sort of the ranking keys: histogram, then its exclusive prefix sums
+            for (int t = threadIdx.x; t < NRK; t += WG) below[t] = 0;
+            __syncthreads();
             for (int t = threadIdx.x; t < ch.count; t += WG) {
                 const uint32_t key = keys[ch.start + t] & mmask;
                 const uint32_t bcode = key >> 6, cell = key & 63u;
@@ -368,6 +373,22 @@ __global__ __launch_bounds__(WG) void k_permute_chunks(const float* __restrict__
                 const int y = 4 * (int)compact3(bcode >> 1) + (int)compact3(cell >> 1);
                 const int z = 4 * (int)compact3(bcode >> 2) + (int)compact3(cell >> 2);
                 rk[t] = (((x + 12 * y + 8 * z) & 15) << 8) | (int)(key & 255u);  // bank, segment, cell
+                atomicAdd(&below[rk[t]], 1);
+            }
+            __syncthreads();
+            constexpr int PER = NRK / WG;
+            int h[PER], sum = 0;
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                h[k] = below[threadIdx.x * PER + k];
+                sum += h[k];
+            }
+            int total;
+            int run = block_excl_scan(sum, &total);
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                below[threadIdx.x * PER + k] = run;
+                run += h[k];
             }
             __syncthreads();
         }
@@ -376,13 +397,14 @@ __global__ __launch_bounds__(WG) void k_permute_chunks(const float* __restrict__
             const uint32_t key = keys[j];
             int slot = t;
             if (deal) {
+                // rank = the particles with a lower ranking key + those before it with the same one.
+                // Within a chunk (blocks of one 2x2x1 slab) the segment and cell bits identify the
+                // particle code, so equal ranking keys are a run of equal codes, consecutive in
+                // sorted order.
                 const int mine = rk[t];
-                int r = 0;
-                for (int u = 0; u < ch.count; ++u) {
-                    const int o = rk[u];
-                    r += (o < mine || (o == mine && u < t)) ? 1 : 0;
-                }
-                slot = dealt_slot(ch.count, r);
+                int first = t;
+                while (first > 0 && rk[first - 1] == mine) --first;
+                slot = dealt_slot(ch.count, below[mine] + (t - first));
             }
             const int k = (int)src[j];  // its position before the sort
             const int dst = ch.start + slot;
