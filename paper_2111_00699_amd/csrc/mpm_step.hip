@@ -137,9 +137,36 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, int* __res
     const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
     const int nwaves = gridDim.x * (WG / 64);
     float4* acc4 = reinterpret_cast<float4*>(acc);
-    for (int it = blockIdx.x * (WG / 64) + (threadIdx.x >> 6); it < total; it += nwaves) {
-        const int b = __builtin_amdgcn_readfirstlane(it < nact ? active[it] : ovf[it - nact]);
-        const Scene& sc = T.scene[T.rank_scene[rank_of_brick(T, b)]];
+    // The blocks of a wave are a software pipeline: the block index, the registration count
+    // and this lane's first registration of the next block are loaded as the current block
+    // starts, and that registration's tile box and the block's global-path flag once the
+    // current block's tiles are in, so the chain block -> registrations -> boxes -> staged
+    // tiles is not paid in full per block.  (Every read is in bounds: reg holds REG_MAX
+    // entries per block index, and box is read only for a registration that exists.)
+    const bool one = T.S == 1;
+    int it = blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+    int b_nx = 0, m_nx = 0, r_nx = 0, dirty_nx = 0;
+    int4 bb_nx = make_int4(0, 0, 0, 0);
+    if (it < total) {
+        b_nx = it < nact ? active[it] : ovf[it - nact];
+        m_nx = it < nact ? reg_n[it] : 0;
+        r_nx = reg[(int64_t)it * REG_MAX + lane];
+        if (lane < m_nx) bb_nx = box[r_nx];
+        dirty_nx = acc_dirty[__builtin_amdgcn_readfirstlane(b_nx)];
+    }
+    for (; it < total; it += nwaves) {
+        const int b = __builtin_amdgcn_readfirstlane(b_nx);
+        const int m = min(__builtin_amdgcn_readfirstlane(m_nx), REG_MAX);
+        const int nx = it + nwaves;
+        if (nx < total) {
+            b_nx = nx < nact ? active[nx] : ovf[nx - nact];
+            m_nx = nx < nact ? reg_n[nx] : 0;
+            r_nx = reg[(int64_t)nx * REG_MAX + lane];
+        } else {
+            m_nx = 0;
+        }
+        // one scene: no lookup (the record's address does not depend on the block)
+        const Scene& sc = T.scene[one ? 0 : T.rank_scene[rank_of_brick(T, b)]];
         const Step P = sc.P;
         const int NB = P.NB, base = sc.brick_base;
         const int lb = b - base;
@@ -147,10 +174,10 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, int* __res
         const int n0 = 4 * (bx - 1), n1 = 4 * (by - 1), n2 = 4 * (bz - 1);  // first node of the block
         const int g[3] = {n0 + lx, n1 + ly, n2 + lz};
         // the block's global-atomic sums, if P2G sent any here this substep
-        const bool dirty = __builtin_amdgcn_readfirstlane(acc_dirty[b]) != 0;
+        const bool dirty = __builtin_amdgcn_readfirstlane(dirty_nx) != 0;
         float4 a = dirty ? acc4[(int64_t)b * 64 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
         if (it < nact) {  // a physical block: gather the tiles registered with it (at most REG_MAX)
-            const int m = min(__builtin_amdgcn_readfirstlane(reg_n[it]), REG_MAX);
+            int4 bb = bb_nx;  // this lane's registration of the round (the first round's was prefetched)
             for (int rb = 0; rb < m; rb += 64) {  // 64 registrations a round, one per lane
                 // Each lane prepares its registration's tile for the whole wave: the lanes of
                 // this block whose node lies in the tile's box (a 64-bit mask, lane = x + 4 y +
@@ -159,8 +186,8 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, int* __res
                 bool ov = false;  // does tile `lane` still exist and reach into this block?
                 uint64_t lm = 0;
                 int base = 0, s1 = 0, s2 = 0;
+                if (rb > 0 && rb + lane < m) bb = box[reg[(int64_t)it * REG_MAX + rb + lane]];
                 if (rb + lane < m) {
-                    const int4 bb = box[reg[(int64_t)it * REG_MAX + rb + lane]];
                     const int e0 = bb.y & 255, e1 = (bb.y >> 8) & 255, e2 = bb.y >> 16;
                     const int l0 = bb.x & 1023, l1 = (bb.x >> 10) & 1023, l2 = bb.x >> 20;
                     // block-local node range [x0, x1) x [y0, y1) x [z0, z1) inside the box
@@ -210,6 +237,10 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, int* __res
                 }
             }
         }
+        // the next block's first-round tile boxes and global-path flag (its index and
+        // registrations have arrived by now)
+        if (lane < m_nx) bb_nx = box[r_nx];
+        if (nx < total) dirty_nx = acc_dirty[__builtin_amdgcn_readfirstlane(b_nx)];
         float v[3] = {0.0f, 0.0f, 0.0f};
         if (a.x > 0.0f) {
             const float inv = __frcp_rn(a.x);
