@@ -128,7 +128,9 @@ typedef struct {
     uint64_t stream;    /* hipStream_t as an integer (e.g. torch.cuda.Stream.cuda_stream); 0 = null stream */
     uint32_t flags;     /* MPM_FLAG_* */
     int32_t lag;        /* substeps the host may run ahead of the device before it must read the
-                           rebuild flag (1..64; 0 selects the default 3) */
+                           rebuild flag (1..64; 0 selects the default 5).  Substeps are marked
+                           in groups (every 4th substep with lag >= 5, every 2nd with lag >= 3),
+                           so a flag is read once its group has ended */
     int32_t chunk;      /* particles per P2G/G2P work chunk: 64..512, multiple of 64 (0 = 256) */
     int32_t reserved;
     const mpm_scene* scenes; /* num_scenes descriptors (copied), or NULL: every scene takes n, bc,

@@ -8,12 +8,15 @@
 //
 // Rebuild scheduling without draining the stream: G2P sets a device flag when
 // a particle leaves its free zone and, the first time, writes it to a pinned
-// host ring slot of that substep; an event marks the substep's end.  Before
-// enqueueing substep k the host reads the slots of substeps that have
-// finished, waiting only for substep k - lag, so the device keeps `lag`
-// substeps queued.  A particle that leaves its free zone before the rebuild
-// lands is still transferred exactly (through global atomics), so the lag
-// costs speed, never correctness.
+// host ring slot of that substep; an event marks the end of every group of
+// substeps (four with the default lag: an event on the stream delays the next
+// kernel by about 6 us, which per substep cost 3% of the snow frame).  Before
+// enqueueing substep k the host reads the slots of the groups that have
+// finished, waiting only for the group of substep k - lag (its last substep is
+// at most k - lag + 3), so the device keeps at least lag - 4 substeps queued
+// (one with the default lag of 5).  A particle that leaves its free zone
+// before the rebuild lands is still transferred exactly (through global
+// atomics), so the lag costs speed, never correctness.
 //
 // Batched scenes: every scene is a rank in one particle-code order, so each
 // phase of a substep is one launch over all scenes; a frame gives scene s
@@ -384,11 +387,33 @@ int prof_end(mpm_ctx* c, int slot) {
     return MPM_OK;
 }
 
-// Read the rebuild flags of finished substeps, waiting for those at or
-// before `must_upto`.
+// Substeps close their group of ev_every(c) with an event (a marker costs the
+// stream a few microseconds between kernels, so not every substep records one).
+int ev_every(const mpm_ctx* c) { return c->cfg.lag >= 5 ? 4 : c->cfg.lag >= 3 ? 2 : 1; }
+bool closes_group(const mpm_ctx* c, int64_t t) { return ((t + 1) % ev_every(c)) == 0; }
+
+// Read the rebuild flag of substep t (finished).
+void read_flag(mpm_ctx* c, int64_t t) {
+    if (__atomic_load_n(&c->ring[(int)(t % RING)], __ATOMIC_ACQUIRE) && t >= c->last_rebuild &&
+        !(c->cfg.flags & MPM_FLAG_MANUAL_REBUILD))
+        c->need_rebuild = true;
+}
+
+// Read the rebuild flags of finished substeps, waiting for the group that
+// holds substep `must_upto` (the group's closing event is never more than
+// ev_every - 1 substeps later; `must_upto` >= the last substep drains the
+// stream instead).
 int poll_flags(mpm_ctx* c, int64_t must_upto) {
+    if (c->checked < c->step && must_upto >= c->step - 1) {
+        HIP_OK(c, hipStreamSynchronize(c->stream));
+        for (; c->checked < c->step; ++c->checked) read_flag(c, c->checked);
+        return MPM_OK;
+    }
+    const int64_t k = ev_every(c);
     while (c->checked < c->step) {
-        const int slot = (int)(c->checked % RING);
+        const int64_t t = (c->checked / k) * k + k - 1;  // the substep closing checked's group
+        if (t >= c->step) break;                            // not enqueued yet
+        const int slot = (int)(t % RING);
         if (c->checked <= must_upto) {
             hipError_t e;
             while ((e = hipEventQuery(c->ev[slot])) == hipErrorNotReady) {
@@ -399,10 +424,7 @@ int poll_flags(mpm_ctx* c, int64_t must_upto) {
             if (e == hipErrorNotReady) break;
             if (e != hipSuccess) return fail(c, MPM_EDEVICE, std::string("hipEventQuery: ") + hipGetErrorString(e));
         }
-        if (__atomic_load_n(&c->ring[slot], __ATOMIC_ACQUIRE) && c->checked >= c->last_rebuild &&
-            !(c->cfg.flags & MPM_FLAG_MANUAL_REBUILD))
-            c->need_rebuild = true;
-        ++c->checked;
+        for (; c->checked <= t; ++c->checked) read_flag(c, c->checked);
     }
     return MPM_OK;
 }
@@ -586,7 +608,7 @@ int substep_one(mpm_ctx* c, int act) {
         if ((r = prof_end(c, slot))) return r;
     }
     HIP_OK(c, hipGetLastError());
-    HIP_OK(c, hipEventRecord(c->ev[rs], c->stream));
+    if (closes_group(c, c->step)) HIP_OK(c, hipEventRecord(c->ev[rs], c->stream));
     note_substep(c, act);
     return MPM_OK;
 }
@@ -851,7 +873,7 @@ int mpm_create(const mpm_config* cfg, mpm_ctx** out) {
     mpm_ctx* c = new mpm_ctx();
     c->cfg = *cfg;
     c->cfg.scenes = nullptr;  // copied below
-    if (c->cfg.lag == 0) c->cfg.lag = 3;
+    if (c->cfg.lag == 0) c->cfg.lag = 5;
     if (c->cfg.chunk == 0) c->cfg.chunk = 256;
     c->stream = reinterpret_cast<hipStream_t>(cfg->stream);
     (void)hipGetDevice(&c->device);
