@@ -35,9 +35,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # P2G launches are timed with HIP events on a sample: every PROFILE_EVERY-th
-# launch of the timed frames (bracketing all of them would cost the frame
-# time about 4%).
-PROFILE_EVERY = 16
+# launch of the timed frames, about 310 of the 20,040 (each event pair holds
+# the stream back a few microseconds; bracketing all launches would cost the
+# frame time about 4%).
+PROFILE_EVERY = 64
 # LDS 64-bit integer atomic throughput of gfx950, measured with a probe of
 # ds_add_u64 on distinct addresses: 9.1 lane-operations per clock per compute
 # unit, i.e. 9.1 x 256 CUs x 2.4 GHz.  P2G's fixed-point scatter issues 27
@@ -870,7 +871,7 @@ def main():
         log(f"[bench] warmup frame {f + 1}/{args.warmup} enqueued")
     sim.synchronize()
     st0 = sim.stats()
-    # every 16th launch: the events cost a few microseconds of stream time each
+    # every 64th launch: the events cost a few microseconds of stream time each
     sim.profile(mpm.PHASE_P2G | mpm.PHASE_G2P | mpm.PROFILE_EVERY(PROFILE_EVERY))
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
