@@ -6,10 +6,13 @@
 //
 // MI355X design:
 //  * The grid update is one wave64 per 4^3 block of the physical (and
-//    overflow) block lists.  It gathers each node from the FP64 tiles that
-//    P2G staged for the chunks of the 27 particle blocks around it (no
-//    global atomics on the tiled path), adds the global-path accumulator,
-//    then applies gravity and the wall condition and clears the accumulator.
+//    overflow) block lists.  It gathers each node from the tiles (exact
+//    fixed-point sums, stored as FP32) that P2G staged for the chunks of the
+//    27 particle blocks around it (no global atomics on the tiled path), adds
+//    the global-path accumulator, then applies gravity and the wall
+//    condition and clears the accumulator.  A wave's blocks are pipelined:
+//    the next block's registrations and tile boxes load while the current
+//    block gathers.
 //  * G2P takes one chunk per workgroup and loads the chunk's node box (the
 //    box its P2G tile used) into LDS, so the 27-node gathers read LDS.
 //  * Work lists are dealt to the eight XCDs in contiguous ranges of the
