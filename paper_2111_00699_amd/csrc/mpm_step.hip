@@ -260,18 +260,25 @@ __global__ __launch_bounds__(WG) void k_grid(float* __restrict__ acc, int* __res
             any = any || lowside[k] || highside[k];
         }
         if (BC && any) wall_condition(P, lowside, highside, v);
-        vel[(int64_t)b * 64 + lane] = make_float4(v[0], v[1], v[2], a.x);
-        if (P.flip > 0.0f) {  // ASFLIP: the change from the transferred velocity p/m
-            float4 d = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (a.x > 0.0f) {
-                const float inv = __frcp_rn(a.x);
-                d = make_float4(v[0] - a.y * inv, v[1] - a.z * inv, v[2] - a.w * inv, 0.0f);
+        // A block that took no mass this substep keeps its old contents and stamp: no
+        // particle's stencil reaches it (every node of a stencil takes mass from its own
+        // particle, or a weight of exactly zero, which multiplies the old finite value),
+        // and reads of the grid show a block with an old stamp as empty.
+        const bool took_mass = __ballot(a.x > 0.0f) != 0ull;
+        if (took_mass) {
+            vel[(int64_t)b * 64 + lane] = make_float4(v[0], v[1], v[2], a.x);
+            if (P.flip > 0.0f) {  // ASFLIP: the change from the transferred velocity p/m
+                float4 d = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (a.x > 0.0f) {
+                    const float inv = __frcp_rn(a.x);
+                    d = make_float4(v[0] - a.y * inv, v[1] - a.z * inv, v[2] - a.w * inv, 0.0f);
+                }
+                dvel[(int64_t)b * 64 + lane] = d;
             }
-            dvel[(int64_t)b * 64 + lane] = d;
         }
         if (CLEAR && dirty) acc4[(int64_t)b * 64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (lane == 0) {
-            stamp[b] = step;
+            if (took_mass) stamp[b] = step;
             if (CLEAR && dirty) acc_dirty[b] = 0;
             if (CLEAR && it >= nact) brick_state[b] = 0;
         }
